@@ -1,0 +1,343 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each check fixes part of the method by mathematics rather than by re-typing the
+oracle: exact-rational runs of the same method (pivot sequence, tableau),
+brute-force enumeration of bases (optimum), closed forms, the algebraic
+identity T = B^-1 [A | I | b], strong duality, and hand-worked fixtures.
+"""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from exact_ref import brute_force_optimum, exact_simplex
+from goldens import read_fixture
+from paper_2211_10979_amd import lpgen
+
+
+def rand_lp(seed, m, n, lo=1, hi=1000, signed=False):
+    rng = np.random.default_rng(seed)
+    A = rng.integers(lo, hi + 1, size=(m, n)).astype(np.float64)
+    if signed:
+        A *= rng.choice([-1.0, 1.0], size=(m, n), p=[0.3, 0.7])
+    b = rng.integers(lo, hi + 1, size=m).astype(np.float64)
+    c = rng.integers(lo, hi + 1, size=n).astype(np.float64)
+    return A, b, c
+
+
+def rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+# ---------------------------------------------------------------- fixtures
+
+
+def test_table1_initial_tableau():
+    """Initialization Step builds Table I (z column dropped: it stays e_0)."""
+    fx = read_fixture("table1_layout.txt")
+    m, n = fx["m"], fx["n"]
+    full = fx["T"]
+    zcol = n + m
+    assert np.array_equal(full[:, zcol], np.eye(m + 1)[:, 0])
+    expect = np.delete(full, zcol, axis=1)
+    o = oracle.OracleLP(fx["A"], fx["b"], fx["c"])
+    assert np.array_equal(o.tableau(), expect)
+    assert o.basis().tolist() == [n + i for i in range(m)]
+
+
+def test_hand_example():
+    fx = read_fixture("hand_example.txt")
+    r = oracle.solve(fx["A"], fx["b"], fx["c"])
+    assert r["status"] == oracle.OPTIMAL
+    assert list(zip(r["rows"].tolist(), r["cols"].tolist())) == fx["pivot"]
+    assert r["objective"] == pytest.approx(fx["objective"], rel=1e-14)
+    assert np.allclose(r["x"], fx["x"], rtol=1e-14, atol=1e-14)
+    assert np.allclose(r["y"], fx["y"], rtol=1e-14, atol=1e-14)
+    o = oracle.OracleLP(fx["A"], fx["b"], fx["c"])
+    o.step(-1)
+    assert np.allclose(o.tableau(), fx["T"], rtol=1e-14, atol=1e-14)
+
+
+# ---------------------------------------------------------------- brute force
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_optimum_matches_vertex_enumeration(seed):
+    rng = np.random.default_rng(1000 + seed)
+    m, n = int(rng.integers(1, 6)), int(rng.integers(1, 6))
+    hi = [5, 20, 1000][seed % 3]
+    A, b, c = rand_lp(seed, m, n, 1, hi)
+    best, _ = brute_force_optimum(A, b, c)
+    r = oracle.solve(A, b, c)
+    assert r["status"] == oracle.OPTIMAL
+    assert rel(r["objective"], float(best)) <= 1e-12
+    # the oracle's own x is feasible and attains the optimum
+    assert np.all(r["x"] >= 0)
+    assert np.all(A @ r["x"] <= b + 1e-9 * np.maximum(1, np.abs(b)))
+    assert rel(float(c @ r["x"]), float(best)) <= 1e-12
+
+
+# ---------------------------------------------------------------- exact simplex
+
+
+def _compare_with_exact(A, b, c):
+    """Walks the exact method along the oracle's pivots.
+
+    Every decision must equal the exact one, except where the exact values of
+    the oracle's choice and the exact choice are within 1e-9 (relative) of
+    each other: there rounding may legitimately decide, and the case is
+    reported as skipped.
+    """
+    from exact_ref import ExactTableau
+
+    r = oracle.solve(A, b, c)
+    log = list(zip(r["rows"].tolist(), r["cols"].tolist()))
+    et = ExactTableau(A, b, c, 1e-9, 1e-9)
+    W = et.W
+    for k, (ro, qo) in enumerate(log):
+        qe = et.entering()
+        assert qe is not None, f"pivot {k}: exact method is already optimal"
+        if qe != qo:
+            a, bb = et.T[0][qe], et.T[0][qo]
+            gap = abs(a - bb) / max(abs(a), Fraction(1))
+            assert gap < Fraction(1, 10**9), f"pivot {k}: entering {qo} vs exact {qe}"
+            pytest.skip(f"pricing near-tie at pivot {k} (relative gap {float(gap):.1e})")
+        re_ = et.leaving(qe)
+        assert re_ is not None
+        if re_ != ro:
+            assert et.T[ro][qe] > et.eps_p, f"pivot {k}: row {ro} not eligible"
+            a = et.T[re_][W - 1] / et.T[re_][qe]
+            bb = et.T[ro][W - 1] / et.T[ro][qe]
+            gap = abs(a - bb) / max(abs(a), Fraction(1))
+            assert gap < Fraction(1, 10**9), f"pivot {k}: leaving {ro} vs exact {re_}"
+            pytest.skip(f"ratio near-tie at pivot {k} (relative gap {float(gap):.1e})")
+        et.pivot(re_, qe)
+    et.solve()
+    assert len(et.log) == len(log), "exact method continues after the oracle stopped"
+    assert oracle.STATUS_NAMES[r["status"]] == et.status
+    if et.status == "OPTIMAL":
+        assert rel(r["objective"], float(et.objective())) <= 1e-12
+    return r, et
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_pivot_sequence_matches_exact_simplex(seed):
+    rng = np.random.default_rng(2000 + seed)
+    m, n = int(rng.integers(2, 25)), int(rng.integers(2, 25))
+    kind = seed % 3
+    if kind == 0:
+        A, b, c = rand_lp(seed, m, n, 1, 1000)
+    elif kind == 1:  # small integers: many exact ties and degenerate pivots
+        A, b, c = rand_lp(seed, m, n, 1, 4)
+    else:  # mixed signs: more pivots, may be unbounded
+        A, b, c = rand_lp(seed, m, n, 1, 9, signed=True)
+    _compare_with_exact(A, b, c)
+
+
+def test_pivot_sequence_generator_workload_small():
+    lp = lpgen.dense_lp(11, 30, 30)
+    r, ex = _compare_with_exact(lp.A, lp.b, lp.c)
+    assert r["pivots"] >= 1
+
+
+def test_tableau_matches_exact_after_every_pivot():
+    A, b, c = rand_lp(7, 12, 15, 1, 9, signed=True)
+    ex = exact_simplex(A, b, c, eps_d=1e-9, eps_p=1e-9)
+    o = oracle.OracleLP(A, b, c)
+    from exact_ref import ExactTableau
+
+    et = ExactTableau(A, b, c, 1e-9, 1e-9)
+    for k, (r, q) in enumerate(ex.log):
+        o.step(1)
+        et.pivot(r, q)
+        T = o.tableau()
+        E = np.array([[float(v) for v in row] for row in et.T])
+        assert np.allclose(T, E, rtol=1e-9, atol=1e-9), f"pivot {k}"
+
+
+# ---------------------------------------------------------------- closed forms
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_diagonal_closed_form(seed):
+    rng = np.random.default_rng(seed)
+    n = 12
+    d = rng.integers(1, 50, size=n).astype(np.float64)
+    A = np.diag(d)
+    b = rng.integers(1, 100, size=n).astype(np.float64)
+    c = rng.integers(1, 6, size=n).astype(np.float64)  # repeated values: ties
+    r = oracle.solve(A, b, c)
+    order = sorted(range(n), key=lambda j: (-c[j], j))
+    assert r["cols"].tolist() == order
+    assert r["rows"].tolist() == [j + 1 for j in order]
+    assert r["pivots"] == n
+    assert r["objective"] == pytest.approx(float(np.sum(c * b / d)), rel=1e-13)
+    assert np.allclose(r["y"], c / d, rtol=1e-14)
+    assert np.allclose(r["x"], b / d, rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_single_variable(seed):
+    rng = np.random.default_rng(seed)
+    m = 9
+    a = rng.integers(1, 6, size=m).astype(np.float64)
+    b = rng.integers(1, 20, size=m).astype(np.float64)
+    c = np.array([3.0])
+    r = oracle.solve(a.reshape(m, 1), b, c)
+    ratios = [Fraction(int(b[i]), int(a[i])) for i in range(m)]
+    best = min(ratios)
+    r_expect = ratios.index(best) + 1  # lowest row among equal ratios
+    assert r["pivots"] == 1
+    assert r["rows"].tolist() == [r_expect] and r["cols"].tolist() == [0]
+    assert r["objective"] == pytest.approx(3.0 * float(best), rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_single_row(seed):
+    rng = np.random.default_rng(seed)
+    n = 10
+    a = rng.integers(1, 30, size=n).astype(np.float64)
+    c = rng.integers(1, 30, size=n).astype(np.float64)
+    b = np.array([17.0])
+    r = oracle.solve(a.reshape(1, n), b, c)
+    assert r["status"] == oracle.OPTIMAL
+    assert r["objective"] == pytest.approx(17.0 * float(np.max(c / a)), rel=1e-13)
+
+
+def test_nonpositive_costs_need_no_pivot():
+    A, b, _ = rand_lp(3, 6, 7)
+    c = -np.arange(7, dtype=np.float64)
+    r = oracle.solve(A, b, c)
+    assert r["status"] == oracle.OPTIMAL and r["pivots"] == 0 and r["objective"] == 0.0
+
+
+def test_unbounded_column():
+    A, b, c = rand_lp(4, 5, 4, 1, 9)
+    A[:, 2] = -np.abs(A[:, 2])
+    A[1, 2] = 0.0
+    c[:] = 1.0
+    c[2] = 50.0
+    r = oracle.solve(A, b, c)
+    assert r["status"] == oracle.UNBOUNDED and r["pivots"] == 0
+
+
+def test_iteration_cap():
+    lp = lpgen.dense_lp(1, 40, 40)
+    full = oracle.solve(lp.A, lp.b, lp.c)
+    assert full["pivots"] >= 2
+    r = oracle.solve(lp.A, lp.b, lp.c, max_pivots=1)
+    assert r["status"] == oracle.ITER_LIMIT and r["pivots"] == 1
+    assert (r["rows"][0], r["cols"][0]) == (full["rows"][0], full["cols"][0])
+
+
+def test_rejects_bad_input():
+    A, b, c = rand_lp(5, 3, 3)
+    with pytest.raises(ValueError):
+        oracle.OracleLP(A, -b, c)
+    A2 = A.copy()
+    A2[0, 0] = np.nan
+    with pytest.raises(ValueError):
+        oracle.OracleLP(A2, b, c)
+
+
+def test_step_budget_resumes_identically():
+    lp = lpgen.dense_lp(9, 60, 50)
+    full = oracle.solve(lp.A, lp.b, lp.c)
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    while o.step(1) == oracle.RUNNING:
+        pass
+    rows, cols = o.log()
+    assert rows.tolist() == full["rows"].tolist() and cols.tolist() == full["cols"].tolist()
+
+
+# ---------------------------------------------------------------- algebraic identity and invariants
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tableau_equals_basis_inverse_identity(seed):
+    A, b, c = rand_lp(seed, 40, 55, 1, 9, signed=True)
+    m, n = A.shape
+    W = n + m + 1
+    full = np.hstack([A, np.eye(m), b[:, None]])
+    cext = np.concatenate([c, np.zeros(m)])
+    o = oracle.OracleLP(A, b, c)
+    k = 0
+    while o.step(1) == oracle.RUNNING and k < 200:
+        k += 1
+        basis = o.basis()
+        B = full[:, basis]
+        body = np.linalg.solve(B, full)
+        row0 = cext[basis] @ body - np.concatenate([cext, [0.0]])
+        expect = np.vstack([row0, body])
+        T = o.tableau()
+        scale = max(1.0, float(np.max(np.abs(expect))))
+        assert np.max(np.abs(T - expect)) <= 1e-8 * scale, f"pivot {k}"
+    assert W == T.shape[1]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_invariants_every_pivot(seed):
+    lp = lpgen.dense_lp(100 + seed, 50, 70)
+    A, b, c = lp.A, lp.b, lp.c
+    o = oracle.OracleLP(A, b, c)
+    prev_obj = 0.0
+    while o.step(1) == oracle.RUNNING:
+        T = o.tableau()
+        basis = o.basis()
+        m = A.shape[0]
+        for i, j in enumerate(basis):
+            col = T[:, j]
+            assert col[i + 1] == 1.0 and np.count_nonzero(col) == 1  # exact unit vector, row 0 exactly 0
+        assert np.all(T[1:, -1] >= -1e-9 * max(1.0, float(np.max(np.abs(T[1:, -1])))))
+        assert T[0, -1] >= prev_obj - 1e-12 * max(1.0, abs(prev_obj))
+        prev_obj = T[0, -1]
+        assert len(set(basis.tolist())) == m
+
+
+# ---------------------------------------------------------------- duality and an independent solver
+
+
+@pytest.mark.parametrize("name", ["dense_200x200", "dense_2000x2000"])
+def test_workload_certificates(name):
+    lp = lpgen.workload(name)
+    r = oracle.solve(lp.A, lp.b, lp.c)
+    assert r["status"] == oracle.OPTIMAL
+    cert = oracle.certificates(lp.A, lp.b, lp.c, r["x"], r["y"], r["objective"])
+    assert cert["ok"], cert
+
+
+@pytest.mark.parametrize("m,n,seed", [(30, 40, 1), (200, 200, 1), (300, 150, 2), (1000, 1000, 3)])
+def test_objective_matches_highs(m, n, seed):
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    lp = lpgen.dense_lp(seed, m, n)
+    r = oracle.solve(lp.A, lp.b, lp.c)
+    res = scipy_opt.linprog(-lp.c, A_ub=lp.A, b_ub=lp.b, bounds=(0, None), method="highs")
+    assert res.status == 0
+    assert rel(r["objective"], -res.fun) <= 1e-9
+
+
+def test_certificates_detect_bad_points():
+    A = np.array([[1.0, 1.0], [1.0, 3.0]])
+    b = np.array([4.0, 6.0])
+    c = np.array([2.0, 3.0])
+    good = oracle.certificates(A, b, c, np.array([3.0, 1.0]), np.array([1.5, 0.5]), 9.0)
+    assert good["ok"]
+    assert not oracle.certificates(A, b, c, np.array([3.0, 1.1]), np.array([1.5, 0.5]), 9.3)["ok"]  # infeasible
+    assert not oracle.certificates(A, b, c, np.array([2.0, 1.0]), np.array([1.5, 0.5]), 7.0)["ok"]  # gap
+    assert not oracle.certificates(A, b, c, np.array([3.0, 1.0]), np.array([1.0, 0.5]), 9.0)["ok"]  # dual infeasible
+    assert not oracle.certificates(A, b, c, np.array([3.0, 1.0]), np.array([1.5, 0.5]), 9.5)["ok"]  # objective
+
+
+def test_thread_count_does_not_change_result():
+    lp = lpgen.dense_lp(21, 300, 250)
+    r1 = oracle.solve(lp.A, lp.b, lp.c, threads=1)
+    o1 = oracle.OracleLP(lp.A, lp.b, lp.c, threads=1)
+    o4 = oracle.OracleLP(lp.A, lp.b, lp.c, threads=4)
+    o1.step(-1)
+    o4.step(-1)
+    assert np.array_equal(o1.tableau(), o4.tableau())
+    assert r1["pivots"] == o4.pivots
+    assert math.isfinite(r1["objective"])
