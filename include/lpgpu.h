@@ -1,0 +1,280 @@
+/*
+ * lpgpu: dense full-tableau primal simplex on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Mamalis & Perlitis, Section III):
+ *     maximise c^T x  subject to  A x <= b,  x >= 0,  with b >= 0,
+ * solved by the standard full-tableau method: the tableau of Table I with the
+ * slack basis (Initialization Step); Step 1 picks the entering column with the
+ * most negative objective-row entry; Step 2 the leaving row by the minimum
+ * ratio test; Step 3 pivots the whole tableau; the loop stops at optimality or
+ * unboundedness (Iterate/Finalization Step).
+ *
+ * Arithmetic contract (binary64 throughout, identical in every mode):
+ *   - tableau T has m+1 rows and W = n+m+1 columns; the z column of Table I
+ *     is left out (it stays the unit vector e_0); column W-1 is the RHS;
+ *   - Step 1: q = lowest j in [0, n+m) with the smallest T[0][j]; optimal when
+ *     T[0][q] >= -eps_dual;
+ *   - Step 2: over rows i in [1, m] with T[i][q] > eps_pivot, the smallest
+ *     T[i][W-1] / T[i][q] (IEEE division), lowest i on ties; none: unbounded;
+ *   - iteration cap: checked after Step 2; max_pivots pivots done and another
+ *     one needed gives LP_ITER_LIMIT;
+ *   - Step 3: p = T[r][q]; F = column q before the update; R_j = T[r][j] / p;
+ *     T[i][j] = fma(-F_i, R_j, T[i][j]) for i != r; T[r][j] = R_j;
+ *   - a NaN met by Step 1 or Step 2 gives LP_NUMERICAL.
+ * Results: x_j is the RHS of the row where j is basic (0 when nonbasic),
+ * y_i = T[0][n+i-1] (the duals), objective = T[0][W-1]. The same LP gives the
+ * same pivot sequence alone, in a batch and in the server.
+ *
+ * Conventions: every function returns an int32 code (LP_OK = 0, negative =
+ * error) unless stated. Host arrays are caller-owned and only read during the
+ * call (inputs are copied). Pivot logs hold the tableau row r in [1, m] and
+ * the column q in [0, n+m). Contexts are not thread-safe; distinct contexts
+ * may be used from distinct threads. The server is thread-safe.
+ */
+#ifndef LPGPU_H
+#define LPGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Outcome of a solve (lp_result.status). */
+enum {
+    LP_OPTIMAL = 0,    /* Step 1 found no entering column */
+    LP_UNBOUNDED = 1,  /* Step 2 found no eligible row */
+    LP_ITER_LIMIT = 2, /* max_pivots pivots done, another one needed */
+    LP_NUMERICAL = 3,  /* a NaN reached Step 1 or Step 2 */
+    LP_RUNNING = 4     /* not finished (lp_step budget ran out, or not solved yet) */
+};
+
+/* Return codes. */
+enum {
+    LP_OK = 0,
+    LP_E_INVAL = -1,   /* NULL pointer, m or n < 1, non-finite input, bad option */
+    LP_E_NEG_RHS = -2, /* some b_i < 0: the slack basis is infeasible (no Phase I) */
+    LP_E_NOMEM = -3,   /* device or host allocation failed */
+    LP_E_DEVICE = -4,  /* a HIP call failed; lp_last_error() has the text */
+    LP_E_STATE = -5,   /* call out of order (e.g. solution before solve) */
+    LP_E_PENDING = -6, /* server result not ready yet */
+    LP_E_BUDGET = -7   /* LP larger than the server's memory budget */
+};
+
+typedef struct lp_ctx lp_ctx;
+typedef struct lp_batch lp_batch;
+typedef struct lp_server lp_server;
+
+typedef struct {
+    double eps_dual;        /* enter only if T[0][j] < -eps_dual             (default 1e-9) */
+    double eps_pivot;       /* row eligible only if T[i][q] > eps_pivot       (default 1e-9) */
+    int64_t max_pivots;     /* <= 0 selects 50*(m+n)                          (default 0) */
+    int32_t record_pivots;  /* 1 = keep the (r, q) log                       (default 1) */
+    int32_t device;         /* HIP device ordinal                             (default 0) */
+    void *stream;           /* hipStream_t to run on; NULL = library-owned    (default NULL) */
+    void *device_buffer;    /* optional caller-owned device memory for the tableau, at least
+                               lp_tableau_bytes(m, n) bytes and 256-byte aligned; it must
+                               outlive the context                            (default NULL) */
+    size_t device_buffer_bytes;
+    int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto */
+    int32_t cols_per_block; /* update kernel: tableau columns per workgroup; 0 = auto */
+    int32_t use_graph;      /* 1 = replay a captured hipGraph, 0 = plain launches (default 1) */
+    int32_t reserved;
+} lp_options;
+
+typedef struct {
+    int32_t status;   /* LP_OPTIMAL .. LP_RUNNING */
+    int32_t reserved;
+    int64_t pivots;   /* pivots performed */
+    double objective; /* T[0][W-1] */
+    double solve_ms;  /* device time of the last lp_solve / lp_step call */
+} lp_result;
+
+typedef struct {
+    int32_t m, n;
+    int64_t width;          /* W = n+m+1 */
+    int64_t ld;             /* column stride of the column-major device tableau, in doubles */
+    size_t tableau_bytes;   /* ld * W * 8 */
+    const double *tableau;  /* device pointer: T[i][j] at tableau[j*ld + i] */
+} lp_info;
+
+/* Library version string. Never fails. */
+const char *lp_version(void);
+
+/* Text for a return code or status; never NULL. */
+const char *lp_error_string(int code);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *lp_last_error(void);
+
+/* Fills *o with the defaults listed above. LP_E_INVAL if o is NULL. */
+int lp_options_default(lp_options *o);
+
+/* Device bytes of the tableau for an m x n LP (0 if m or n < 1). */
+size_t lp_tableau_bytes(int32_t m, int32_t n);
+
+/*
+ * Creates a context and builds the tableau of Table I with the slack basis
+ * (Initialization Step) on the device.
+ *   A: host, row-major m x n; b: host, m; c: host, n. Copied during the call.
+ *   opt: NULL for defaults.
+ * Errors: LP_E_INVAL (NULL, m or n < 1, non-finite value, bad option),
+ * LP_E_NEG_RHS (b_i < 0), LP_E_NOMEM, LP_E_DEVICE. On error *out is NULL.
+ */
+int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+              const lp_options *opt);
+
+/*
+ * As lp_create, with A (row-major m x n), b and c already in device memory
+ * on opt->device. They are read by kernels on the context stream and may be
+ * freed once lp_create returns. Values are not validated on the host:
+ * negative or non-finite inputs give undefined pivots (finite, b >= 0 is the
+ * caller's promise).
+ */
+int lp_create_device(lp_ctx **out, int32_t m, int32_t n, const double *dA, const double *db, const double *dc,
+                     const lp_options *opt);
+
+/*
+ * Rebuilds the tableau of an existing context from device-resident A, b, c of
+ * the same m and n (the Initialization Step again), resetting the pivot count
+ * and log. Asynchronous on the context stream.
+ */
+int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double *dc);
+
+/*
+ * Runs Steps 1-3 until the LP is optimal, unbounded, hits max_pivots or meets
+ * a NaN. Blocks until done. LP_OK means it ran; the outcome is in
+ * lp_get_solution's status.
+ */
+int lp_solve(lp_ctx *h);
+
+/*
+ * Runs at most `pivots` further pivots (the outcome may stay LP_RUNNING), and
+ * blocks until done. lp_solve continues from here.
+ */
+int lp_step(lp_ctx *h, int64_t pivots);
+
+/*
+ * Copies the result. x: n doubles or NULL; y: m duals or NULL. Valid after
+ * lp_solve / lp_step (LP_E_STATE before).
+ */
+int lp_get_solution(const lp_ctx *h, lp_result *res, double *x, double *y);
+
+/*
+ * Copies up to cap logged pivots (rows r in [1, m], cols q in [0, n+m)) and
+ * stores the number of pivots performed in *count (which may exceed cap, or
+ * the log if record_pivots was 0).
+ */
+int lp_get_pivots(const lp_ctx *h, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
+
+/*
+ * Copies the tableau to host memory, column by column: out[j*(m+1) + i] =
+ * T[i][j] for j in [0, W), i in [0, m]. out holds (m+1)*W doubles.
+ */
+int lp_get_tableau(const lp_ctx *h, double *out);
+
+/* Copies the basis: basis[i-1] is the variable basic in tableau row i. */
+int lp_get_basis(const lp_ctx *h, int32_t *basis);
+
+/* Sizes and the device tableau pointer. */
+int lp_get_info(const lp_ctx *h, lp_info *info);
+
+/* Frees the context and its device memory (not a caller's device_buffer). NULL-safe. */
+void lp_destroy(lp_ctx *h);
+
+/*
+ * Diagnostic: the device's binary64 division and fused multiply-add, the two
+ * roundings of Steps 2 and 3, applied element-wise on `device`:
+ *   quot[k] = a[k] / b[k],   fmav[k] = fma(a[k], b[k], c[k]),   k < count.
+ * All five arrays are host arrays of `count` doubles (quot/fmav written).
+ * Lets a caller check that the device rounds as IEEE 754 prescribes (round
+ * to nearest even, one rounding per operation, subnormals kept).
+ */
+int lp_diag_arith(int32_t device, int64_t count, const double *a, const double *b, const double *c, double *quot,
+                  double *fmav);
+
+/* ------------------------------------------------------------------ batched
+ * Many independent LPs advanced together by one persistent kernel, captured
+ * in a hipGraph: every running LP performs Steps 1-3 once per step. Each LP
+ * follows exactly the pivot sequence lp_solve gives it.
+ */
+
+/*
+ * A, b, c: host arrays of `count` pointers to row-major m[k] x n[k], m[k] and
+ * n[k] doubles. Copied during the call. Same errors as lp_create; the first
+ * failing LP's code is returned.
+ */
+int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32_t *n, const double *const *A,
+                    const double *const *b, const double *const *c, const lp_options *opt);
+
+/* Solves every LP of the batch; blocks until all have stopped. */
+int lp_batch_solve(lp_batch *bt);
+
+/* Result of LP k (0-based); x: n[k] or NULL, y: m[k] or NULL. */
+int lp_batch_get_solution(const lp_batch *bt, int32_t k, lp_result *res, double *x, double *y);
+
+/* Pivot log of LP k, as lp_get_pivots. */
+int lp_batch_get_pivots(const lp_batch *bt, int32_t k, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
+
+/* Device time of the last lp_batch_solve in milliseconds (negative if none). */
+double lp_batch_solve_ms(const lp_batch *bt);
+
+void lp_batch_destroy(lp_batch *bt);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop that keeps each admitted LP's tableau resident in device
+ * memory. Requests are admitted in arrival order while the resident bytes fit
+ * the budget and a slot is free; admitted LPs advance together through the
+ * batched kernel (continuous batching); finished LPs are harvested and their
+ * memory reused.
+ */
+
+typedef struct {
+    int64_t submitted;
+    int64_t completed;
+    int64_t rejected;
+    int64_t resident_now;      /* LPs resident on the device */
+    size_t bytes_in_use;       /* device bytes of resident tableaux */
+    size_t peak_bytes;         /* highest bytes_in_use seen */
+    int64_t ticks;             /* scheduler iterations that launched work */
+    double p50_ms, p99_ms;     /* latency, submit to completion, over completed requests */
+    double mean_ms;
+} lp_server_stats;
+
+/*
+ * hbm_budget_bytes: ceiling on resident tableau bytes; max_slots: most LPs
+ * resident at once (<= 0: 4096). Starts the scheduler thread.
+ */
+int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots, const lp_options *opt);
+
+/*
+ * Queues one LP (inputs copied; thread-safe). *ticket identifies it.
+ * LP_E_BUDGET if its tableau alone exceeds the budget.
+ */
+int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+                     uint64_t *ticket);
+
+/*
+ * LP_OK and the result once the request finished (x: n, y: m, either may be
+ * NULL); LP_E_PENDING before; LP_E_INVAL for an unknown or already-collected
+ * ticket. A collected result is released.
+ */
+int lp_server_poll(lp_server *s, uint64_t ticket, lp_result *res, double *x, double *y);
+
+/* As lp_server_poll, but blocks until the request finished. */
+int lp_server_wait(lp_server *s, uint64_t ticket, lp_result *res, double *x, double *y);
+
+/* Pivot log of a finished, not yet collected request. */
+int lp_server_get_pivots(lp_server *s, uint64_t ticket, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
+
+int lp_server_get_stats(lp_server *s, lp_server_stats *st);
+
+/* Drains every queued request, then stops the scheduler and frees everything. NULL-safe. */
+void lp_server_destroy(lp_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPGPU_H */

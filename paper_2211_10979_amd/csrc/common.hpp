@@ -1,0 +1,91 @@
+// Internal definitions shared by the lpgpu kernels and host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "lpgpu.h"
+
+namespace lpgpu {
+
+// Rows of the column-major tableau are padded to a multiple of 16 doubles so
+// that every column starts on a 128-byte line.
+constexpr int kRowAlign = 16;
+
+inline int64_t padded_ld(int32_t m) { return ((int64_t)m + 1 + kRowAlign - 1) / kRowAlign * kRowAlign; }
+
+// Per-LP solver state, resident in device memory. The kernels read and write
+// it; the host only reads it back between graph replays.
+struct DevState {
+    int32_t status;      // LP_RUNNING until Step 1 or 2 ends the solve
+    int32_t go;          // 1: the update kernel applies pivot (r, q, p) now
+    int32_t r, q;        // pivot row in [1, m], pivot column in [0, n+m)
+    double p;            // T[r][q]
+    int64_t pivots;      // pivots decided (and applied once the update ran)
+    int64_t stop_at;     // pause (status stays RUNNING) when pivots reaches this
+    int64_t max_pivots;  // iteration cap
+    int64_t log_cap;     // entries in the pivot log
+    double eps_d, eps_p;
+    int32_t fresh;       // 1: no pricing partials yet, scan row 0 instead
+    int32_t nparts;      // number of pricing partials written by the update kernel
+};
+
+// (value, index) pair of the two-stage argmin.
+struct ArgMin {
+    double v;
+    int32_t i;
+};
+
+// Lexicographic order: smaller value first, then the lower index. A NaN wins
+// over every number so that it reaches the final stage, which reports it.
+__device__ __forceinline__ bool lex_less(double av, int32_t ai, double bv, int32_t bi) {
+    const bool an = av != av, bn = bv != bv;
+    if (an || bn) return an && (!bn || ai < bi);
+    return av < bv || (av == bv && ai < bi);
+}
+
+// An empty slot: +inf with the largest index loses to every real candidate.
+constexpr int32_t kNoIndex = 0x7fffffff;
+
+__device__ __forceinline__ void wave_argmin(double &v, int32_t &i) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int32_t oi = __shfl_xor(i, off, 64);
+        if (lex_less(ov, oi, v, i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
+
+// Block-wide lexicographic argmin; every thread gets the result. `sv`/`si`
+// are LDS scratch of at least blockDim.x / 64 entries.
+__device__ __forceinline__ void block_argmin(double &v, int32_t &i, double *sv, int32_t *si) {
+    wave_argmin(v, i);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        sv[wave] = v;
+        si[wave] = i;
+    }
+    __syncthreads();
+    v = lane < nw ? sv[lane] : __builtin_inf();
+    i = lane < nw ? si[lane] : kNoIndex;
+    wave_argmin(v, i);
+}
+
+// Thread-local last error text and a setter returning the code.
+int set_error(int code, const std::string &msg);
+
+#define LP_HIP_CHECK(expr)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::lpgpu::set_error(LP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace lpgpu

@@ -1,0 +1,52 @@
+// Element-wise device division and fma, for checking the device's rounding.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+
+using namespace lpgpu;
+
+namespace {
+
+__global__ void k_diag_arith(int64_t count, const double *__restrict__ a, const double *__restrict__ b,
+                             const double *__restrict__ c, double *__restrict__ quot, double *__restrict__ fmav) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    quot[k] = a[k] / b[k];
+    fmav[k] = fma(a[k], b[k], c[k]);
+}
+
+}  // namespace
+
+extern "C" int lp_diag_arith(int32_t device, int64_t count, const double *a, const double *b, const double *c,
+                             double *quot, double *fmav) {
+    if (count < 0 || (count > 0 && (!a || !b || !c || !quot || !fmav))) return set_error(LP_E_INVAL, "bad argument");
+    if (count == 0) return LP_OK;
+    int prev = 0;
+    LP_HIP_CHECK(hipGetDevice(&prev));
+    LP_HIP_CHECK(hipSetDevice(device));
+    double *d = nullptr;
+    const size_t bytes = (size_t)count * sizeof(double);
+    hipError_t e = hipMalloc((void **)&d, 5 * bytes);
+    if (e != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return set_error(LP_E_NOMEM, "hipMalloc failed");
+    }
+    int rc = LP_OK;
+    if (hipMemcpy(d, a, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d + count, b, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d + 2 * count, c, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        rc = set_error(LP_E_DEVICE, "copy to device failed");
+    } else {
+        hipLaunchKernelGGL(k_diag_arith, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, nullptr, count, d,
+                           d + count, d + 2 * count, d + 3 * count, d + 4 * count);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(quot, d + 3 * count, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(fmav, d + 4 * count, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = set_error(LP_E_DEVICE, "diagnostic kernel failed");
+    }
+    (void)hipFree(d);
+    (void)hipSetDevice(prev);
+    return rc;
+}

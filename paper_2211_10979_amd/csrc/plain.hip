@@ -1,0 +1,459 @@
+// Host side of the single-LP solver: context lifetime, the captured pivot
+// graph, and the C entry points lp_create ... lp_destroy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "plain_kernels.hpp"
+
+using namespace lpgpu;
+
+namespace {
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct UpdateConfig {
+    int block;  // threads per workgroup
+    int vpt;    // double2 vectors per thread kept in registers (0 = general form)
+};
+
+// Smallest (block, VPT) whose block*VPT vectors cover the m+1 rows.
+UpdateConfig pick_update_config(int32_t m) {
+    const int64_t nvec = ((int64_t)m + 2) / 2;
+    if (nvec <= 64) return {64, 1};
+    if (nvec <= 128) return {128, 1};
+    if (nvec <= 256) return {256, 1};
+    if (nvec <= 512) return {256, 2};
+    if (nvec <= 1024) return {256, 4};
+    if (nvec <= 2048) return {256, 8};
+    if (nvec <= 4096) return {256, 16};
+    return {1024, 0};
+}
+
+}  // namespace
+
+struct lp_ctx {
+    int device = 0;
+    int32_t m = 0, n = 0;
+    int64_t W = 0, ld = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double *T = nullptr;
+    bool own_T = false;
+    double *F = nullptr;
+    ArgMin *parts = nullptr;
+    DevState *st = nullptr;
+    int32_t *basis = nullptr;
+    int32_t *log_r = nullptr, *log_q = nullptr;
+    double *out = nullptr;
+    DevState *host_st = nullptr;  // pinned, two slots for the pipelined status read-back
+    double eps_d = 1e-9, eps_p = 1e-9;
+    int64_t max_pivots = 0, log_cap = 0;
+    int cols_per_block = 8, nparts = 0;
+    UpdateConfig ucfg{};
+    int chunk = 8;
+    bool use_graph = true;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
+    int64_t pivots_host = 0;
+    int32_t status_host = LP_RUNNING;
+    bool ran = false;
+    double last_ms = -1.0;
+};
+
+namespace {
+
+void free_ctx(lp_ctx *h) {
+    if (!h) return;
+    DeviceGuard g(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->own_T && h->T) (void)hipFree(h->T);
+    if (h->F) (void)hipFree(h->F);
+    if (h->parts) (void)hipFree(h->parts);
+    if (h->st) (void)hipFree(h->st);
+    if (h->basis) (void)hipFree(h->basis);
+    if (h->log_r) (void)hipFree(h->log_r);
+    if (h->log_q) (void)hipFree(h->log_q);
+    if (h->out) (void)hipFree(h->out);
+    if (h->host_st) (void)hipHostFree(h->host_st);
+    if (h->ev_start) (void)hipEventDestroy(h->ev_start);
+    if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
+    for (auto &e : h->ev_slot)
+        if (e) (void)hipEventDestroy(e);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int validate_opts(const lp_options &o) {
+    if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
+        return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
+    if (o.cols_per_block < 0 || o.cols_per_block > kMaxColsPerBlock)
+        return set_error(LP_E_INVAL, "cols_per_block must be in [0, 64]");
+    if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
+    return LP_OK;
+}
+
+// Allocates everything except the inputs; the tableau is not built yet.
+int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
+    lp_options o;
+    lp_options_default(&o);
+    if (opt_in) o = *opt_in;
+    if (int rc = validate_opts(o)) return rc;
+    int ndev = 0;
+    LP_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
+
+    lp_ctx *h = new (std::nothrow) lp_ctx;
+    if (!h) return set_error(LP_E_NOMEM, "host allocation failed");
+    h->device = o.device;
+    DeviceGuard g(h->device);
+    h->m = m;
+    h->n = n;
+    h->W = (int64_t)n + m + 1;
+    h->ld = padded_ld(m);
+    h->eps_d = o.eps_dual;
+    h->eps_p = o.eps_pivot;
+    h->max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m + n);
+    h->log_cap = o.record_pivots ? h->max_pivots : 0;
+    h->cols_per_block = o.cols_per_block > 0 ? o.cols_per_block : 8;
+    h->nparts = (int)((h->W + h->cols_per_block - 1) / h->cols_per_block);
+    h->ucfg = pick_update_config(m);
+    h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
+    h->use_graph = o.use_graph != 0;
+
+    auto fail = [&](int rc) {
+        free_ctx(h);
+        return rc;
+    };
+    auto dev_alloc = [&](void **p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(e == hipErrorOutOfMemory ? LP_E_NOMEM : LP_E_DEVICE,
+                             std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        return LP_OK;
+    };
+
+    if (o.stream) {
+        h->stream = (hipStream_t)o.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(set_error(LP_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
+        h->own_stream = true;
+    }
+    const size_t tbytes = lp_tableau_bytes(m, n);
+    if (o.device_buffer) {
+        if (o.device_buffer_bytes < tbytes || ((uintptr_t)o.device_buffer & 255u))
+            return fail(set_error(LP_E_INVAL, "device_buffer too small or not 256-byte aligned"));
+        h->T = (double *)o.device_buffer;
+    } else {
+        if (int rc = dev_alloc((void **)&h->T, tbytes)) return fail(rc);
+        h->own_T = true;
+    }
+    if (int rc = dev_alloc((void **)&h->F, (size_t)h->ld * sizeof(double))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->parts, (size_t)h->nparts * sizeof(ArgMin))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->st, sizeof(DevState))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->basis, (size_t)m * sizeof(int32_t))) return fail(rc);
+    if (h->log_cap) {
+        if (int rc = dev_alloc((void **)&h->log_r, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->log_q, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
+    }
+    if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
+    {
+        hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
+        if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
+    }
+    if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_slot[1], hipEventDisableTiming) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
+    *out = h;
+    return LP_OK;
+}
+
+// Initialization Step from device-resident inputs, on the context stream.
+int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *dc) {
+    const int32_t m = h->m, n = h->n;
+    const int64_t ld = h->ld;
+    dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
+    hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, h->stream, h->T, ld, m, n, dA, dc);
+    const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
+    hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, h->stream, h->T, ld, m,
+                       n, db);
+    DevState init{};
+    init.status = LP_RUNNING;
+    init.go = 0;
+    init.pivots = 0;
+    init.stop_at = 0;
+    init.max_pivots = h->max_pivots;
+    init.log_cap = h->log_cap;
+    init.eps_d = h->eps_d;
+    init.eps_p = h->eps_p;
+    init.fresh = 1;
+    init.nparts = h->nparts;
+    const int64_t ninit = std::max<int64_t>(std::max<int64_t>(m, ld), 1);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init, h->basis,
+                       m, n, h->F, ld);
+    LP_HIP_CHECK(hipGetLastError());
+    h->pivots_host = 0;
+    h->status_host = LP_RUNNING;
+    h->ran = false;
+    return LP_OK;
+}
+
+void launch_pivot(lp_ctx *h) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts, h->st, h->F,
+                       h->basis, h->log_r, h->log_q);
+    const dim3 grid((unsigned)h->nparts), block((unsigned)h->ucfg.block);
+#define LP_UPD(B, V)                                                                                   \
+    if (h->ucfg.block == B && h->ucfg.vpt == V) {                                                      \
+        hipLaunchKernelGGL((k_update<B, V>), grid, block, 0, h->stream, h->T, h->ld, h->m, h->n,       \
+                           h->cols_per_block, h->F, h->st, h->parts);                                  \
+        return;                                                                                        \
+    }
+    LP_UPD(64, 1)
+    LP_UPD(128, 1)
+    LP_UPD(256, 1)
+    LP_UPD(256, 2)
+    LP_UPD(256, 4)
+    LP_UPD(256, 8)
+    LP_UPD(256, 16)
+    LP_UPD(1024, 0)
+#undef LP_UPD
+}
+
+int launch_chunk(lp_ctx *h) {
+    if (!h->use_graph) {
+        for (int k = 0; k < h->chunk; ++k) launch_pivot(h);
+        LP_HIP_CHECK(hipGetLastError());
+        return LP_OK;
+    }
+    if (!h->gexec) {
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        LP_HIP_CHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < h->chunk; ++k) launch_pivot(h);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (e != hipSuccess) return set_error(LP_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        h->graph = graph;
+        LP_HIP_CHECK(hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0));
+    }
+    LP_HIP_CHECK(hipGraphLaunch(h->gexec, h->stream));
+    return LP_OK;
+}
+
+// Runs pivots until the status leaves RUNNING or `stop_at` pivots are done.
+// Chunks are pipelined two deep: chunk k+1 is queued before the status of
+// chunk k is read back, so the device never waits for the host.
+int run_until(lp_ctx *h, int64_t stop_at) {
+    DeviceGuard g(h->device);
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
+    LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
+    int slot = 0;
+    if (int rc = launch_chunk(h)) return rc;
+    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    LP_HIP_CHECK(hipEventRecord(h->ev_slot[0], h->stream));
+    for (;;) {
+        const int next = slot ^ 1;
+        if (int rc = launch_chunk(h)) return rc;
+        LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[next], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        LP_HIP_CHECK(hipEventRecord(h->ev_slot[next], h->stream));
+        LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
+        const DevState s = h->host_st[slot];
+        if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
+        slot = next;
+    }
+    LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    DevState s;
+    LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    h->pivots_host = s.pivots;
+    h->status_host = s.status;
+    float ms = 0.f;
+    LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    h->last_ms = ms;
+    h->ran = true;
+    return LP_OK;
+}
+
+bool all_finite(const double *p, int64_t k) {
+    for (int64_t i = 0; i < k; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_create_device(lp_ctx **out, int32_t m, int32_t n, const double *dA, const double *db, const double *dc,
+                     const lp_options *opt) {
+    if (!out) return set_error(LP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < 1 || !dA || !db || !dc) return set_error(LP_E_INVAL, "m, n must be >= 1 and inputs non-NULL");
+    lp_ctx *h = nullptr;
+    if (int rc = alloc_ctx(&h, m, n, opt)) return rc;
+    DeviceGuard g(h->device);
+    if (int rc = enqueue_build(h, dA, db, dc)) {
+        free_ctx(h);
+        return rc;
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_ctx(h);
+        return set_error(LP_E_DEVICE, std::string("build: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return LP_OK;
+}
+
+int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+              const lp_options *opt) {
+    if (!out) return set_error(LP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < 1 || !A || !b || !c) return set_error(LP_E_INVAL, "m, n must be >= 1 and inputs non-NULL");
+    if (!all_finite(A, (int64_t)m * n) || !all_finite(b, m) || !all_finite(c, n))
+        return set_error(LP_E_INVAL, "non-finite input");
+    for (int32_t i = 0; i < m; ++i)
+        if (b[i] < 0.0) return set_error(LP_E_NEG_RHS, "b has a negative entry: the slack basis is infeasible");
+    lp_ctx *h = nullptr;
+    if (int rc = alloc_ctx(&h, m, n, opt)) return rc;
+    DeviceGuard g(h->device);
+    double *stage = nullptr;
+    const size_t na = (size_t)m * n, bytes = (na + m + n) * sizeof(double);
+    hipError_t e = hipMalloc((void **)&stage, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_ctx(h);
+        return set_error(LP_E_NOMEM, "hipMalloc (input staging) failed");
+    }
+    int rc = LP_OK;
+    if (hipMemcpyAsync(stage, A, na * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(stage + na, b, (size_t)m * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(stage + na + m, c, (size_t)n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        rc = set_error(LP_E_DEVICE, "input copy failed");
+    if (!rc) rc = enqueue_build(h, stage, stage + na, stage + na + m);
+    if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = set_error(LP_E_DEVICE, "build failed");
+    (void)hipFree(stage);
+    if (rc) {
+        free_ctx(h);
+        return rc;
+    }
+    *out = h;
+    return LP_OK;
+}
+
+int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double *dc) {
+    if (!h || !dA || !db || !dc) return set_error(LP_E_INVAL, "NULL argument");
+    DeviceGuard g(h->device);
+    return enqueue_build(h, dA, db, dc);
+}
+
+int lp_solve(lp_ctx *h) {
+    if (!h) return set_error(LP_E_INVAL, "NULL context");
+    return run_until(h, INT64_MAX);
+}
+
+int lp_step(lp_ctx *h, int64_t pivots) {
+    if (!h || pivots < 0) return set_error(LP_E_INVAL, "NULL context or negative pivot budget");
+    DeviceGuard g(h->device);
+    if (h->ran || h->pivots_host > 0) {
+        DevState s;
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+        h->pivots_host = s.pivots;
+    }
+    const int64_t stop = h->pivots_host > INT64_MAX - pivots ? INT64_MAX : h->pivots_host + pivots;
+    return run_until(h, stop);
+}
+
+int lp_get_solution(const lp_ctx *hc, lp_result *res, double *x, double *y) {
+    if (!hc) return set_error(LP_E_INVAL, "NULL context");
+    if (!hc->ran) return set_error(LP_E_STATE, "no solve has run on this context");
+    lp_ctx *h = const_cast<lp_ctx *>(hc);
+    DeviceGuard g(h->device);
+    hipLaunchKernelGGL(k_extract, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->basis, h->out);
+    LP_HIP_CHECK(hipGetLastError());
+    std::vector<double> buf((size_t)h->n + h->m + 1);
+    LP_HIP_CHECK(hipMemcpyAsync(buf.data(), h->out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    DevState s;
+    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    s = h->host_st[0];
+    if (x) std::memcpy(x, buf.data(), (size_t)h->n * sizeof(double));
+    if (y) std::memcpy(y, buf.data() + h->n, (size_t)h->m * sizeof(double));
+    if (res) {
+        res->status = s.status;
+        res->reserved = 0;
+        res->pivots = s.pivots;
+        res->objective = buf[(size_t)h->n + h->m];
+        res->solve_ms = h->last_ms;
+    }
+    return LP_OK;
+}
+
+int lp_get_pivots(const lp_ctx *h, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count) {
+    if (!h || cap < 0 || (cap > 0 && (!rows || !cols))) return set_error(LP_E_INVAL, "bad argument");
+    DeviceGuard g(h->device);
+    DevState s;
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (count) *count = s.pivots;
+    const int64_t k = std::min<int64_t>(std::min<int64_t>(s.pivots, h->log_cap), cap);
+    if (k > 0) {
+        LP_HIP_CHECK(hipMemcpy(rows, h->log_r, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost));
+        LP_HIP_CHECK(hipMemcpy(cols, h->log_q, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return LP_OK;
+}
+
+int lp_get_tableau(const lp_ctx *h, double *out) {
+    if (!h || !out) return set_error(LP_E_INVAL, "NULL argument");
+    DeviceGuard g(h->device);
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    LP_HIP_CHECK(hipMemcpy2D(out, (size_t)(h->m + 1) * sizeof(double), h->T, (size_t)h->ld * sizeof(double),
+                             (size_t)(h->m + 1) * sizeof(double), (size_t)h->W, hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+int lp_get_basis(const lp_ctx *h, int32_t *basis) {
+    if (!h || !basis) return set_error(LP_E_INVAL, "NULL argument");
+    DeviceGuard g(h->device);
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    LP_HIP_CHECK(hipMemcpy(basis, h->basis, (size_t)h->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return LP_OK;
+}
+
+int lp_get_info(const lp_ctx *h, lp_info *info) {
+    if (!h || !info) return set_error(LP_E_INVAL, "NULL argument");
+    info->m = h->m;
+    info->n = h->n;
+    info->width = h->W;
+    info->ld = h->ld;
+    info->tableau_bytes = lp_tableau_bytes(h->m, h->n);
+    info->tableau = h->T;
+    return LP_OK;
+}
+
+void lp_destroy(lp_ctx *h) { free_ctx(h); }
+
+}  // extern "C"
