@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the dense full-tableau simplex on one MI355X; prints one JSON line.
+
+One step = one pass of the whole solve on the 8000 x 8000 dense LP (seed 3;
+tableau 8001 x 16001 binary64, about 1 GB, resident in HBM): rebuild the
+tableau of Table I from the device-resident A, b, c (Initialization Step),
+pivot with Steps 1-3 until optimal, and extract x, y and the objective.
+
+Reported:
+  value           pivots/s over the timed steps (inputs already in HBM);
+  roofline        the Step 3 update kernel (the dominant one): algorithmic
+                  bytes per launch / its average duration from HIP events
+                  recorded around it on its own stream during the timed
+                  steps, against 8 TB/s;
+  cpu_baseline    the CPU oracle on the host cores, on full solves of the
+                  same LP (generation excluded);
+  batched/serving the batched and the served forms, when built.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pivots/s + HBM GB/s (m=n=8000 FP64); batched LP solves/s & p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def update_bytes(m: int, n: int, cols: int, launches: int) -> float:
+    """Algorithmic bytes of `launches` update kernels that rewrote `cols`
+    columns in total: each rewritten column is read and written once
+    (16 (m+1) B); every launch also reads the pivot column F (8 (m+1) B) and,
+    for every column, its pivot-row and row-0 entries (16 W B)."""
+    W = n + m + 1
+    return 16.0 * (m + 1) * cols + launches * (8.0 * (m + 1) + 16.0 * W)
+
+
+def bench_plain(args, lpgpu, lpgen, torch):
+    lp = lpgen.workload(args.workload)
+    m, n = lp.m, lp.n
+    dev = torch.device("cuda", 0)
+    dA = torch.from_numpy(lp.A).to(dev)
+    db = torch.from_numpy(lp.b).to(dev)
+    dc = torch.from_numpy(lp.c).to(dev)
+    torch.cuda.synchronize()
+    h = lpgpu.lp_create_device(m, n, dA, db, dc, time_kernels=args.time_kernels, chunk_pivots=args.chunk,
+                               cols_per_block=args.cols_per_block, rows_per_thread=args.rows_per_thread)
+    try:
+        def step():
+            lpgpu.lp_reload_device(h, dA, db, dc)
+            lpgpu.lp_solve(h)
+            return lpgpu.lp_get_solution(h)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        tot_piv = tot_cols = tot_launch = 0
+        upd_ms = 0.0
+        solve_ms = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res, x, y = step()
+            t = lpgpu.lp_get_timing(h)
+            tot_piv += t["pivots"]
+            tot_cols += t["updated_columns"]
+            tot_launch += t["update_launches"]
+            upd_ms += t["update_ms"]
+            solve_ms += t["solve_ms"]
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        rows, cols = lpgpu.lp_get_pivots(h)
+    finally:
+        lpgpu.lp_destroy(h)
+    from paper_2211_10979_amd.certify import certify
+
+    ok, resid = certify(lp.A, lp.b, lp.c, x, y, res["objective"])
+    W = n + m + 1
+    per_piv = tot_piv / args.steps
+    alg_total = update_bytes(m, n, tot_cols, tot_piv)
+    out = dict(
+        value=tot_piv / elapsed,
+        ms_per_step=1000.0 * elapsed / args.steps,
+        pivots_per_solve=per_piv,
+        solves_per_s=args.steps / elapsed,
+        status=lpgpu.STATUS_NAMES[res["status"]],
+        objective=res["objective"],
+        certificates_ok=bool(ok),
+        certificate_max_residual=max(resid.values()),
+        end_to_end_alg_gbs=alg_total / elapsed / 1e9,
+        end_to_end_alg_frac=alg_total / elapsed / 1e9 / HBM_PEAK_GBS,
+        device_solve_ms_per_step=solve_ms / args.steps,
+        full_tableau_bytes_per_pivot=16.0 * (m + 1) * W,
+        log=(rows, cols),
+        lp=lp,
+    )
+    if tot_launch:
+        per_launch_bytes = update_bytes(m, n, tot_cols, tot_piv) / tot_piv
+        avg_ms = upd_ms / tot_launch
+        ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                               kernel="k_update", avg_launch_us=round(avg_ms * 1e3, 2),
+                               alg_bytes_per_launch=per_launch_bytes, launches=tot_launch,
+                               columns_per_launch=tot_cols / tot_piv)
+    return out
+
+
+def cpu_baseline(args, lp, gpu_log):
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    budget = args.cpu_seconds
+    t_total = 0.0
+    pivots = 0
+    solves = 0
+    match = None
+    while solves == 0 or t_total < budget:
+        o = oracle.OracleLP(lp.A, lp.b, lp.c, threads=threads)
+        t0 = time.perf_counter()
+        o.step(-1)
+        t_total += time.perf_counter() - t0
+        pivots += o.pivots
+        solves += 1
+        if match is None:
+            r, q = o.log()
+            match = r.tolist() == gpu_log[0].tolist() and q.tolist() == gpu_log[1].tolist()
+        o.close()
+    return dict(value=pivots / t_total, unit="pivots/s", cores=threads, kind="oracle",
+                sample=f"{solves} full solve(s) of {args.workload} ({pivots // solves} pivots each), "
+                       f"{t_total:.1f} s of CPU time, input generation excluded",
+                solves_per_s=solves / t_total, oracle_log_matches_gpu=bool(match))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dense_8000x8000")
+    ap.add_argument("--chunk", type=int, default=0, help="pivots per graph replay (0 = library default)")
+    ap.add_argument("--cols-per-block", type=int, default=0)
+    ap.add_argument("--rows-per-thread", type=int, default=0)
+    ap.add_argument("--time-kernels", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run the plain copy kernel over this many GiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(f"bench.py runs on one GPU only: the solver keeps each LP on a single device "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2211_10979_amd import lpgen, lpgpu
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lpgpu.library()  # fails loudly when the HIP library is not built
+
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * (1 << 30))
+        ms = lpgpu.lp_diag_copy(nbytes, reps=5)
+        print(json.dumps(dict(copy_bytes=nbytes, copy_ms=ms, copy_gbs=2 * nbytes / ms / 1e6)), flush=True)
+        return
+
+    log(f"plain solve: {args.workload}, warmup {args.warmup}, steps {args.steps}")
+    plain = bench_plain(args, lpgpu, lpgen, torch)
+    lp = plain.pop("lp")
+    gpu_log = plain.pop("log")
+    roof = plain.pop("roofline", None)
+    w = lpgen.WORKLOADS[args.workload]
+    line = dict(
+        metric=METRIC,
+        value=round(plain["value"], 2),
+        unit="pivots/s",
+        n_gpus=1,
+        steps=args.steps,
+        warmup=args.warmup,
+        ms_per_step=round(plain["ms_per_step"], 4),
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="f64",
+        data="synthetic",
+        config=dict(workload=args.workload, m=w["m"], n=w["n"], seed=w["seed"],
+                    tableau=f"{w['m'] + 1}x{w['m'] + w['n'] + 1}", generator="A,b,c integer uniform [1,1000]",
+                    parallelism="single GPU"),
+        roofline=roof,
+        plain=plain,
+    )
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle")
+        line["cpu_baseline"] = cpu_baseline(args, lp, gpu_log)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,8 +78,14 @@ typedef struct {
                                outlive the context                            (default NULL) */
     size_t device_buffer_bytes;
     int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto */
-    int32_t cols_per_block; /* update kernel: tableau columns per workgroup; 0 = auto */
+    int32_t cols_per_block; /* update kernel: listed columns per workgroup (1, 2, 4, 8, 16; 0 = auto) */
     int32_t use_graph;      /* 1 = replay a captured hipGraph, 0 = plain launches (default 1) */
+    int32_t time_kernels;   /* 1 = time every update kernel with HIP events (lp_get_timing); the
+                               kernels are then launched directly, not from a graph (default 0) */
+    int32_t rows_per_thread;/* update kernel: row pairs per thread and column (1, 2, 4, 8; 0 = auto) */
+    int32_t batch_block;    /* batched kernel: threads per workgroup (256, 512, 1024; 0 = autotune
+                               cache or default) */
+    int32_t batch_unroll;   /* batched kernel: items in flight per thread (1, 2, 4, 8; 0 = auto) */
     int32_t reserved;
 } lp_options;
 
@@ -180,6 +186,19 @@ int lp_get_basis(const lp_ctx *h, int32_t *basis);
 /* Sizes and the device tableau pointer. */
 int lp_get_info(const lp_ctx *h, lp_info *info);
 
+typedef struct {
+    double solve_ms;          /* device time of the last lp_solve / lp_step */
+    double update_ms;         /* summed device time of the update kernels that applied a pivot
+                                 during that call (time_kernels = 1; else 0) */
+    int64_t update_launches;  /* number of update kernels in update_ms */
+    int64_t pivots;           /* pivots performed since the tableau was built */
+    int64_t updated_columns;  /* tableau columns rewritten by Step 3, summed over those pivots
+                                 (columns whose normalised pivot-row entry is nonzero) */
+} lp_timing;
+
+/* Timing and work counters of the context (see lp_timing). */
+int lp_get_timing(const lp_ctx *h, lp_timing *t);
+
 /* Frees the context and its device memory (not a caller's device_buffer). NULL-safe. */
 void lp_destroy(lp_ctx *h);
 
@@ -193,6 +212,15 @@ void lp_destroy(lp_ctx *h);
  */
 int lp_diag_arith(int32_t device, int64_t count, const double *a, const double *b, const double *c, double *quot,
                   double *fmav);
+
+/*
+ * Diagnostic: a plain device-to-device copy of `bytes` bytes (rounded down to
+ * a multiple of 16), repeated `reps` times on `device`, between two buffers
+ * the call allocates and frees. Reads and writes exactly `bytes` per
+ * repetition, so hardware byte counters of this kernel calibrate those of the
+ * solver's kernels. *ms receives the average device time of one copy.
+ */
+int lp_diag_copy(int32_t device, size_t bytes, int32_t reps, double *ms);
 
 /* ------------------------------------------------------------------ batched
  * Many independent LPs advanced together by one persistent kernel, captured
@@ -219,6 +247,26 @@ int lp_batch_get_pivots(const lp_batch *bt, int32_t k, int32_t *rows, int32_t *c
 
 /* Device time of the last lp_batch_solve in milliseconds (negative if none). */
 double lp_batch_solve_ms(const lp_batch *bt);
+
+/* Rebuilds every tableau from the inputs kept by lp_batch_create (the
+ * Initialization Step again), so that the batch can be solved again. */
+int lp_batch_reset(lp_batch *bt);
+
+/* The persistent kernel's shape in use: threads per workgroup, items in
+ * flight per thread, workgroups per compute unit. Any pointer may be NULL. */
+int lp_batch_get_shape(const lp_batch *bt, int32_t *block, int32_t *unroll, int32_t *grid_per_cu);
+
+/*
+ * Autotuner: solves the batch once per candidate kernel shape (rebuilding the
+ * tableaux before each trial, best of `trials` runs), keeps the fastest
+ * shape for later solves, leaves the batch reset, and appends the choice to
+ * the JSON-lines cache `cache_path` (NULL: no file) under the batch's size
+ * bucket (LP count and largest m, n, each rounded up to a power of two).
+ * lp_batch_create applies a cached choice when the environment variable
+ * LP_AUTOTUNE_CACHE names that file. *best_ms (may be NULL) receives the
+ * fastest solve time.
+ */
+int lp_batch_autotune(lp_batch *bt, const char *cache_path, int32_t trials, double *best_ms);
 
 void lp_batch_destroy(lp_batch *bt);
 

@@ -49,6 +49,10 @@ int lp_options_default(lp_options *o) {
     o->chunk_pivots = 0;
     o->cols_per_block = 0;
     o->use_graph = 1;
+    o->time_kernels = 0;
+    o->rows_per_thread = 0;
+    o->batch_block = 0;
+    o->batch_unroll = 0;
     o->reserved = 0;
     return LP_OK;
 }

@@ -1,0 +1,567 @@
+// Host side of the batched solver (lp_batch_*): one arena for every LP's
+// tableau and lists, a captured graph {queue reset, persistent kernel}, and
+// the autotuner that picks the persistent kernel's shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "batch_engine.hpp"
+#include "plain_kernels.hpp"
+
+using namespace lpgpu;
+
+namespace lpgpu {
+
+const BatchShape kBatchShapes[] = {
+    {256, 1, 2}, {256, 2, 2}, {256, 4, 2}, {256, 4, 4}, {256, 8, 2}, {512, 1, 1}, {512, 2, 1}, {512, 2, 2},
+    {512, 4, 1}, {512, 4, 2}, {1024, 1, 1}, {1024, 2, 1}, {1024, 4, 1}, {1024, 2, 2},
+};
+const int kNumBatchShapes = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
+
+size_t batch_lds_bytes(int32_t m, int32_t n) {
+    const int64_t nvec = ((int64_t)m + 2) / 2;
+    return (size_t)(16 * nvec + 12 * ((int64_t)n + 2));
+}
+
+bool batch_fits(int32_t m, int32_t n, size_t lds_limit) {
+    const int64_t nvec = ((int64_t)m + 2) / 2;
+    return nvec < 4096 && ((int64_t)n + 2) * nvec < (int64_t)1 << 24 && batch_lds_bytes(m, n) <= lds_limit;
+}
+
+uint64_t nvec_magic(int32_t nvec) { return (((uint64_t)1 << 36) + (uint64_t)nvec - 1) / (uint64_t)nvec; }
+
+int launch_batch_kernel(const BatchShape &sh, int grid, size_t lds, hipStream_t stream, const BatchDesc *desc,
+                        BatchState *state, const int32_t *order, const int32_t *norder, int32_t *head,
+                        int64_t budget) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, head);
+#define LP_BATCH(B, U)                                                                                          \
+    if (sh.block == B && sh.unroll == U) {                                                                      \
+        hipLaunchKernelGGL((k_batch<B, U>), dim3((unsigned)grid), dim3(B), lds, stream, desc, state, order,     \
+                           norder, head, budget);                                                               \
+        return LP_OK;                                                                                           \
+    }
+    LP_BATCH(256, 1)
+    LP_BATCH(256, 2)
+    LP_BATCH(256, 4)
+    LP_BATCH(256, 8)
+    LP_BATCH(512, 1)
+    LP_BATCH(512, 2)
+    LP_BATCH(512, 4)
+    LP_BATCH(1024, 1)
+    LP_BATCH(1024, 2)
+    LP_BATCH(1024, 4)
+#undef LP_BATCH
+    return set_error(LP_E_INVAL, "unsupported batch kernel shape");
+}
+
+// Raises (never lowers) the dynamic-LDS limit of every batched-kernel
+// instance: batches and servers of one process share these attributes.
+int set_batch_lds_limit(size_t lds) {
+    static std::mutex mu;
+    static size_t current = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (lds <= current) return LP_OK;
+#define LP_ATTR(B, U)                                                                                         \
+    LP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<B, U>),                         \
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    LP_ATTR(256, 1)
+    LP_ATTR(256, 2)
+    LP_ATTR(256, 4)
+    LP_ATTR(256, 8)
+    LP_ATTR(512, 1)
+    LP_ATTR(512, 2)
+    LP_ATTR(512, 4)
+    LP_ATTR(1024, 1)
+    LP_ATTR(1024, 2)
+    LP_ATTR(1024, 4)
+#undef LP_ATTR
+    current = lds;
+    return LP_OK;
+}
+
+size_t device_lds_limit(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 64 * 1024;
+    return prop.sharedMemPerBlock;
+}
+
+int device_cus(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
+    return prop.multiProcessorCount;
+}
+
+// ---- autotune cache: one JSON object per line,
+// {"key": "<bucket>", "block": B, "unroll": U, "grid_per_cu": G, "ms": t}
+std::string batch_bucket_key(int32_t count, int32_t mmax, int32_t nmax) {
+    auto up = [](int64_t x) {
+        int64_t p = 1;
+        while (p < x) p <<= 1;
+        return p;
+    };
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "batch/count%lld/m%lld/n%lld", (long long)up(count), (long long)up(mmax),
+                  (long long)up(nmax));
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, BatchShape *out) {
+    if (!path || !*path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        int b = 0, u = 0, g = 0;
+        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d", k, &b,
+                        &u, &g) == 4 &&
+            key == k) {
+            for (int i = 0; i < kNumBatchShapes; ++i)
+                if (kBatchShapes[i].block == b && kBatchShapes[i].unroll == u && kBatchShapes[i].grid_per_cu == g) {
+                    *out = kBatchShapes[i];
+                    found = true;  // the last matching line wins
+                }
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const BatchShape &sh, double ms) {
+    if (!path || !*path) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), sh.block, sh.unroll, sh.grid_per_cu, ms);
+    std::fclose(f);
+}
+
+}  // namespace lpgpu
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct lp_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t count = 0;
+    std::vector<int32_t> m, n;
+    std::vector<int64_t> ld, out_off, in_off;
+    std::vector<BatchDesc> desc_host;
+    double *tab = nullptr;       // tableaux
+    int32_t *ints = nullptr;     // basis, lists, logs
+    double *inputs = nullptr;    // A, b, c of every LP, kept for rebuilds
+    double *out = nullptr;       // x, y, objective of every LP
+    int64_t *out_off_dev = nullptr;
+    BatchDesc *desc = nullptr;
+    BatchState *state = nullptr;
+    int32_t *order = nullptr;    // LP indices, largest first
+    int32_t *norder = nullptr;   // number of entries of `order`
+    int32_t *head = nullptr;     // queue head
+    BatchState init{};
+    size_t lds = 0;
+    BatchShape shape{};
+    int cus = 256;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double last_ms = -1.0;
+    bool solved = false;
+    std::vector<BatchState> st_host;
+    std::vector<double> out_host;
+};
+
+namespace {
+
+void free_batch(lp_batch *b) {
+    if (!b) return;
+    DeviceGuard g(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : {(void *)b->tab, (void *)b->ints, (void *)b->inputs, (void *)b->out, (void *)b->out_off_dev,
+                    (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->norder, (void *)b->head})
+        if (p) (void)hipFree(p);
+    if (b->e0) (void)hipEventDestroy(b->e0);
+    if (b->e1) (void)hipEventDestroy(b->e1);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int capture_batch_graph(lp_batch *b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    const int grid = std::max(1, std::min<int>(b->count, b->shape.grid_per_cu * b->cus));
+    LP_HIP_CHECK(hipStreamSynchronize(b->stream));
+    LP_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_batch_kernel(b->shape, grid, b->lds, b->stream, b->desc, b->state, b->order, b->norder, b->head,
+                                 INT64_MAX);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(LP_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b->graph = graph;
+    LP_HIP_CHECK(hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0));
+    return LP_OK;
+}
+
+// Initialization Step for every LP, from the stored inputs.
+int rebuild_all(lp_batch *b) {
+    for (int32_t k = 0; k < b->count; ++k) {
+        const BatchDesc &d = b->desc_host[k];
+        const double *A = b->inputs + b->in_off[k];
+        const double *bb = A + (int64_t)d.m * d.n;
+        const double *c = bb + d.m;
+        dim3 gs((unsigned)((d.n + kBuildTile - 1) / kBuildTile), (unsigned)((d.ld + kBuildTile - 1) / kBuildTile));
+        hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, b->stream, d.T, d.ld, d.m, d.n, A, c);
+        const int64_t nslack = (int64_t)(d.m + 1) * (d.ld / 2);
+        hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, b->stream, d.T, d.ld,
+                           d.m, d.n, bb);
+        hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, b->stream, d, b->state + k, b->init);
+    }
+    LP_HIP_CHECK(hipGetLastError());
+    b->solved = false;
+    return LP_OK;
+}
+
+int run_batch(lp_batch *b) {
+    DeviceGuard g(b->device);
+    LP_HIP_CHECK(hipEventRecord(b->e0, b->stream));
+    LP_HIP_CHECK(hipGraphLaunch(b->gexec, b->stream));
+    LP_HIP_CHECK(hipEventRecord(b->e1, b->stream));
+    hipLaunchKernelGGL(k_batch_extract, dim3((unsigned)b->count), dim3(256), 0, b->stream, b->desc,
+                       b->out_off_dev, b->out);
+    LP_HIP_CHECK(hipGetLastError());
+    LP_HIP_CHECK(hipMemcpyAsync(b->st_host.data(), b->state, b->st_host.size() * sizeof(BatchState),
+                                hipMemcpyDeviceToHost, b->stream));
+    LP_HIP_CHECK(hipMemcpyAsync(b->out_host.data(), b->out, b->out_host.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, b->stream));
+    LP_HIP_CHECK(hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    LP_HIP_CHECK(hipEventElapsedTime(&ms, b->e0, b->e1));
+    b->last_ms = ms;
+    b->solved = true;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32_t *n, const double *const *A,
+                    const double *const *bv, const double *const *cv, const lp_options *opt_in) {
+    if (!out) return set_error(LP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !m || !n || !A || !bv || !cv) return set_error(LP_E_INVAL, "bad batch arguments");
+    lp_options o;
+    lp_options_default(&o);
+    if (opt_in) o = *opt_in;
+    if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
+        return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
+    int ndev = 0;
+    LP_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
+    const size_t lds_limit = device_lds_limit(o.device);
+    for (int32_t k = 0; k < count; ++k) {
+        if (m[k] < 1 || n[k] < 1 || !A[k] || !bv[k] || !cv[k])
+            return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": bad size or NULL input");
+        if (!batch_fits(m[k], n[k], lds_limit))
+            return set_error(LP_E_INVAL, "LP " + std::to_string(k) + " is too large for the batched kernel");
+        for (int64_t t = 0; t < (int64_t)m[k] * n[k]; ++t)
+            if (!std::isfinite(A[k][t])) return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": non-finite A");
+        for (int32_t i = 0; i < m[k]; ++i) {
+            if (!std::isfinite(bv[k][i])) return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": non-finite b");
+            if (bv[k][i] < 0.0) return set_error(LP_E_NEG_RHS, "LP " + std::to_string(k) + ": negative b");
+        }
+        for (int32_t j = 0; j < n[k]; ++j)
+            if (!std::isfinite(cv[k][j])) return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": non-finite c");
+    }
+
+    lp_batch *b = new (std::nothrow) lp_batch;
+    if (!b) return set_error(LP_E_NOMEM, "host allocation failed");
+    b->device = o.device;
+    DeviceGuard g(b->device);
+    auto fail = [&](int rc) {
+        free_batch(b);
+        return rc;
+    };
+    b->count = count;
+    b->m.assign(m, m + count);
+    b->n.assign(n, n + count);
+    b->cus = device_cus(o.device);
+    if (o.stream) {
+        b->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "hipStreamCreate failed"));
+        b->own_stream = true;
+    }
+    if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
+
+    // layout
+    int64_t tab_total = 0, int_total = 0, in_total = 0, out_total = 0;
+    std::vector<int64_t> tab_off(count), int_off(count), logcap(count);
+    b->ld.resize(count);
+    b->out_off.resize(count);
+    b->in_off.resize(count);
+    int32_t mmax = 0, nmax = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const int64_t ld = padded_ld(m[k]), W = (int64_t)n[k] + m[k] + 1;
+        b->ld[k] = ld;
+        tab_off[k] = tab_total;
+        tab_total += ld * W;
+        const int64_t maxp = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m[k] + n[k]);
+        logcap[k] = o.record_pivots ? std::min<int64_t>(maxp, 4 * ((int64_t)m[k] + n[k]) + 64) : 0;
+        int_off[k] = int_total;
+        int_total += (int64_t)m[k] + (n[k] + 2) + ((int64_t)n[k] + m[k]) + 2 * logcap[k];
+        int_total = (int_total + 3) / 4 * 4;
+        b->in_off[k] = in_total;
+        in_total += (int64_t)m[k] * n[k] + m[k] + n[k];
+        b->out_off[k] = out_total;
+        out_total += (int64_t)n[k] + m[k] + 1;
+        b->lds = std::max(b->lds, batch_lds_bytes(m[k], n[k]));
+        mmax = std::max(mmax, m[k]);
+        nmax = std::max(nmax, n[k]);
+    }
+    auto dmalloc = [&](void **p, size_t bytes) -> int {
+        if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(LP_E_NOMEM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+        }
+        return LP_OK;
+    };
+    if (int rc = dmalloc((void **)&b->tab, tab_total * sizeof(double))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->ints, int_total * sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->inputs, in_total * sizeof(double))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->out, out_total * sizeof(double))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->out_off_dev, count * sizeof(int64_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->desc, count * sizeof(BatchDesc))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->state, count * sizeof(BatchState))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->order, count * sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->norder, sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->head, sizeof(int32_t))) return fail(rc);
+
+    b->desc_host.resize(count);
+    for (int32_t k = 0; k < count; ++k) {
+        BatchDesc &d = b->desc_host[k];
+        d.T = b->tab + tab_off[k];
+        d.ld = b->ld[k];
+        d.m = m[k];
+        d.n = n[k];
+        int32_t *base = b->ints + int_off[k];
+        d.basis = base;
+        d.cols = base + m[k];
+        d.pos = d.cols + n[k] + 2;
+        d.log_r = d.pos + n[k] + m[k];
+        d.log_q = d.log_r + logcap[k];
+        d.log_cap = logcap[k];
+        d.nvec = (m[k] + 2) / 2;
+        d.magic = nvec_magic(d.nvec);
+        d.pad = 0;
+        d.scratch = nullptr;
+    }
+    // inputs, staged through one host buffer
+    {
+        std::vector<double> host((size_t)in_total);
+        for (int32_t k = 0; k < count; ++k) {
+            double *dst = host.data() + b->in_off[k];
+            std::memcpy(dst, A[k], (size_t)m[k] * n[k] * sizeof(double));
+            std::memcpy(dst + (int64_t)m[k] * n[k], bv[k], (size_t)m[k] * sizeof(double));
+            std::memcpy(dst + (int64_t)m[k] * n[k] + m[k], cv[k], (size_t)n[k] * sizeof(double));
+        }
+        if (hipMemcpy(b->inputs, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "input copy failed"));
+    }
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return (int64_t)m[a] * (n[a] + 2) > (int64_t)m[c] * (n[c] + 2);
+    });
+    if (hipMemcpy(b->desc, b->desc_host.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->norder, &count, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->out_off_dev, b->out_off.data(), count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "descriptor copy failed"));
+
+    b->init = BatchState{};
+    b->init.status = LP_RUNNING;
+    b->init.eps_d = o.eps_dual;
+    b->init.eps_p = o.eps_pivot;
+    b->init.max_pivots = 0;  // per LP below
+    b->st_host.resize(count);
+    b->out_host.resize((size_t)out_total);
+    // per-LP iteration caps differ: built by the init kernel from init, then patched
+    if (int rc = rebuild_all(b)) return fail(rc);
+    {
+        std::vector<BatchState> st(count);
+        for (int32_t k = 0; k < count; ++k) {
+            st[k] = b->init;
+            st[k].max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m[k] + n[k]);
+        }
+        if (hipStreamSynchronize(b->stream) != hipSuccess ||
+            hipMemcpy(b->state, st.data(), count * sizeof(BatchState), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "state init failed"));
+        b->st_host = st;
+    }
+    if (int rc = set_batch_lds_limit(b->lds)) return fail(rc);
+
+    // kernel shape: explicit option, else the autotune cache, else a default
+    b->shape = kBatchShapes[2];
+    const char *cache = std::getenv("LP_AUTOTUNE_CACHE");
+    BatchShape cached{};
+    if (o.batch_block > 0 || o.batch_unroll > 0) {
+        bool ok = false;
+        for (int i = 0; i < kNumBatchShapes; ++i)
+            if ((o.batch_block <= 0 || kBatchShapes[i].block == o.batch_block) &&
+                (o.batch_unroll <= 0 || kBatchShapes[i].unroll == o.batch_unroll)) {
+                b->shape = kBatchShapes[i];
+                ok = true;
+                break;
+            }
+        if (!ok) return fail(set_error(LP_E_INVAL, "no batch kernel shape with that block / unroll"));
+    } else if (cache_lookup(cache, batch_bucket_key(count, mmax, nmax), &cached)) {
+        b->shape = cached;
+    }
+    if (int rc = capture_batch_graph(b)) return fail(rc);
+    *out = b;
+    return LP_OK;
+}
+
+int lp_batch_solve(lp_batch *b) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    return run_batch(b);
+}
+
+int lp_batch_reset(lp_batch *b) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    DeviceGuard g(b->device);
+    std::vector<BatchState> st(b->count);
+    for (int32_t k = 0; k < b->count; ++k) {
+        st[k] = b->init;
+        st[k].max_pivots = b->st_host[k].max_pivots;
+    }
+    if (int rc = rebuild_all(b)) return rc;
+    LP_HIP_CHECK(hipMemcpyAsync(b->state, st.data(), st.size() * sizeof(BatchState), hipMemcpyHostToDevice,
+                                b->stream));
+    LP_HIP_CHECK(hipStreamSynchronize(b->stream));
+    b->solved = false;
+    return LP_OK;
+}
+
+int lp_batch_get_solution(const lp_batch *b, int32_t k, lp_result *res, double *x, double *y) {
+    if (!b || k < 0 || k >= b->count) return set_error(LP_E_INVAL, "bad batch or index");
+    if (!b->solved) return set_error(LP_E_STATE, "batch not solved yet");
+    const double *o = b->out_host.data() + b->out_off[k];
+    const int32_t m = b->m[k], n = b->n[k];
+    if (x) std::memcpy(x, o, (size_t)n * sizeof(double));
+    if (y) std::memcpy(y, o + n, (size_t)m * sizeof(double));
+    if (res) {
+        res->status = b->st_host[k].status;
+        res->reserved = 0;
+        res->pivots = b->st_host[k].pivots;
+        res->objective = o[n + m];
+        res->solve_ms = b->last_ms;
+    }
+    return LP_OK;
+}
+
+int lp_batch_get_pivots(const lp_batch *b, int32_t k, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count) {
+    if (!b || k < 0 || k >= b->count || cap < 0 || (cap > 0 && (!rows || !cols)))
+        return set_error(LP_E_INVAL, "bad argument");
+    DeviceGuard g(b->device);
+    LP_HIP_CHECK(hipStreamSynchronize(b->stream));
+    BatchState s;
+    LP_HIP_CHECK(hipMemcpy(&s, b->state + k, sizeof(s), hipMemcpyDeviceToHost));
+    const BatchDesc &d = b->desc_host[k];
+    if (count) *count = s.pivots;
+    const int64_t c = std::min<int64_t>(std::min<int64_t>(s.pivots, d.log_cap), cap);
+    if (c > 0) {
+        LP_HIP_CHECK(hipMemcpy(rows, d.log_r, (size_t)c * sizeof(int32_t), hipMemcpyDeviceToHost));
+        LP_HIP_CHECK(hipMemcpy(cols, d.log_q, (size_t)c * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return LP_OK;
+}
+
+double lp_batch_solve_ms(const lp_batch *b) { return b ? b->last_ms : -1.0; }
+
+int lp_batch_get_shape(const lp_batch *b, int32_t *block, int32_t *unroll, int32_t *grid_per_cu) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    if (block) *block = b->shape.block;
+    if (unroll) *unroll = b->shape.unroll;
+    if (grid_per_cu) *grid_per_cu = b->shape.grid_per_cu;
+    return LP_OK;
+}
+
+int lp_batch_autotune(lp_batch *b, const char *cache_path, int32_t trials, double *best_ms) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    if (trials < 1) trials = 1;
+    DeviceGuard g(b->device);
+    const BatchShape keep = b->shape;
+    double best = 1e300;
+    BatchShape best_shape = keep;
+    for (int i = 0; i < kNumBatchShapes; ++i) {
+        b->shape = kBatchShapes[i];
+        if (int rc = capture_batch_graph(b)) return rc;
+        double t = 1e300;
+        for (int r = 0; r < trials; ++r) {
+            if (int rc = lp_batch_reset(b)) return rc;
+            if (int rc = run_batch(b)) return rc;
+            t = std::min(t, b->last_ms);
+        }
+        if (t < best) {
+            best = t;
+            best_shape = b->shape;
+        }
+    }
+    b->shape = best_shape;
+    if (int rc = capture_batch_graph(b)) return rc;
+    if (int rc = lp_batch_reset(b)) return rc;
+    int32_t mmax = 0, nmax = 0;
+    for (int32_t k = 0; k < b->count; ++k) {
+        mmax = std::max(mmax, b->m[k]);
+        nmax = std::max(nmax, b->n[k]);
+    }
+    cache_store(cache_path, batch_bucket_key(b->count, mmax, nmax), best_shape, best);
+    if (best_ms) *best_ms = best;
+    return LP_OK;
+}
+
+void lp_batch_destroy(lp_batch *b) { free_batch(b); }
+
+}  // extern "C"

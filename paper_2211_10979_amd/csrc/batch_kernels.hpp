@@ -1,0 +1,308 @@
+// Kernels of the batched solver: many independent LPs, each advanced pivot
+// by pivot (Steps 1-3 of Section III) by one workgroup of a persistent kernel.
+//
+// Workgroups take LPs off a device queue (an atomic counter over an order
+// array, largest LP first). A workgroup runs its LP for at most `budget`
+// pivots, then takes the next one, so a launch always ends; an LP left
+// RUNNING continues in the next launch. Nothing waits on another workgroup.
+//
+// Within a workgroup one pivot is:
+//   Step 1  argmin over the nonbasic columns' row-0 entries (reduced while
+//           the previous pivot's update wrote them, or by a scan on entry);
+//   Step 2  ratio test over column q (block argmin);
+//   Step 3  F = column q and R = normalised pivot row (by rewrite-list
+//           position) staged in LDS, then the rewrite of every listed column.
+// The rewrite list (nonbasic columns, the entering column, the RHS) and its
+// maintenance are the same as the single-LP solver's; the arithmetic of every
+// entry is identical, so each LP follows the single-LP pivot sequence.
+#pragma once
+
+#include "common.hpp"
+
+namespace lpgpu {
+
+struct BatchDesc {
+    double *T;          // column-major tableau, T[i][j] = T[j*ld + i]
+    int64_t ld;         // padded rows (multiple of 16)
+    int32_t m, n;
+    int32_t *basis;     // m
+    int32_t *cols;      // n+2: nonbasic columns, entering column, RHS
+    int32_t *pos;       // n+m: position in cols[0..n) or -1
+    int32_t *log_r;     // log_cap
+    int32_t *log_q;
+    int64_t log_cap;
+    uint64_t magic;     // ceil(2^36 / nvec): item -> (column, row pair) split
+    int32_t nvec;       // (m+2)/2 row pairs per column
+    int32_t pad;
+    double *scratch;    // NULL: F, R and the list live in LDS; else in this global area
+};
+
+struct BatchState {
+    int32_t status;
+    int32_t pad;
+    int64_t pivots;
+    int64_t max_pivots;
+    int64_t cols_done;  // rewritten columns (nonzero R), summed over pivots
+    double eps_d, eps_p;
+};
+
+// Quotient by nvec of item < 2^24 with nvec < 2^12: exact, since
+// item * nvec < 2^36 (Granlund-Montgomery with a rounded-up reciprocal).
+__device__ __forceinline__ uint32_t div_nvec(uint32_t item, uint64_t magic) {
+    return (uint32_t)(((uint64_t)item * magic) >> 36);
+}
+
+template <int BT>
+__device__ __forceinline__ void batch_block_argmin(double &v, int32_t &i, double *sv, int32_t *si) {
+    wave_argmin(v, i);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int nw = BT / 64;
+    __syncthreads();
+    if (lane == 0) {
+        sv[wave] = v;
+        si[wave] = i;
+    }
+    __syncthreads();
+    v = lane < nw ? sv[lane] : __builtin_inf();
+    i = lane < nw ? si[lane] : kNoIndex;
+    wave_argmin(v, i);
+}
+
+// One LP, at most `budget` pivots. `work` holds F (2*nvec doubles), R (n+2
+// doubles) and the rewrite list (n+2 int32): the workgroup's LDS, or the
+// LP's global scratch area when they do not fit in LDS.
+template <int BT, int U>
+__device__ __forceinline__ void batch_solve_one(const BatchDesc &d, BatchState *__restrict__ stp, double *work,
+                                                double *sv, int32_t *si, int32_t *sint, int64_t budget) {
+    const int tid = threadIdx.x;
+    BatchState s = *stp;
+    if (s.status != LP_RUNNING) return;
+    const int32_t m = d.m, n = d.n;
+    const int64_t ld = d.ld;
+    const int64_t W = (int64_t)n + m + 1;
+    const int32_t nvec = d.nvec;
+    double *T = d.T;
+    double *F = work;                                        // 2*nvec
+    double *R = work + 2 * (int64_t)nvec;                    // n+2
+    int32_t *L = reinterpret_cast<int32_t *>(R + n + 2);     // n+2
+
+    // Step 1 on entry: scan the nonbasic columns' row-0 entries.
+    double v = __builtin_inf();
+    int32_t q = kNoIndex;
+    for (int32_t t = tid; t < n; t += BT) {
+        const int32_t j = d.cols[t];
+        const double x = T[(int64_t)j * ld];
+        if (lex_less(x, j, v, q)) {
+            v = x;
+            q = j;
+        }
+    }
+    batch_block_argmin<BT>(v, q, sv, si);
+
+    int64_t done = 0;
+    int32_t status = LP_RUNNING;
+    int64_t cols_done = 0;
+    for (;;) {
+        if (v != v) {
+            status = LP_NUMERICAL;
+            break;
+        }
+        if (v >= -s.eps_d) {
+            status = LP_OPTIMAL;
+            break;
+        }
+        if (done >= budget) break;
+
+        // Step 2.
+        const double *colq = T + (int64_t)q * ld;
+        const double *rhs = T + (W - 1) * ld;
+        double rv = __builtin_inf();
+        int32_t r = kNoIndex;
+        int bad = 0;
+        for (int32_t i = 1 + tid; i <= m; i += BT) {
+            const double a = colq[i], bb = rhs[i];
+            if (a != a || bb != bb) {
+                bad = 1;
+            } else if (a > s.eps_p) {
+                const double ratio = bb / a;
+                if (ratio != ratio)
+                    bad = 1;
+                else if (lex_less(ratio, i, rv, r)) {
+                    rv = ratio;
+                    r = i;
+                }
+            }
+        }
+        bad = __syncthreads_or(bad);
+        batch_block_argmin<BT>(rv, r, sv, si);
+        if (bad) {
+            status = LP_NUMERICAL;
+            break;
+        }
+        if (r == kNoIndex) {
+            status = LP_UNBOUNDED;
+            break;
+        }
+        if (s.pivots >= s.max_pivots) {
+            status = LP_ITER_LIMIT;
+            break;
+        }
+
+        // Step 3 inputs in LDS.
+        const double p = colq[r];
+        const int32_t leave = d.basis[r - 1];
+        const int32_t pq = d.pos[q];
+        for (int32_t i = tid; i < 2 * nvec; i += BT) F[i] = i <= m ? colq[i] : 0.0;
+        int32_t nz = 0;
+        for (int32_t t = tid; t < n + 2; t += BT) {
+            const int32_t j = t == pq ? leave : (t == n ? q : d.cols[t]);
+            const double Rt = T[(int64_t)j * ld + r] / p;
+            R[t] = Rt;
+            L[t] = j;
+            nz += Rt != 0.0;
+        }
+        for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
+        if ((tid & 63) == 0) sint[tid >> 6] = nz;
+        __syncthreads();  // F, R, L ready; every read of cols/pos/basis done
+        if (tid == 0) {
+            int32_t tot = 0;
+            for (int w = 0; w < BT / 64; ++w) tot += sint[w];
+            cols_done += tot;
+            d.cols[pq] = leave;
+            d.pos[leave] = pq;
+            d.pos[q] = -1;
+            d.cols[n] = q;
+            d.basis[r - 1] = q;
+            if (s.pivots < d.log_cap) {
+                d.log_r[s.pivots] = r;
+                d.log_q[s.pivots] = q;
+            }
+        }
+        s.pivots += 1;
+        done += 1;
+
+        // Step 3: rewrite every listed column; items are (column, row pair),
+        // row pairs fastest so that a wave reads contiguous memory.
+        const uint32_t items = (uint32_t)(n + 2) * (uint32_t)nvec;
+        const double2 *F2 = reinterpret_cast<const double2 *>(F);
+        double bestv = __builtin_inf();
+        int32_t bestj = kNoIndex;
+        const int32_t rhs_col = (int32_t)(W - 1);
+        auto rewrite = [&](uint32_t c, uint32_t vr, double2 *a, const double2 xx) {
+            const double Rt = R[c];
+            const double2 f = F2[vr];
+            const int32_t row = 2 * (int32_t)vr;
+            double2 y;
+            y.x = (row == r) ? Rt : fma(-f.x, Rt, xx.x);
+            y.y = (row + 1 == r) ? Rt : fma(-f.y, Rt, xx.y);
+            *a = y;
+            if (vr == 0) {  // row 0: candidate of the next Step 1
+                const int32_t j = L[c];
+                if (j != rhs_col && lex_less(y.x, j, bestv, bestj)) {
+                    bestv = y.x;
+                    bestj = j;
+                }
+            }
+        };
+        uint32_t base = tid;
+        // full rounds: U items per thread, all loads issued before any store
+        for (; base + (uint32_t)(U - 1) * BT < items; base += (uint32_t)BT * U) {
+            double2 x[U];
+            double2 *addr[U];
+            uint32_t vv[U], cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t it = base + (uint32_t)u * BT;
+                cc[u] = div_nvec(it, d.magic);
+                vv[u] = it - cc[u] * (uint32_t)nvec;
+                addr[u] = reinterpret_cast<double2 *>(T + (int64_t)L[cc[u]] * ld) + vv[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = *addr[u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rewrite(cc[u], vv[u], addr[u], x[u]);
+        }
+        // tail: fewer than U items left for this thread
+        for (; base < items; base += (uint32_t)BT) {
+            const uint32_t c = div_nvec(base, d.magic);
+            const uint32_t vr = base - c * (uint32_t)nvec;
+            double2 *a = reinterpret_cast<double2 *>(T + (int64_t)L[c] * ld) + vr;
+            rewrite(c, vr, a, *a);
+        }
+        // next Step 1 from the new row-0 entries; the barriers inside also
+        // order this pivot's writes before the next pivot's reads
+        batch_block_argmin<BT>(bestv, bestj, sv, si);
+        v = bestv;
+        q = bestj;
+    }
+    if (tid == 0) {
+        stp->status = status;
+        stp->pivots = s.pivots;
+        stp->cols_done = s.cols_done + cols_done;
+    }
+    __syncthreads();
+}
+
+// Resets the queue head; launched before every k_batch in the graph.
+static __global__ void k_batch_reset(int32_t *head) { *head = 0; }
+
+template <int BT, int U>
+__global__ __launch_bounds__(BT) void k_batch(const BatchDesc *__restrict__ desc, BatchState *__restrict__ state,
+                                              const int32_t *__restrict__ order, const int32_t *__restrict__ norder,
+                                              int32_t *__restrict__ head, int64_t budget) {
+    extern __shared__ double lds[];
+    __shared__ double sv[BT / 64];
+    __shared__ int32_t si[BT / 64];
+    __shared__ int32_t sint[BT / 64];
+    __shared__ int32_t s_idx;
+    const int32_t count = *norder;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(head, 1);
+        __syncthreads();
+        const int32_t idx = s_idx;
+        __syncthreads();
+        if (idx >= count) return;
+        const int32_t k = order[idx];
+        const BatchDesc d = desc[k];
+        if (d.scratch)
+            batch_solve_one<BT, U>(d, state + k, d.scratch, sv, si, sint, budget);
+        else
+            batch_solve_one<BT, U>(d, state + k, lds, sv, si, sint, budget);
+    }
+}
+
+// Initial rewrite list, positions, basis and state of one LP (grid-stride).
+static __global__ void k_batch_init_lp(BatchDesc d, BatchState *st, BatchState init) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t m = d.m, n = d.n;
+    if (t0 == 0) {
+        *st = init;
+        d.cols[n] = 0;
+        d.cols[n + 1] = n + m;
+    }
+    for (int64_t t = t0; t < (int64_t)n + m; t += stride) {
+        if (t < m) d.basis[t] = n + (int32_t)t;
+        if (t < n) d.cols[t] = (int32_t)t;
+        d.pos[t] = t < n ? (int32_t)t : -1;
+    }
+}
+
+// Finalization for every LP: out + off[k] receives x (n), y (m), objective.
+static __global__ __launch_bounds__(256) void k_batch_extract(const BatchDesc *__restrict__ desc,
+                                                       const int64_t *__restrict__ off, double *__restrict__ out) {
+    const BatchDesc d = desc[blockIdx.x];
+    double *o = out + off[blockIdx.x];
+    const int32_t m = d.m, n = d.n;
+    const int64_t W = (int64_t)n + m + 1;
+    for (int32_t j = threadIdx.x; j < n; j += blockDim.x) o[j] = 0.0;
+    __syncthreads();
+    for (int32_t i = 1 + threadIdx.x; i <= m; i += blockDim.x) {
+        const int32_t bv = d.basis[i - 1];
+        if (bv < n) o[bv] = d.T[(W - 1) * d.ld + i];
+        o[n + i - 1] = d.T[((int64_t)n + i - 1) * d.ld];
+    }
+    if (threadIdx.x == 0) o[n + m] = d.T[(W - 1) * d.ld];
+}
+
+}  // namespace lpgpu

@@ -17,7 +17,52 @@ __global__ void k_diag_arith(int64_t count, const double *__restrict__ a, const 
     fmav[k] = fma(a[k], b[k], c[k]);
 }
 
+// Grid-stride copy of 16-byte vectors.
+__global__ __launch_bounds__(256) void k_diag_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                   int64_t nvec) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvec; k += stride) dst[k] = src[k];
+}
+
 }  // namespace
+
+extern "C" int lp_diag_copy(int32_t device, size_t bytes, int32_t reps, double *ms) {
+    if (reps < 1 || bytes < 16) return set_error(LP_E_INVAL, "bytes must be >= 16 and reps >= 1");
+    int prev = 0;
+    LP_HIP_CHECK(hipGetDevice(&prev));
+    LP_HIP_CHECK(hipSetDevice(device));
+    const int64_t nvec = (int64_t)(bytes / 16);
+    double2 *src = nullptr, *dst = nullptr;
+    if (hipMalloc((void **)&src, nvec * 16) != hipSuccess || hipMalloc((void **)&dst, nvec * 16) != hipSuccess) {
+        if (src) (void)hipFree(src);
+        (void)hipSetDevice(prev);
+        return set_error(LP_E_NOMEM, "hipMalloc failed");
+    }
+    int rc = LP_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMemset(src, 0, nvec * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        rc = set_error(LP_E_DEVICE, "setup failed");
+    } else {
+        const unsigned blocks = 256u * 8u;
+        hipLaunchKernelGGL(k_diag_copy, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);  // warm-up
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_diag_copy, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);
+        (void)hipEventRecord(e1, nullptr);
+        float t = 0.f;
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            rc = set_error(LP_E_DEVICE, "copy kernel failed");
+        else if (ms)
+            *ms = t / reps;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(src);
+    (void)hipFree(dst);
+    (void)hipSetDevice(prev);
+    return rc;
+}
 
 extern "C" int lp_diag_arith(int32_t device, int64_t count, const double *a, const double *b, const double *c,
                              double *quot, double *fmav) {

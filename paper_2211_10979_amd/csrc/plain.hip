@@ -28,22 +28,26 @@ struct DeviceGuard {
 };
 
 struct UpdateConfig {
-    int block;  // threads per workgroup
-    int vpt;    // double2 vectors per thread kept in registers (0 = general form)
+    int block;      // threads per workgroup
+    int cols;       // listed columns per workgroup
+    int rv;         // row pairs (double2) per thread and column
+    int rowchunks;  // row chunks of block*rv pairs covering rows 0..m
 };
 
-// Smallest (block, VPT) whose block*VPT vectors cover the m+1 rows.
-UpdateConfig pick_update_config(int32_t m) {
+// Small m: one chunk of 64 or 128 pairs; otherwise 256 threads with `rv`
+// pairs each.
+UpdateConfig pick_update_config(int32_t m, int cols, int rv) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
-    if (nvec <= 64) return {64, 1};
-    if (nvec <= 128) return {128, 1};
-    if (nvec <= 256) return {256, 1};
-    if (nvec <= 512) return {256, 2};
-    if (nvec <= 1024) return {256, 4};
-    if (nvec <= 2048) return {256, 8};
-    if (nvec <= 4096) return {256, 16};
-    return {1024, 0};
+    if (nvec <= 128) {
+        const int block = nvec <= 64 ? 64 : 128;
+        return {block, cols, 1, 1};
+    }
+    const int64_t span = 256 * (int64_t)rv;
+    return {256, cols, rv, (int)((nvec + span - 1) / span)};
 }
+
+bool valid_cols(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
+bool valid_rv(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 }  // namespace
 
@@ -61,16 +65,26 @@ struct lp_ctx {
     int32_t *basis = nullptr;
     int32_t *log_r = nullptr, *log_q = nullptr;
     double *out = nullptr;
+    int32_t *cols = nullptr;  // rewrite list (n+2)
+    int32_t *pos = nullptr;   // position of each nonbasic column in the list (n+m)
+    double *Rl = nullptr;     // normalised pivot row by list position (n+2)
     DevState *host_st = nullptr;  // pinned, two slots for the pipelined status read-back
     double eps_d = 1e-9, eps_p = 1e-9;
     int64_t max_pivots = 0, log_cap = 0;
-    int cols_per_block = 8, nparts = 0;
+    int nparts = 0;
     UpdateConfig ucfg{};
+    unsigned long long *cols_done = nullptr;  // device counter of rewritten columns
     int chunk = 8;
     bool use_graph = true;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    bool timing = false;
+    // Two captured chunk graphs used alternately, so that the events of one
+    // can be read while the other runs.
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> ev_upd[2];  // timing mode: before/after each update kernel of a chunk
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
+    double update_ms = 0.0;
+    int64_t update_launches = 0;
     int64_t pivots_host = 0;
     int32_t status_host = LP_RUNNING;
     bool ran = false;
@@ -83,8 +97,13 @@ void free_ctx(lp_ctx *h) {
     if (!h) return;
     DeviceGuard g(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int k = 0; k < 2; ++k) {
+        if (h->gexec[k]) (void)hipGraphExecDestroy(h->gexec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        for (auto e : h->ev_upd[k])
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (h->cols_done) (void)hipFree(h->cols_done);
     if (h->own_T && h->T) (void)hipFree(h->T);
     if (h->F) (void)hipFree(h->F);
     if (h->parts) (void)hipFree(h->parts);
@@ -93,6 +112,9 @@ void free_ctx(lp_ctx *h) {
     if (h->log_r) (void)hipFree(h->log_r);
     if (h->log_q) (void)hipFree(h->log_q);
     if (h->out) (void)hipFree(h->out);
+    if (h->cols) (void)hipFree(h->cols);
+    if (h->pos) (void)hipFree(h->pos);
+    if (h->Rl) (void)hipFree(h->Rl);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -105,8 +127,10 @@ void free_ctx(lp_ctx *h) {
 int validate_opts(const lp_options &o) {
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
-    if (o.cols_per_block < 0 || o.cols_per_block > kMaxColsPerBlock)
-        return set_error(LP_E_INVAL, "cols_per_block must be in [0, 64]");
+    if (o.cols_per_block != 0 && !valid_cols(o.cols_per_block))
+        return set_error(LP_E_INVAL, "cols_per_block must be 0 (auto) or one of 1, 2, 4, 8, 16");
+    if (o.rows_per_thread != 0 && !valid_rv(o.rows_per_thread))
+        return set_error(LP_E_INVAL, "rows_per_thread must be 0 (auto) or one of 1, 2, 4, 8");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
     return LP_OK;
 }
@@ -133,11 +157,12 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->eps_p = o.eps_pivot;
     h->max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m + n);
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
-    h->cols_per_block = o.cols_per_block > 0 ? o.cols_per_block : 8;
-    h->nparts = (int)((h->W + h->cols_per_block - 1) / h->cols_per_block);
-    h->ucfg = pick_update_config(m);
+    h->ucfg = pick_update_config(m, o.cols_per_block > 0 ? o.cols_per_block : 4,
+                                 o.rows_per_thread > 0 ? o.rows_per_thread : 1);
+    h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
     h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
     h->use_graph = o.use_graph != 0;
+    h->timing = o.time_kernels != 0;
 
     auto fail = [&](int rc) {
         free_ctx(h);
@@ -178,6 +203,10 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->log_q, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
     }
     if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->cols_done, sizeof(unsigned long long))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->cols, ((size_t)n + 2) * sizeof(int32_t))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)n + 2) * sizeof(double))) return fail(rc);
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
@@ -186,6 +215,13 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_slot[1], hipEventDisableTiming) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
+    if (h->timing) {
+        for (int k = 0; k < 2; ++k) {
+            h->ev_upd[k].assign(2 * (size_t)h->chunk, nullptr);
+            for (auto &e : h->ev_upd[k])
+                if (hipEventCreate(&e) != hipSuccess) return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
+        }
+    }
     *out = h;
     return LP_OK;
 }
@@ -210,9 +246,9 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.eps_p = h->eps_p;
     init.fresh = 1;
     init.nparts = h->nparts;
-    const int64_t ninit = std::max<int64_t>(std::max<int64_t>(m, ld), 1);
+    const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
     hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init, h->basis,
-                       m, n, h->F, ld);
+                       m, n, h->F, ld, h->cols, h->pos, h->cols_done);
     LP_HIP_CHECK(hipGetLastError());
     h->pivots_host = 0;
     h->status_host = LP_RUNNING;
@@ -220,44 +256,77 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     return LP_OK;
 }
 
-void launch_pivot(lp_ctx *h) {
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts, h->st, h->F,
-                       h->basis, h->log_r, h->log_q);
-    const dim3 grid((unsigned)h->nparts), block((unsigned)h->ucfg.block);
-#define LP_UPD(B, V)                                                                                   \
-    if (h->ucfg.block == B && h->ucfg.vpt == V) {                                                      \
-        hipLaunchKernelGGL((k_update<B, V>), grid, block, 0, h->stream, h->T, h->ld, h->m, h->n,       \
-                           h->cols_per_block, h->F, h->st, h->parts);                                  \
+void launch_update(lp_ctx *h) {
+    const UpdateConfig &u = h->ucfg;
+    const dim3 grid((unsigned)((int64_t)u.rowchunks * h->nparts)), block((unsigned)u.block);
+#define LP_UPD(B, C, V)                                                                                \
+    if (u.block == B && u.cols == C && u.rv == V) {                                                    \
+        hipLaunchKernelGGL((k_update<B, C, V>), grid, block, 0, h->stream, h->T, h->ld, h->m, h->n,    \
+                           u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);                        \
         return;                                                                                        \
     }
-    LP_UPD(64, 1)
-    LP_UPD(128, 1)
-    LP_UPD(256, 1)
-    LP_UPD(256, 2)
-    LP_UPD(256, 4)
-    LP_UPD(256, 8)
-    LP_UPD(256, 16)
-    LP_UPD(1024, 0)
+#define LP_UPD_C(C) LP_UPD(64, C, 1) LP_UPD(128, C, 1) LP_UPD(256, C, 1) LP_UPD(256, C, 2) \
+    LP_UPD(256, C, 4) LP_UPD(256, C, 8)
+    LP_UPD_C(1)
+    LP_UPD_C(2)
+    LP_UPD_C(4)
+    LP_UPD_C(8)
+    LP_UPD_C(16)
+#undef LP_UPD_C
 #undef LP_UPD
 }
 
-int launch_chunk(lp_ctx *h) {
-    if (!h->use_graph) {
-        for (int k = 0; k < h->chunk; ++k) launch_pivot(h);
-        LP_HIP_CHECK(hipGetLastError());
-        return LP_OK;
+// One chunk: `chunk` pivots of (select, update), with event records around
+// each update kernel in timing mode.
+int enqueue_chunk(lp_ctx *h, int slot) {
+    for (int k = 0; k < h->chunk; ++k) {
+        hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts, h->st,
+                           h->F, h->basis, h->log_r, h->log_q, h->cols, h->pos, h->Rl, h->cols_done);
+        if (h->timing) LP_HIP_CHECK(hipEventRecord(h->ev_upd[slot][2 * k], h->stream));
+        launch_update(h);
+        if (h->timing) LP_HIP_CHECK(hipEventRecord(h->ev_upd[slot][2 * k + 1], h->stream));
     }
-    if (!h->gexec) {
-        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    LP_HIP_CHECK(hipGetLastError());
+    return LP_OK;
+}
+
+// Captures the two chunk graphs (kernel arguments are fixed per context).
+// Timing mode launches directly instead: HIP cannot report elapsed time
+// between events recorded by a graph.
+int capture_graphs(lp_ctx *h) {
+    if (!h->use_graph || h->timing) return LP_OK;
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (int slot = 0; slot < 2; ++slot) {
         LP_HIP_CHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < h->chunk; ++k) launch_pivot(h);
+        const int rc = enqueue_chunk(h, slot);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
         if (e != hipSuccess) return set_error(LP_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        h->graph = graph;
-        LP_HIP_CHECK(hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0));
+        h->graph[slot] = graph;
+        LP_HIP_CHECK(hipGraphInstantiate(&h->gexec[slot], graph, nullptr, nullptr, 0));
     }
-    LP_HIP_CHECK(hipGraphLaunch(h->gexec, h->stream));
+    return LP_OK;
+}
+
+int launch_chunk(lp_ctx *h, int slot) {
+    if (!h->gexec[slot]) return enqueue_chunk(h, slot);
+    LP_HIP_CHECK(hipGraphLaunch(h->gexec[slot], h->stream));
+    return LP_OK;
+}
+
+// Adds the update-kernel times of the first `active` pivots of a finished chunk.
+int harvest_timing(lp_ctx *h, int slot, int64_t active) {
+    if (!h->timing) return LP_OK;
+    for (int64_t k = 0; k < active && k < h->chunk; ++k) {
+        float ms = 0.f;
+        LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]));
+        h->update_ms += ms;
+        h->update_launches += 1;
+    }
     return LP_OK;
 }
 
@@ -266,19 +335,24 @@ int launch_chunk(lp_ctx *h) {
 // chunk k is read back, so the device never waits for the host.
 int run_until(lp_ctx *h, int64_t stop_at) {
     DeviceGuard g(h->device);
+    h->update_ms = 0.0;
+    h->update_launches = 0;
     hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
-    if (int rc = launch_chunk(h)) return rc;
+    int64_t done_before = h->pivots_host;
+    if (int rc = launch_chunk(h, 0)) return rc;
     LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipEventRecord(h->ev_slot[0], h->stream));
     for (;;) {
         const int next = slot ^ 1;
-        if (int rc = launch_chunk(h)) return rc;
+        if (int rc = launch_chunk(h, next)) return rc;
         LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[next], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
         LP_HIP_CHECK(hipEventRecord(h->ev_slot[next], h->stream));
         LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
         const DevState s = h->host_st[slot];
+        if (int rc = harvest_timing(h, slot, s.pivots - done_before)) return rc;
+        done_before = s.pivots;
         if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
         slot = next;
     }
@@ -286,6 +360,8 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
     DevState s;
     LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    // the chunk queued last may still have applied pivots
+    if (int rc = harvest_timing(h, slot ^ 1, s.pivots - done_before)) return rc;
     h->pivots_host = s.pivots;
     h->status_host = s.status;
     float ms = 0.f;
@@ -322,6 +398,10 @@ int lp_create_device(lp_ctx **out, int32_t m, int32_t n, const double *dA, const
         free_ctx(h);
         return set_error(LP_E_DEVICE, std::string("build: ") + hipGetErrorString(e));
     }
+    if (int rc = capture_graphs(h)) {
+        free_ctx(h);
+        return rc;
+    }
     *out = h;
     return LP_OK;
 }
@@ -354,6 +434,7 @@ int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double 
     if (!rc) rc = enqueue_build(h, stage, stage + na, stage + na + m);
     if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = set_error(LP_E_DEVICE, "build failed");
     (void)hipFree(stage);
+    if (!rc) rc = capture_graphs(h);
     if (rc) {
         free_ctx(h);
         return rc;
@@ -451,6 +532,22 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
     info->ld = h->ld;
     info->tableau_bytes = lp_tableau_bytes(h->m, h->n);
     info->tableau = h->T;
+    return LP_OK;
+}
+
+int lp_get_timing(const lp_ctx *h, lp_timing *t) {
+    if (!h || !t) return set_error(LP_E_INVAL, "NULL argument");
+    DeviceGuard g(h->device);
+    unsigned long long cols = 0;
+    DevState s;
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    LP_HIP_CHECK(hipMemcpy(&cols, h->cols_done, sizeof(cols), hipMemcpyDeviceToHost));
+    LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    t->solve_ms = h->last_ms;
+    t->update_ms = h->update_ms;
+    t->update_launches = h->update_launches;
+    t->pivots = s.pivots;
+    t->updated_columns = (int64_t)cols;
     return LP_OK;
 }
 

@@ -17,12 +17,11 @@
 namespace lpgpu {
 
 constexpr int kBuildTile = 64;
-constexpr int kMaxColsPerBlock = 64;
 
 // Initialization Step, structural part: column j < n of T gets -c_j in row 0
 // and column j of A in rows 1..m (Table I); padding rows are zero. A is
 // row-major, so each 64x64 tile is transposed through LDS.
-__global__ __launch_bounds__(256) void k_build_struct(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+static __global__ __launch_bounds__(256) void k_build_struct(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                       const double *__restrict__ A, const double *__restrict__ c) {
     __shared__ double tile[kBuildTile][kBuildTile + 1];
     const int64_t j0 = (int64_t)blockIdx.x * kBuildTile;
@@ -49,7 +48,7 @@ __global__ __launch_bounds__(256) void k_build_struct(double *__restrict__ T, in
 }
 
 // Initialization Step, slack identity and right-hand side (columns n..W-1).
-__global__ __launch_bounds__(256) void k_build_slack(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+static __global__ __launch_bounds__(256) void k_build_slack(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                      const double *__restrict__ b) {
     const int64_t half = ld / 2;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,24 +66,48 @@ __global__ __launch_bounds__(256) void k_build_slack(double *__restrict__ T, int
     reinterpret_cast<double2 *>(T + (n + s) * ld)[v] = y;
 }
 
-// Solver state, slack basis and a zeroed pivot-column buffer.
-__global__ void k_init(DevState *st, DevState init, int32_t *__restrict__ basis, int32_t m, int32_t n,
-                       double *__restrict__ F, int64_t ld) {
+// Solver state, slack basis, a zeroed pivot-column buffer, the list of
+// columns Step 3 rewrites and the work counter.
+//   cols[0..n)  the nonbasic columns (any order); cols[n] the entering column
+//               of the current pivot; cols[n+1] the right-hand side W-1;
+//   pos[j]      position of column j in cols[0..n), or -1 when j is basic.
+static __global__ void k_init(DevState *st, DevState init, int32_t *__restrict__ basis, int32_t m, int32_t n,
+                       double *__restrict__ F, int64_t ld, int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                       unsigned long long *__restrict__ cols_done) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0) *st = init;
+    if (idx == 0) {
+        *st = init;
+        *cols_done = 0;
+        cols[n] = 0;
+        cols[n + 1] = n + m;
+    }
     if (idx < m) basis[idx] = n + (int32_t)idx;
     if (idx < ld) F[idx] = 0.0;
+    if (idx < n) cols[idx] = (int32_t)idx;
+    if (idx < (int64_t)n + m) pos[idx] = idx < n ? (int32_t)idx : -1;
 }
 
-__global__ void k_set_stop(DevState *st, int64_t stop_at) { st->stop_at = stop_at; }
+static __global__ void k_set_stop(DevState *st, int64_t stop_at) { st->stop_at = stop_at; }
 
-// Steps 1 and 2 for the next pivot; one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_select(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+// Steps 1 and 2 for the next pivot, and the inputs of Step 3; one workgroup
+// of 1024 threads.
+//   Step 1   final stage of the argmin over the update's per-group partials
+//            (a scan of row 0 before the first pivot);
+//   Step 2   ratio test over column q;
+//   Step 3   inputs: F = column q, the rewrite list with q and the leaving
+//            column swapped, and R (normalised pivot row) by list position.
+// Basic columns other than the leaving one are exact unit vectors with a zero
+// in row r and in row 0, so leaving them out of R, of the rewrite and of the
+// Step 1 scan changes no value and no decision.
+static __global__ __launch_bounds__(1024) void k_select(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                 const ArgMin *__restrict__ parts, DevState *__restrict__ st,
                                                 double *__restrict__ F, int32_t *__restrict__ basis,
-                                                int32_t *__restrict__ log_r, int32_t *__restrict__ log_q) {
+                                                int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
+                                                int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                                                double *__restrict__ Rl, unsigned long long *__restrict__ cols_done) {
     __shared__ double sv[16];
     __shared__ int32_t si[16];
+    __shared__ int32_t scount[16];
     const int tid = threadIdx.x, nt = blockDim.x;
     const DevState s = *st;
     if (s.status != LP_RUNNING || s.pivots >= s.stop_at) {
@@ -152,12 +175,33 @@ __global__ __launch_bounds__(1024) void k_select(const double *__restrict__ T, i
         return;
     }
 
-    // Snapshot of the pivot column for the elimination.
+    // Inputs of Step 3. The leaving column takes q's place in the list.
+    const double p = colq[r];
+    const int32_t leave = basis[r - 1];
+    const int32_t pq = pos[q];
     for (int32_t i = tid; i <= m; i += nt) F[i] = colq[i];
+    int32_t nz = 0;
+    for (int32_t t = tid; t < n + 2; t += nt) {
+        const int32_t j = t == pq ? leave : (t == n ? q : cols[t]);
+        const double R = T[(int64_t)j * ld + r] / p;
+        Rl[t] = R;
+        nz += R != 0.0;
+    }
+    // count of rewritten columns (nonzero R), summed over the block
+    for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
+    if ((tid & 63) == 0) scount[tid >> 6] = nz;
+    __syncthreads();  // also orders every read of cols/pos above before the writes below
     if (tid == 0) {
+        int32_t tot = 0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) tot += scount[w];
+        *cols_done += (unsigned long long)tot;
+        cols[pq] = leave;
+        pos[leave] = pq;
+        pos[q] = -1;
+        cols[n] = q;
         st->r = r;
         st->q = q;
-        st->p = colq[r];
+        st->p = p;
         basis[r - 1] = q;
         if (s.pivots < s.log_cap) {
             log_r[s.pivots] = r;
@@ -169,97 +213,104 @@ __global__ __launch_bounds__(1024) void k_select(const double *__restrict__ T, i
     }
 }
 
-// Step 3 on a tile of whole columns, plus the first stage of the next Step 1.
-// Thread t owns the row pairs {2v, 2v+1}, v = t + k*blockDim.x, k < VPT, and
-// keeps their F values in registers across the tile's columns. VPT = 0 is
-// the general form for any m, which re-reads F for every column. The launch
-// must use exactly B threads.
-template <int B, int VPT>
+// Step 3 as a streaming kernel over (row chunk, column group) tiles. A row
+// chunk is B*RV row pairs (double2): thread t owns pairs v_k = base + k*B + t,
+// k < RV, of each of the group's C listed columns. Every entry is read once
+// and rewritten once:
+//     T[i][j] = R_j                        for i = r,
+//     T[i][j] = fma(-F_i, R_j, T[i][j])    otherwise.
+// The row-chunk-0 workgroup of each column group also reduces its columns'
+// new row-0 entries to one (value, column) partial for the next Step 1.
+template <int B, int C, int RV>
 __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                 int32_t cols_per_block, const double *__restrict__ F,
-                                                 const DevState *__restrict__ st, ArgMin *__restrict__ parts) {
-    __shared__ double sR[kMaxColsPerBlock];
+                                              int32_t rowchunks, const int32_t *__restrict__ cols,
+                                              const double *__restrict__ Rl, const double *__restrict__ F,
+                                              const DevState *__restrict__ st, ArgMin *__restrict__ parts) {
     if (!st->go) return;
     const int32_t r = st->r;
-    const double p = st->p;
-    const int64_t W = (int64_t)n + m + 1;
-    const int64_t j0 = (int64_t)blockIdx.x * cols_per_block;
-    const int jn = (int)min<int64_t>(cols_per_block, W - j0);
-    const int tid = threadIdx.x;
-    constexpr int nt = B;
-
-    // Normalised pivot row for this tile (Step 3) and the tile's new row-0
-    // entries, reduced to one (value, column) partial for the next Step 1.
-    // Row 0 is never the pivot row, so its new entry is fma(-F_0, R_j, T_0j).
-    if (tid < 64) {
-        double val = __builtin_inf();
-        int32_t idx = kNoIndex;
-        if (tid < jn) {
-            const int64_t j = j0 + tid;
-            const double *col = T + j * ld;
-            const double Rj = col[r] / p;
-            const double t0 = col[0];
-            sR[tid] = Rj;
-            const double new0 = (Rj == 0.0) ? t0 : fma(-F[0], Rj, t0);
-            if (j < (int64_t)n + m) {
-                val = new0;
-                idx = (int32_t)j;
-            }
-        }
-        wave_argmin(val, idx);
-        if (tid == 0) parts[blockIdx.x] = ArgMin{val, idx};
-    }
-    __syncthreads();
-
-    const int nvec = (m + 2) / 2;  // double2 vectors covering rows 0..m
+    const int32_t ncols = n + 2;
+    const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
+    const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
+    const int32_t c0 = g * C;
+    const int32_t nvec = (m + 2) / 2;
+    const int32_t base = rc * B * RV + (int32_t)threadIdx.x;
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
-    if constexpr (VPT > 0) {
-        double2 f[VPT];
+    const bool row0 = rc == 0 && threadIdx.x == 0;  // holds row 0, never the pivot row
+
+    if (c0 + C <= ncols && (rc + 1) * B * RV <= nvec) {
+        // Full tile: straight-line code, so that all C*RV loads are in flight
+        // before the first store and no wait covers a store.
+        double Rj[C];
+        double2 *col[C];
+        double2 f[RV];
+        double2 x[C][RV];
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-            const int v = tid + k * nt;
-            f[k] = v < nvec ? F2[v] : double2{0.0, 0.0};
+        for (int k = 0; k < RV; ++k) f[k] = F2[base + k * B];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            Rj[c] = Rl[c0 + c];
+            col[c] = reinterpret_cast<double2 *>(T + (int64_t)cols[c0 + c] * ld);
         }
-        for (int jj = 0; jj < jn; ++jj) {
-            const double Rj = sR[jj];
-            if (Rj == 0.0) continue;  // column unchanged up to the sign of zeros
-            double2 *col = reinterpret_cast<double2 *>(T + (j0 + jj) * ld);
-            double2 x[VPT];
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) {
-                const int v = tid + k * nt;
-                if (v < nvec) x[k] = col[v];
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int k = 0; k < RV; ++k) x[c][k] = col[c][base + k * B];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int k = 0; k < RV; ++k) {
+                const int32_t v = base + k * B;
+                double2 y;
+                y.x = (2 * v == r) ? Rj[c] : fma(-f[k].x, Rj[c], x[c][k].x);
+                y.y = (2 * v + 1 == r) ? Rj[c] : fma(-f[k].y, Rj[c], x[c][k].y);
+                col[c][v] = y;
             }
+        if (row0) {
+            double val = __builtin_inf();
+            int32_t idx = kNoIndex;
 #pragma unroll
-            for (int k = 0; k < VPT; ++k) {
-                const int v = tid + k * nt;
-                if (v < nvec) {
-                    double2 y;
-                    y.x = (2 * v == r) ? Rj : fma(-f[k].x, Rj, x[k].x);
-                    y.y = (2 * v + 1 == r) ? Rj : fma(-f[k].y, Rj, x[k].y);
-                    col[v] = y;
+            for (int c = 0; c < C; ++c) {
+                const int32_t j = cols[c0 + c];
+                const double y0 = fma(-f[0].x, Rj[c], x[c][0].x);
+                if (j != n + m && lex_less(y0, j, val, idx)) {
+                    val = y0;
+                    idx = j;
+                }
+            }
+            parts[g] = ArgMin{val, idx};
+        }
+        return;
+    }
+
+    // Edge tile: the last column group or the last row chunk.
+    const int cn = min(C, ncols - c0);
+    double val = __builtin_inf();
+    int32_t idx = kNoIndex;
+    for (int c = 0; c < cn; ++c) {
+        const double R = Rl[c0 + c];
+        const int32_t j = cols[c0 + c];
+        double2 *cp = reinterpret_cast<double2 *>(T + (int64_t)j * ld);
+        for (int k = 0; k < RV; ++k) {
+            const int32_t v = base + k * B;
+            if (v < nvec) {
+                const double2 f = F2[v];
+                const double2 xx = cp[v];
+                double2 y;
+                y.x = (2 * v == r) ? R : fma(-f.x, R, xx.x);
+                y.y = (2 * v + 1 == r) ? R : fma(-f.y, R, xx.y);
+                cp[v] = y;
+                if (row0 && k == 0 && j != n + m && lex_less(y.x, j, val, idx)) {
+                    val = y.x;
+                    idx = j;
                 }
             }
         }
-    } else {
-        for (int jj = 0; jj < jn; ++jj) {
-            const double Rj = sR[jj];
-            if (Rj == 0.0) continue;
-            double2 *col = reinterpret_cast<double2 *>(T + (j0 + jj) * ld);
-            for (int v = tid; v < nvec; v += nt) {
-                const double2 f = F2[v];
-                const double2 x = col[v];
-                double2 y;
-                y.x = (2 * v == r) ? Rj : fma(-f.x, Rj, x.x);
-                y.y = (2 * v + 1 == r) ? Rj : fma(-f.y, Rj, x.y);
-                col[v] = y;
-            }
-        }
     }
+    if (row0) parts[g] = ArgMin{val, idx};
 }
 
 // Finalization: x (n), y (m) and the objective into out[0 .. n+m].
-__global__ __launch_bounds__(1024) void k_extract(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+static __global__ __launch_bounds__(1024) void k_extract(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                  const int32_t *__restrict__ basis, double *__restrict__ out) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t W = (int64_t)n + m + 1;

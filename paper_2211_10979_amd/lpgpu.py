@@ -48,6 +48,10 @@ class lp_options(ctypes.Structure):
         ("chunk_pivots", ctypes.c_int32),
         ("cols_per_block", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("time_kernels", ctypes.c_int32),
+        ("rows_per_thread", ctypes.c_int32),
+        ("batch_block", ctypes.c_int32),
+        ("batch_unroll", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -70,6 +74,16 @@ class lp_info(ctypes.Structure):
         ("ld", ctypes.c_int64),
         ("tableau_bytes", ctypes.c_size_t),
         ("tableau", ctypes.c_void_p),
+    ]
+
+
+class lp_timing(ctypes.Structure):
+    _fields_ = [
+        ("solve_ms", ctypes.c_double),
+        ("update_ms", ctypes.c_double),
+        ("update_launches", ctypes.c_int64),
+        ("pivots", ctypes.c_int64),
+        ("updated_columns", ctypes.c_int64),
     ]
 
 
@@ -113,14 +127,19 @@ SIGNATURES = {
     "lp_get_tableau": (ctypes.c_int, [_P, _D]),
     "lp_get_basis": (ctypes.c_int, [_P, _I32]),
     "lp_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lp_info)]),
+    "lp_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(lp_timing)]),
     "lp_destroy": (None, [_P]),
     "lp_diag_arith": (ctypes.c_int, [ctypes.c_int32, _I64, _D, _D, _D, _D, _D]),
+    "lp_diag_copy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, _D]),
     "lp_batch_create": (ctypes.c_int, [_PP, ctypes.c_int32, _I32, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                        ctypes.POINTER(_D), _OPT]),
     "lp_batch_solve": (ctypes.c_int, [_P]),
     "lp_batch_get_solution": (ctypes.c_int, [_P, ctypes.c_int32, _RES, _D, _D]),
     "lp_batch_get_pivots": (ctypes.c_int, [_P, ctypes.c_int32, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_int64)]),
     "lp_batch_solve_ms": (ctypes.c_double, [_P]),
+    "lp_batch_reset": (ctypes.c_int, [_P]),
+    "lp_batch_get_shape": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "lp_batch_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _D]),
     "lp_batch_destroy": (None, [_P]),
     "lp_server_create": (ctypes.c_int, [_PP, ctypes.c_size_t, ctypes.c_int32, _OPT]),
     "lp_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _D, _D, _D,
@@ -242,6 +261,12 @@ def lp_get_info(h) -> lp_info:
     return info
 
 
+def lp_get_timing(h) -> dict:
+    t = lp_timing()
+    _check(library().lp_get_timing(h, ctypes.byref(t)), "lp_get_timing")
+    return {name: getattr(t, name) for name, _ in lp_timing._fields_}
+
+
 def lp_get_solution(h, want_x=True, want_y=True):
     """Returns (result dict, x or None, y or None)."""
     info = lp_get_info(h)
@@ -285,6 +310,13 @@ def lp_get_basis(h):
 def lp_destroy(h):
     if h:
         library().lp_destroy(h)
+
+
+def lp_diag_copy(nbytes, reps=10, device=0) -> float:
+    """Average device time (ms) of one plain copy of `nbytes` bytes."""
+    ms = ctypes.c_double()
+    _check(library().lp_diag_copy(device, int(nbytes), int(reps), ctypes.byref(ms)), "lp_diag_copy")
+    return ms.value
 
 
 def lp_diag_arith(a, b, c, device=0):
@@ -342,6 +374,23 @@ def lp_batch_get_pivots(h, k):
     return rows[:kk].copy(), cols[:kk].copy()
 
 
+def lp_batch_reset(h):
+    _check(library().lp_batch_reset(h), "lp_batch_reset")
+
+
+def lp_batch_get_shape(h):
+    b, u, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(library().lp_batch_get_shape(h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(g)), "lp_batch_get_shape")
+    return dict(block=b.value, unroll=u.value, grid_per_cu=g.value)
+
+
+def lp_batch_autotune(h, cache_path=None, trials=2) -> float:
+    ms = ctypes.c_double()
+    path = cache_path.encode() if cache_path else None
+    _check(library().lp_batch_autotune(h, path, int(trials), ctypes.byref(ms)), "lp_batch_autotune")
+    return ms.value
+
+
 def lp_batch_destroy(h):
     if h:
         library().lp_batch_destroy(h)
@@ -386,13 +435,16 @@ def lp_server_wait(h, ticket, m, n):
     return _res_dict(res), x, y
 
 
-def lp_server_get_pivots(h, ticket, cap=1 << 20):
+def lp_server_get_pivots(h, ticket):
+    """Pivot log of a finished, uncollected request (LPError LP_E_PENDING before)."""
     count = ctypes.c_int64()
-    rows = np.empty(cap, dtype=np.int32)
-    cols = np.empty(cap, dtype=np.int32)
-    _check(library().lp_server_get_pivots(h, ticket, _ip(rows), _ip(cols), cap, ctypes.byref(count)),
+    _check(library().lp_server_get_pivots(h, ticket, None, None, 0, ctypes.byref(count)), "lp_server_get_pivots")
+    k = count.value
+    rows = np.empty(max(k, 1), dtype=np.int32)
+    cols = np.empty(max(k, 1), dtype=np.int32)
+    _check(library().lp_server_get_pivots(h, ticket, _ip(rows), _ip(cols), k, ctypes.byref(count)),
            "lp_server_get_pivots")
-    k = min(cap, count.value)
+    k = min(k, count.value)
     return rows[:k].copy(), cols[:k].copy()
 
 

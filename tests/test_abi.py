@@ -1,0 +1,84 @@
+"""The C ABI without a GPU: the library loads and exports every function that
+include/lpgpu.h declares, the binding knows them all, and the host-only
+entry points behave as documented."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpgpu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(lp_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lpgpu():
+    from paper_2211_10979_amd import lpgpu as mod
+
+    if not os.path.exists(mod.LIB_PATH):
+        pytest.skip("liblpgpu.so not built")
+    return mod
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lp_create", "lp_solve", "lp_get_solution", "lp_get_pivots", "lp_destroy", "lp_batch_create",
+                 "lp_batch_solve", "lp_server_create", "lp_server_submit", "lp_server_poll"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lpgpu):
+    lib = ctypes.CDLL(lpgpu.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+def test_binding_covers_the_header(lpgpu):
+    assert set(declared_functions()) <= set(lpgpu.SIGNATURES), set(declared_functions()) - set(lpgpu.SIGNATURES)
+
+
+def test_host_only_entry_points(lpgpu):
+    lib = lpgpu.library()
+    assert b"lpgpu" in lib.lp_version()
+    assert lib.lp_error_string(lpgpu.LP_E_NEG_RHS)
+    assert lib.lp_error_string(12345) == b"unknown code"
+    o = lpgpu.lp_options_default()
+    assert o.eps_dual == 1e-9 and o.eps_pivot == 1e-9 and o.record_pivots == 1 and o.use_graph == 1
+    assert lib.lp_options_default(None) == lpgpu.LP_E_INVAL
+    # tableau bytes: ld = m+1 rounded up to 16 doubles, W = n+m+1 columns
+    assert lpgpu.lp_tableau_bytes(8000, 8000) == 8016 * 16001 * 8
+    assert lpgpu.lp_tableau_bytes(15, 3) == 16 * 19 * 8
+    assert lpgpu.lp_tableau_bytes(16, 3) == 32 * 20 * 8
+    assert lpgpu.lp_tableau_bytes(0, 3) == 0
+
+
+def test_null_arguments_are_rejected_without_a_device(lpgpu):
+    lib = lpgpu.library()
+    assert lib.lp_create(None, 1, 1, None, None, None, None) == lpgpu.LP_E_INVAL
+    h = ctypes.c_void_p()
+    assert lib.lp_create(ctypes.byref(h), 0, 1, None, None, None, None) == lpgpu.LP_E_INVAL
+    assert lib.lp_solve(None) == lpgpu.LP_E_INVAL
+    assert lib.lp_get_solution(None, None, None, None) == lpgpu.LP_E_INVAL
+    lib.lp_destroy(None)  # NULL-safe
+    assert lpgpu.lp_last_error() if hasattr(lpgpu, "lp_last_error") else True
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle is a separate C file built by gcc; the HIP sources never
+    include or name it, and it never includes them."""
+    csrc = os.path.join(ROOT, "paper_2211_10979_amd", "csrc")
+    for f in os.listdir(csrc):
+        text = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in text.lower(), f
+    otext = open(os.path.join(ROOT, "oracle", "tableau_simplex.c")).read()
+    assert "#include \"" not in otext and "lpgpu" not in otext
+    pytext = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    assert "paper_2211_10979_amd" not in pytext

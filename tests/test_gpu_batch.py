@@ -1,0 +1,163 @@
+"""GPU parity of the batched solver: every LP of a batch follows exactly the
+pivot sequence of the CPU oracle (and of the single-LP solver), whatever the
+kernel shape and the mix of sizes and outcomes."""
+
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_10979_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+lpgpu = pytest.importorskip("paper_2211_10979_amd.lpgpu")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_lps(seed, count, lo=1, hi=130):
+    """Uneven sizes and every outcome: optimal, unbounded, no pivot."""
+    rng = np.random.default_rng(seed)
+    lps = []
+    for k in range(count):
+        m, n = int(rng.integers(lo, hi + 1)), int(rng.integers(lo, hi + 1))
+        kind = k % 5
+        if kind == 0:
+            lp = lpgen.dense_lp(seed, m, n, k=k)
+            A, b, c = lp.A, lp.b, lp.c
+        else:
+            A = rng.integers(1, 10, size=(m, n)).astype(float)
+            if kind in (1, 2):
+                A *= rng.choice([-1.0, 1.0], size=(m, n), p=[0.3, 0.7])
+            b = rng.integers(1, 10, size=m).astype(float)
+            c = rng.integers(1, 10, size=n).astype(float)
+            if kind == 3:
+                c = -c  # optimal at the origin: no pivot
+        lps.append((A, b, c))
+    return lps
+
+
+def check_batch(h, lps):
+    for k, (A, b, c) in enumerate(lps):
+        m, n = A.shape
+        res, x, y = lpgpu.lp_batch_get_solution(h, k, m, n)
+        rows, cols = lpgpu.lp_batch_get_pivots(h, k)
+        o = oracle.solve(A, b, c)
+        assert res["status"] == o["status"], k
+        assert res["pivots"] == o["pivots"], k
+        assert rows.tolist() == o["rows"].tolist() and cols.tolist() == o["cols"].tolist(), k
+        assert np.array_equal(x, o["x"]) and np.array_equal(y, o["y"]), k
+        assert abs(res["objective"] - o["objective"]) <= 1e-9 * max(1.0, abs(o["objective"])), k
+        if o["status"] == oracle.OPTIMAL:
+            assert oracle.certificates(A, b, c, x, y, res["objective"])["ok"], k
+
+
+def test_batch_mixed_sizes_and_outcomes():
+    lps = mixed_lps(3, 80)
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_solve(h)
+        check_batch(h, lps)
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_batch_workload_512():
+    """The 512-LP workload: m, n uniform on [32, 512], generator LPs."""
+    sizes = lpgen.batch_sizes(lpgen.BATCH_SEED, 512)
+    lps = [(lp.A, lp.b, lp.c) for lp in (lpgen.dense_lp(lpgen.BATCH_SEED, m, n, k=k)
+                                         for k, (m, n) in enumerate(sizes))]
+    say("batch of 512: create")
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_solve(h)
+        say("batch of 512 solved in", lpgpu.lp_batch_solve_ms(h), "ms")
+        check_batch(h, lps)
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+@pytest.mark.parametrize("block,unroll", [(256, 1), (256, 2), (256, 4), (256, 8), (512, 1), (512, 2), (512, 4),
+                                          (1024, 1), (1024, 2), (1024, 4)])
+def test_every_kernel_shape_gives_the_same_pivots(block, unroll):
+    lps = mixed_lps(11, 30, 1, 300)
+    h = lpgpu.lp_batch_create(lps, batch_block=block, batch_unroll=unroll)
+    try:
+        assert lpgpu.lp_batch_get_shape(h)["block"] == block
+        lpgpu.lp_batch_solve(h)
+        check_batch(h, lps)
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_batch_equals_solo_solver_bitwise():
+    lps = mixed_lps(5, 12, 100, 400)
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_solve(h)
+        for k, (A, b, c) in enumerate(lps):
+            g = lpgpu.solve(A, b, c)
+            res, x, y = lpgpu.lp_batch_get_solution(h, k, *A.shape)
+            assert np.array_equal(x.view(np.uint64), g["x"].view(np.uint64))
+            assert np.array_equal(y, g["y"])
+            assert res["objective"] == g["objective"]
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_reset_and_resolve_are_identical():
+    lps = mixed_lps(7, 20)
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_solve(h)
+        first = [lpgpu.lp_batch_get_solution(h, k, *A.shape) for k, (A, _, _) in enumerate(lps)]
+        lpgpu.lp_batch_reset(h)
+        lpgpu.lp_batch_solve(h)
+        for k, (A, _, _) in enumerate(lps):
+            r2, x2, y2 = lpgpu.lp_batch_get_solution(h, k, *A.shape)
+            assert r2["pivots"] == first[k][0]["pivots"] and np.array_equal(x2, first[k][1])
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_iteration_cap_in_batch():
+    lps = mixed_lps(9, 10, 40, 80)
+    h = lpgpu.lp_batch_create(lps, max_pivots=2)
+    try:
+        lpgpu.lp_batch_solve(h)
+        for k, (A, b, c) in enumerate(lps):
+            res, _, _ = lpgpu.lp_batch_get_solution(h, k, *A.shape)
+            o = oracle.solve(A, b, c, max_pivots=2)
+            assert res["status"] == o["status"] and res["pivots"] == o["pivots"]
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_autotuner_writes_and_reuses_its_cache(monkeypatch):
+    lps = mixed_lps(13, 40, 20, 200)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.jsonl")
+        h = lpgpu.lp_batch_create(lps)
+        try:
+            best = lpgpu.lp_batch_autotune(h, path, trials=1)
+            shape = lpgpu.lp_batch_get_shape(h)
+            assert best > 0
+            lpgpu.lp_batch_solve(h)
+            check_batch(h, lps)
+        finally:
+            lpgpu.lp_batch_destroy(h)
+        line = open(path).read().strip().splitlines()[-1]
+        assert f'"block": {shape["block"]}' in line and '"key": "batch/count64/m256/n256"' in line
+        monkeypatch.setenv("LP_AUTOTUNE_CACHE", path)
+        h2 = lpgpu.lp_batch_create(lps)
+        try:
+            assert lpgpu.lp_batch_get_shape(h2) == shape
+        finally:
+            lpgpu.lp_batch_destroy(h2)

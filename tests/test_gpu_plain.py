@@ -221,7 +221,10 @@ def test_general_row_layout_large_m():
     assert_same_result(A, b, c, g, oracle.solve(A, b, c))
 
 
-@pytest.mark.parametrize("opts", [dict(cols_per_block=1), dict(cols_per_block=3), dict(cols_per_block=64),
+@pytest.mark.parametrize("opts", [dict(cols_per_block=1), dict(cols_per_block=2), dict(cols_per_block=4),
+                                  dict(cols_per_block=8), dict(cols_per_block=16),
+                                  dict(cols_per_block=1, rows_per_thread=8), dict(cols_per_block=2, rows_per_thread=4),
+                                  dict(cols_per_block=16, rows_per_thread=2), dict(rows_per_thread=8),
                                   dict(use_graph=0), dict(chunk_pivots=1), dict(chunk_pivots=33)])
 def test_launch_options_do_not_change_results(opts):
     A, b, c = rand_lp(5, 333, 444, 1, 9, signed=True)
@@ -311,5 +314,48 @@ def test_bad_inputs_are_rejected():
     with pytest.raises(lpgpu.LPError) as e:
         lpgpu.lp_create(A2, b, c)
     assert e.value.code == lpgpu.LP_E_INVAL
-    with pytest.raises(lpgpu.LPError):
-        lpgpu.lp_create(A, b, c, cols_per_block=65)
+    for bad in (3, 32, 64, -1):
+        with pytest.raises(lpgpu.LPError) as e:
+            lpgpu.lp_create(A, b, c, cols_per_block=bad)
+        assert e.value.code == lpgpu.LP_E_INVAL
+    for bad in (3, 16, -2):
+        with pytest.raises(lpgpu.LPError) as e:
+            lpgpu.lp_create(A, b, c, rows_per_thread=bad)
+        assert e.value.code == lpgpu.LP_E_INVAL
+
+
+def test_work_counter_and_kernel_timing():
+    """updated_columns counts the columns with a nonzero normalised pivot-row
+    entry, pivot by pivot, and timing mode times one update per pivot."""
+    A, b, c = rand_lp(21, 150, 170, 1, 9, signed=True)
+    h = lpgpu.lp_create(A, b, c, time_kernels=1, chunk_pivots=4)
+    o = oracle.OracleLP(A, b, c)
+    try:
+        total = 0
+        for _ in range(12):
+            T = o.tableau()
+            before = o.pivots
+            o.step(1)
+            if o.pivots == before:
+                break
+            r = int(o.log()[0][-1])
+            total += int(np.count_nonzero(T[r]))
+            lpgpu.lp_step(h, 1)
+            t = lpgpu.lp_get_timing(h)
+            assert t["pivots"] == o.pivots
+            assert t["updated_columns"] == total
+            assert t["update_launches"] == 1 and t["update_ms"] > 0
+        lpgpu.lp_solve(h)
+        t = lpgpu.lp_get_timing(h)
+        o.step(-1)
+        assert t["pivots"] == o.pivots
+    finally:
+        lpgpu.lp_destroy(h)
+        o.close()
+
+
+@pytest.mark.parametrize("opts", [dict(time_kernels=1), dict(time_kernels=1, use_graph=0)])
+def test_timing_mode_keeps_results(opts):
+    lp = lpgen.dense_lp(5, 900, 1100)
+    g = lpgpu.solve(lp.A, lp.b, lp.c, **opts)
+    assert_same_result(lp.A, lp.b, lp.c, g, oracle.solve(lp.A, lp.b, lp.c))
