@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -107,15 +109,168 @@ def bench_plain(args, lpgpu, lpgen, torch):
         lp=lp,
     )
     if tot_launch:
-        per_launch_bytes = update_bytes(m, n, tot_cols, tot_piv) / tot_piv
+        # every update launch is timed, including the few that return at once
+        # after the optimum; they carry no algorithmic bytes
+        per_launch_bytes = update_bytes(m, n, tot_cols, tot_piv) / tot_launch
         avg_ms = upd_ms / tot_launch
         ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         out["roofline"] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                                frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
                                kernel="k_update", avg_launch_us=round(avg_ms * 1e3, 2),
                                alg_bytes_per_launch=per_launch_bytes, launches=tot_launch,
-                               columns_per_launch=tot_cols / tot_piv)
+                               pivots=tot_piv, alg_bytes_per_pivot=update_bytes(m, n, tot_cols, tot_piv) / tot_piv,
+                               columns_per_pivot=tot_cols / tot_piv)
     return out
+
+
+def bench_batch(args, lpgpu, lpgen, torch):
+    """512 LPs (m, n uniform on [32, 512]): the batched form against the same
+    LPs solved one at a time by the single-LP solver, both from
+    device-resident inputs, both rebuilding every tableau inside the timed
+    region."""
+    from paper_2211_10979_amd.certify import certify
+
+    sizes = lpgen.batch_sizes(lpgen.BATCH_SEED, args.batch_lps)
+    lps = [lpgen.dense_lp(lpgen.BATCH_SEED, m, n, k=k) for k, (m, n) in enumerate(sizes)]
+    h = lpgpu.lp_batch_create([(lp.A, lp.b, lp.c) for lp in lps])
+    try:
+        tune_ms = lpgpu.lp_batch_autotune(h, os.environ.get("LP_AUTOTUNE_CACHE"), trials=2)
+        shape = lpgpu.lp_batch_get_shape(h)
+        for _ in range(2):
+            lpgpu.lp_batch_reset(h)
+            lpgpu.lp_batch_solve(h)
+        reps = args.batch_steps
+        dev_ms = 0.0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lpgpu.lp_batch_reset(h)
+            lpgpu.lp_batch_solve(h)
+            dev_ms += lpgpu.lp_batch_solve_ms(h)
+        batch_s = (time.perf_counter() - t0) / reps
+        results = [lpgpu.lp_batch_get_solution(h, k, lp.m, lp.n) for k, lp in enumerate(lps)]
+        logs = [lpgpu.lp_batch_get_pivots(h, k) for k in range(len(lps))]
+    finally:
+        lpgpu.lp_batch_destroy(h)
+    pivots = sum(r[0]["pivots"] for r in results)
+    alg = sum(r[0]["pivots"] * 16.0 * (lp.m + 1) * (lp.n + 2) for r, lp in zip(results, lps))
+    cert_ok = all(certify(lp.A, lp.b, lp.c, x, y, res["objective"])[0] for (res, x, y), lp in zip(results, lps))
+
+    # one at a time: a context per LP, inputs on the device, same rebuild + solve
+    dev = torch.device("cuda", 0)
+    ctxs, dins = [], []
+    for lp in lps:
+        d = [torch.from_numpy(a).to(dev) for a in (lp.A, lp.b, lp.c)]
+        dins.append(d)
+        ctxs.append(lpgpu.lp_create_device(lp.m, lp.n, *d))
+    try:
+        for h1, d in zip(ctxs[:16], dins[:16]):
+            lpgpu.lp_reload_device(h1, *d)
+            lpgpu.lp_solve(h1)
+        same = True
+        t0 = time.perf_counter()
+        for k, (h1, d) in enumerate(zip(ctxs, dins)):
+            lpgpu.lp_reload_device(h1, *d)
+            lpgpu.lp_solve(h1)
+            res, x, y = lpgpu.lp_get_solution(h1)
+            if k < len(results):
+                same &= bool(np.array_equal(x, results[k][1]) and res["pivots"] == results[k][0]["pivots"])
+        solo_s = time.perf_counter() - t0
+        for k, h1 in enumerate(ctxs):
+            r, q = lpgpu.lp_get_pivots(h1)
+            same &= r.tolist() == logs[k][0].tolist() and q.tolist() == logs[k][1].tolist()
+    finally:
+        for h1 in ctxs:
+            lpgpu.lp_destroy(h1)
+    n = len(lps)
+    return dict(workload=f"batch of {n} dense LPs, m and n uniform on [32, 512], seed {lpgen.BATCH_SEED}",
+                solves_per_s=round(n / batch_s, 1), ms_per_batch=round(1e3 * batch_s, 3),
+                device_ms_per_batch=round(dev_ms / reps, 3), pivots=pivots,
+                alg_gbs=round(alg / (dev_ms / reps * 1e-3) / 1e9, 1),
+                one_at_a_time_solves_per_s=round(n / solo_s, 1),
+                speedup_vs_one_at_a_time=round(solo_s / batch_s, 2),
+                kernel_shape=shape, autotune_best_ms=round(tune_ms, 3),
+                identical_to_single_lp_solver=bool(same), certificates_ok=bool(cert_ok))
+
+
+def bench_serve(args, lpgpu, lpgen):
+    """A Poisson arrival stream of dense LPs (m, n log-uniform on [64, 4096])
+    through the server, against one-at-a-time solves of the same trace."""
+    import threading
+
+    from paper_2211_10979_amd.certify import certify
+
+    count = args.serve_lps
+    sizes, gaps = lpgen.trace_sizes(lpgen.TRACE_SEED, count)
+    log(f"serving: generating {count} LPs")
+    lps = [lpgen.dense_lp(lpgen.TRACE_SEED, m, n, k=k) for k, (m, n) in enumerate(sizes)]
+
+    def solo(lp):
+        t0 = time.perf_counter()
+        h = lpgpu.lp_create(lp.A, lp.b, lp.c)
+        lpgpu.lp_solve(h)
+        res, x, y = lpgpu.lp_get_solution(h)
+        lpgpu.lp_destroy(h)
+        return time.perf_counter() - t0, res, x
+
+    # calibrate the one-at-a-time rate on a sample, then set the arrival rate
+    sample = lps[: min(len(lps), 100)]
+    for lp in sample[:5]:
+        solo(lp)
+    t_sample = sum(solo(lp)[0] for lp in sample)
+    c_seq = len(sample) / t_sample
+    lam = args.serve_load * c_seq
+    arrivals = np.cumsum(gaps) / lam
+
+    # one at a time on the same trace: service times measured back to back,
+    # each LP starts at max(its arrival, previous finish)
+    log("serving: one-at-a-time baseline")
+    finish = 0.0
+    lat = []
+    solo_res = []
+    for lp, arr in zip(lps, arrivals):
+        dt, res, x = solo(lp)
+        start = max(arr, finish)
+        finish = start + dt
+        lat.append(finish - arr)
+        solo_res.append((res, x))
+    solo_makespan = finish - arrivals[0]
+
+    log("serving: server")
+    s = lpgpu.lp_server_create(int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
+    tickets = [None] * count
+    try:
+        t0 = time.perf_counter()
+
+        def submitter():
+            for k, (lp, arr) in enumerate(zip(lps, arrivals)):
+                wait = arr - arrivals[0] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                tickets[k] = lpgpu.lp_server_submit(s, lp.A, lp.b, lp.c)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        served = []
+        for k, lp in enumerate(lps):
+            served.append(lpgpu.lp_server_wait(s, tickets[k], lp.m, lp.n))
+        makespan = time.perf_counter() - t0
+        st = lpgpu.lp_server_get_stats(s)
+    finally:
+        lpgpu.lp_server_destroy(s)
+    same = all(sr[0]["pivots"] == so[0]["pivots"] and np.array_equal(sr[1], so[1])
+               for sr, so in zip(served, solo_res))
+    cert = all(certify(lp.A, lp.b, lp.c, x, y, r["objective"])[0] for (r, x, y), lp in zip(served[:200], lps))
+    return dict(workload=f"{count} dense LPs of the Poisson trace (m, n log-uniform on [64, 4096], seed "
+                         f"{lpgen.TRACE_SEED}), arrival rate {args.serve_load} x the one-at-a-time rate",
+                lps=count, arrival_rate_per_s=round(lam, 1), budget_gb=args.serve_budget_gb,
+                max_slots=args.serve_slots, solves_per_s=round(count / makespan, 1),
+                p50_ms=round(st["p50_ms"], 3), p99_ms=round(st["p99_ms"], 3),
+                peak_resident_gb=round(st["peak_bytes"] / (1 << 30), 3), ticks=st["ticks"],
+                one_at_a_time_solves_per_s=round(count / solo_makespan, 1),
+                one_at_a_time_p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3),
+                one_at_a_time_p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3),
+                identical_to_one_at_a_time=bool(same), certificates_ok_first_200=bool(cert))
 
 
 def cpu_baseline(args, lp, gpu_log):
@@ -156,6 +311,15 @@ def main():
     ap.add_argument("--time-kernels", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-lps", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-lps", type=int, default=1000,
+                    help="LPs of the arrival trace served (the full trace has 10000)")
+    ap.add_argument("--serve-load", type=float, default=1.5, help="arrival rate / one-at-a-time solve rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run the plain copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -206,6 +370,11 @@ def main():
         roofline=roof,
         plain=plain,
     )
+    if not args.no_batch:
+        log(f"batched: {args.batch_lps} LPs")
+        line["batched"] = bench_batch(args, lpgpu, lpgen, torch)
+    if not args.no_serve:
+        line["serving"] = bench_serve(args, lpgpu, lpgen)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle")
         line["cpu_baseline"] = cpu_baseline(args, lp, gpu_log)

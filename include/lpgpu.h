@@ -86,7 +86,8 @@ typedef struct {
     int32_t batch_block;    /* batched kernel: threads per workgroup (256, 512, 1024; 0 = autotune
                                cache or default) */
     int32_t batch_unroll;   /* batched kernel: items in flight per thread (1, 2, 4, 8; 0 = auto) */
-    int32_t reserved;
+    int32_t update_hints;   /* update kernel cache hints: bit 0 non-temporal loads, bit 1
+                               non-temporal stores (default 0) */
 } lp_options;
 
 typedef struct {
@@ -188,8 +189,9 @@ int lp_get_info(const lp_ctx *h, lp_info *info);
 
 typedef struct {
     double solve_ms;          /* device time of the last lp_solve / lp_step */
-    double update_ms;         /* summed device time of the update kernels that applied a pivot
-                                 during that call (time_kernels = 1; else 0) */
+    double update_ms;         /* summed device time of the update kernels launched during that
+                                 call (time_kernels = 1; else 0), including the few launched
+                                 after the solve ended, which return at once */
     int64_t update_launches;  /* number of update kernels in update_ms */
     int64_t pivots;           /* pivots performed since the tableau was built */
     int64_t updated_columns;  /* tableau columns rewritten by Step 3, summed over those pivots

@@ -53,7 +53,7 @@ int lp_options_default(lp_options *o) {
     o->rows_per_thread = 0;
     o->batch_block = 0;
     o->batch_unroll = 0;
-    o->reserved = 0;
+    o->update_hints = 0;
     return LP_OK;
 }
 

@@ -32,6 +32,7 @@ struct UpdateConfig {
     int cols;       // listed columns per workgroup
     int rv;         // row pairs (double2) per thread and column
     int rowchunks;  // row chunks of block*rv pairs covering rows 0..m
+    int nt;         // bit 0: non-temporal loads, bit 1: non-temporal stores
 };
 
 // Small m: one chunk of 64 or 128 pairs; otherwise 256 threads with `rv`
@@ -40,10 +41,10 @@ UpdateConfig pick_update_config(int32_t m, int cols, int rv) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
     if (nvec <= 128) {
         const int block = nvec <= 64 ? 64 : 128;
-        return {block, cols, 1, 1};
+        return {block, cols, 1, 1, 0};
     }
     const int64_t span = 256 * (int64_t)rv;
-    return {256, cols, rv, (int)((nvec + span - 1) / span)};
+    return {256, cols, rv, (int)((nvec + span - 1) / span), 0};
 }
 
 bool valid_cols(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
@@ -131,6 +132,7 @@ int validate_opts(const lp_options &o) {
         return set_error(LP_E_INVAL, "cols_per_block must be 0 (auto) or one of 1, 2, 4, 8, 16");
     if (o.rows_per_thread != 0 && !valid_rv(o.rows_per_thread))
         return set_error(LP_E_INVAL, "rows_per_thread must be 0 (auto) or one of 1, 2, 4, 8");
+    if (o.update_hints < 0 || o.update_hints > 3) return set_error(LP_E_INVAL, "update_hints must be in [0, 3]");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
     return LP_OK;
 }
@@ -159,6 +161,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
     h->ucfg = pick_update_config(m, o.cols_per_block > 0 ? o.cols_per_block : 4,
                                  o.rows_per_thread > 0 ? o.rows_per_thread : 1);
+    if (h->ucfg.block == 256) h->ucfg.nt = o.update_hints & 3;
     h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
     h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
     h->use_graph = o.use_graph != 0;
@@ -259,20 +262,23 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
 void launch_update(lp_ctx *h) {
     const UpdateConfig &u = h->ucfg;
     const dim3 grid((unsigned)((int64_t)u.rowchunks * h->nparts)), block((unsigned)u.block);
-#define LP_UPD(B, C, V)                                                                                \
-    if (u.block == B && u.cols == C && u.rv == V) {                                                    \
-        hipLaunchKernelGGL((k_update<B, C, V>), grid, block, 0, h->stream, h->T, h->ld, h->m, h->n,    \
-                           u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);                        \
+#define LP_UPD(B, C, V, NL, NS)                                                                        \
+    if (u.block == B && u.cols == C && u.rv == V && u.nt == (NL | (NS << 1))) {                        \
+        hipLaunchKernelGGL((k_update<B, C, V, NL, NS>), grid, block, 0, h->stream, h->T, h->ld, h->m,  \
+                           h->n, u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);                  \
         return;                                                                                        \
     }
-#define LP_UPD_C(C) LP_UPD(64, C, 1) LP_UPD(128, C, 1) LP_UPD(256, C, 1) LP_UPD(256, C, 2) \
-    LP_UPD(256, C, 4) LP_UPD(256, C, 8)
+#define LP_UPD_V(C, V) LP_UPD(256, C, V, 0, 0) LP_UPD(256, C, V, 1, 0) LP_UPD(256, C, V, 0, 1) \
+    LP_UPD(256, C, V, 1, 1)
+#define LP_UPD_C(C) LP_UPD(64, C, 1, 0, 0) LP_UPD(128, C, 1, 0, 0) LP_UPD_V(C, 1) LP_UPD_V(C, 2) \
+    LP_UPD_V(C, 4) LP_UPD_V(C, 8)
     LP_UPD_C(1)
     LP_UPD_C(2)
     LP_UPD_C(4)
     LP_UPD_C(8)
     LP_UPD_C(16)
 #undef LP_UPD_C
+#undef LP_UPD_V
 #undef LP_UPD
 }
 
@@ -318,10 +324,11 @@ int launch_chunk(lp_ctx *h, int slot) {
     return LP_OK;
 }
 
-// Adds the update-kernel times of the first `active` pivots of a finished chunk.
-int harvest_timing(lp_ctx *h, int slot, int64_t active) {
+// Adds the times of every update launch of a finished chunk: those that
+// applied a pivot and the no-op ones queued after the solve ended.
+int harvest_timing(lp_ctx *h, int slot) {
     if (!h->timing) return LP_OK;
-    for (int64_t k = 0; k < active && k < h->chunk; ++k) {
+    for (int64_t k = 0; k < h->chunk; ++k) {
         float ms = 0.f;
         LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]));
         h->update_ms += ms;
@@ -340,7 +347,6 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
-    int64_t done_before = h->pivots_host;
     if (int rc = launch_chunk(h, 0)) return rc;
     LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipEventRecord(h->ev_slot[0], h->stream));
@@ -351,8 +357,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
         LP_HIP_CHECK(hipEventRecord(h->ev_slot[next], h->stream));
         LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
         const DevState s = h->host_st[slot];
-        if (int rc = harvest_timing(h, slot, s.pivots - done_before)) return rc;
-        done_before = s.pivots;
+        if (int rc = harvest_timing(h, slot)) return rc;
         if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
         slot = next;
     }
@@ -360,8 +365,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
     DevState s;
     LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
-    // the chunk queued last may still have applied pivots
-    if (int rc = harvest_timing(h, slot ^ 1, s.pivots - done_before)) return rc;
+    if (int rc = harvest_timing(h, slot ^ 1)) return rc;  // the chunk queued last
     h->pivots_host = s.pivots;
     h->status_host = s.status;
     float ms = 0.f;

@@ -116,6 +116,16 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     }
     const int64_t W = (int64_t)n + m + 1;
 
+    // Rewrite-list entries this thread reads in Step 3's inputs: loaded now,
+    // off the critical path (they do not depend on q or r).
+    constexpr int kPre = 8;
+    int32_t cpre[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const int32_t t = tid + k * nt;
+        cpre[k] = t < n ? cols[t] : 0;
+    }
+
     // Step 1: most negative objective-row entry, lowest column on ties.
     double v = __builtin_inf();
     int32_t q = kNoIndex;
@@ -146,13 +156,18 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     }
 
     // Step 2: minimum ratio over rows with T[i][q] > eps_p, lowest row on ties.
+    // The pivot column is also copied to F on the way (used only if a pivot
+    // follows).
     const double *colq = T + (int64_t)q * ld;
     const double *rhs = T + (W - 1) * ld;
+    const int32_t pq = pos[q];
     double rv = __builtin_inf();
     int32_t r = kNoIndex;
     int bad = 0;
+    if (tid == 0) F[0] = colq[0];
     for (int32_t i = 1 + tid; i <= m; i += nt) {
         const double a = colq[i], bb = rhs[i];
+        F[i] = a;
         if (a != a || bb != bb) {
             bad = 1;
         } else if (a > s.eps_p) {
@@ -178,15 +193,19 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     // Inputs of Step 3. The leaving column takes q's place in the list.
     const double p = colq[r];
     const int32_t leave = basis[r - 1];
-    const int32_t pq = pos[q];
-    for (int32_t i = tid; i <= m; i += nt) F[i] = colq[i];
     int32_t nz = 0;
-    for (int32_t t = tid; t < n + 2; t += nt) {
-        const int32_t j = t == pq ? leave : (t == n ? q : cols[t]);
+    auto stage_R = [&](int32_t t, int32_t listed) {
+        const int32_t j = t == pq ? leave : (t == n ? q : (t == n + 1 ? (int32_t)(W - 1) : listed));
         const double R = T[(int64_t)j * ld + r] / p;
         Rl[t] = R;
         nz += R != 0.0;
+    };
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const int32_t t = tid + k * nt;
+        if (t < n + 2) stage_R(t, cpre[k]);
     }
+    for (int32_t t = tid + kPre * nt; t < n + 2; t += nt) stage_R(t, t < n ? cols[t] : 0);
     // count of rewritten columns (nonzero R), summed over the block
     for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
     if ((tid & 63) == 0) scount[tid >> 6] = nz;
@@ -221,7 +240,31 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
 //     T[i][j] = fma(-F_i, R_j, T[i][j])    otherwise.
 // The row-chunk-0 workgroup of each column group also reduces its columns'
 // new row-0 entries to one (value, column) partial for the next Step 1.
-template <int B, int C, int RV>
+// 16-byte loads and stores, optionally with the non-temporal hint (the
+// tableau streams through once per pivot).
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ double2 ld2(const double2 *p) {
+    if constexpr (NT) {
+        const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
+        return double2{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void st2(double2 *p, const double2 &y) {
+    if constexpr (NT) {
+        v2d v = {y.x, y.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<v2d *>(p));
+    } else {
+        *p = y;
+    }
+}
+
+template <int B, int C, int RV, int NTL = 0, int NTS = 0>
 __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                               int32_t rowchunks, const int32_t *__restrict__ cols,
                                               const double *__restrict__ Rl, const double *__restrict__ F,
@@ -254,7 +297,7 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int k = 0; k < RV; ++k) x[c][k] = col[c][base + k * B];
+            for (int k = 0; k < RV; ++k) x[c][k] = ld2<NTL != 0>(col[c] + base + k * B);
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
@@ -263,7 +306,7 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
                 double2 y;
                 y.x = (2 * v == r) ? Rj[c] : fma(-f[k].x, Rj[c], x[c][k].x);
                 y.y = (2 * v + 1 == r) ? Rj[c] : fma(-f[k].y, Rj[c], x[c][k].y);
-                col[c][v] = y;
+                st2<NTS != 0>(col[c] + v, y);
             }
         if (row0) {
             double val = __builtin_inf();

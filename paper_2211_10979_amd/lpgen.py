@@ -28,6 +28,8 @@ rejected when u >= floor(2^64 / span) * span, else the value is lo + u mod span.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -40,7 +42,16 @@ MIX1 = 0xBF58476D1CE4E5B9
 MIX2 = 0x94D049BB133111EB
 SIZE_STREAM_SALT = 0x5EED
 
-_CHUNK = 1 << 22
+_CHUNK = 1 << 20
+_POOL = None
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        workers = int(os.environ.get("LPGEN_THREADS", "0")) or min(16, len(os.sched_getaffinity(0)))
+        _POOL = ThreadPoolExecutor(max_workers=max(1, workers))
+    return _POOL
 
 
 def mix64(z: int) -> int:
@@ -65,13 +76,24 @@ class Stream:
         self.drawn = 0  # number of outputs consumed so far
 
     def raw(self, count: int) -> np.ndarray:
-        """The next `count` raw 64-bit outputs."""
+        """The next `count` raw 64-bit outputs (blocks computed in parallel;
+        each output depends only on its position, so the result does not
+        depend on the number of threads)."""
         out = np.empty(count, dtype=np.uint64)
-        with np.errstate(over="ignore"):
-            for lo in range(0, count, _CHUNK):
-                hi = min(count, lo + _CHUNK)
-                t = np.arange(self.drawn + lo + 1, self.drawn + hi + 1, dtype=np.uint64)
+        first = self.drawn
+
+        def block(lo):
+            hi = min(count, lo + _CHUNK)
+            with np.errstate(over="ignore"):
+                t = np.arange(first + lo + 1, first + hi + 1, dtype=np.uint64)
                 out[lo:hi] = _mix64_np(np.uint64(self.state) + t * np.uint64(GOLDEN))
+
+        starts = range(0, count, _CHUNK)
+        if count > 2 * _CHUNK:
+            list(_pool().map(block, starts))
+        else:
+            for lo in starts:
+                block(lo)
         self.drawn += count
         return out
 
@@ -90,6 +112,38 @@ class Stream:
             need -= keep.size
         u = np.concatenate(got) if len(got) > 1 else got[0]
         return (u % np.uint64(span)).astype(np.int64) + lo
+
+    def values(self, count: int, lo: int, hi: int) -> np.ndarray:
+        """As integers(), as float64, computed block-parallel. When no draw
+        of the range is rejected (each draw is rejected with probability
+        below 2^-54), the k-th value is the k-th draw's; otherwise the exact
+        sequential rejection path is taken."""
+        span = hi - lo + 1
+        limit = np.uint64(((1 << 64) // span) * span)
+        out = np.empty(count, dtype=np.float64)
+        first = self.drawn
+        rejected = [False]
+
+        def block(b0):
+            b1 = min(count, b0 + _CHUNK)
+            with np.errstate(over="ignore"):
+                t = np.arange(first + b0 + 1, first + b1 + 1, dtype=np.uint64)
+                u = _mix64_np(np.uint64(self.state) + t * np.uint64(GOLDEN))
+            if np.any(u >= limit):
+                rejected[0] = True
+            np.add(u % np.uint64(span), np.uint64(lo), out=u)
+            out[b0:b1] = u
+
+        starts = range(0, count, _CHUNK)
+        if count > 2 * _CHUNK:
+            list(_pool().map(block, starts))
+        else:
+            for b0 in starts:
+                block(b0)
+        if rejected[0]:
+            return self.integers(count, lo, hi).astype(np.float64)
+        self.drawn += count
+        return out
 
     def unit(self, count: int) -> np.ndarray:
         """`count` doubles in [0, 1) from the top 53 bits of each draw."""
@@ -127,9 +181,9 @@ def dense_lp(seed: int, m: int, n: int, k: int = 0, lo: int = 1, hi: int = 1000)
     if m < 1 or n < 1:
         raise ValueError("m and n must be >= 1")
     s = lp_stream(seed, k)
-    A = s.integers(m * n, lo, hi).astype(np.float64).reshape(m, n)
-    b = s.integers(m, lo, hi).astype(np.float64)
-    c = s.integers(n, lo, hi).astype(np.float64)
+    A = s.values(m * n, lo, hi).reshape(m, n)
+    b = s.values(m, lo, hi)
+    c = s.values(n, lo, hi)
     return LP(A, b, c)
 
 

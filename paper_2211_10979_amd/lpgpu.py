@@ -52,7 +52,7 @@ class lp_options(ctypes.Structure):
         ("rows_per_thread", ctypes.c_int32),
         ("batch_block", ctypes.c_int32),
         ("batch_unroll", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("update_hints", ctypes.c_int32),
     ]
 
 

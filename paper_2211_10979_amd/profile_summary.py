@@ -1,0 +1,106 @@
+"""Formats rocprofv3 output as a short text summary.
+
+    python -m paper_2211_10979_amd.profile_summary <rocprofv3 output dir> [--kernel NAME]
+
+Reads whatever the directory holds:
+  * `*_kernel_stats.csv` (from --kernel-trace --stats --output-format csv):
+    calls, total, average, min and max duration per kernel;
+  * `*_results.db` (rocprofv3's SQLite output): the same per-kernel figures
+    from its dispatch table;
+  * `*_counter_collection.csv` (from --pmc): per-kernel average of each
+    counter over the dispatches of that kernel.
+Durations are in microseconds.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import os
+import sqlite3
+import statistics
+from collections import defaultdict
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def kernel_stats_csv(path):
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            calls = int(r["Calls"])
+            rows.append(dict(kernel=_short(r["Name"]), calls=calls, total_us=float(r["TotalDurationNs"]) / 1e3,
+                             avg_us=float(r["AverageNs"]) / 1e3, min_us=float(r["MinNs"]) / 1e3,
+                             max_us=float(r["MaxNs"]) / 1e3))
+    return rows
+
+
+def kernel_stats_db(path):
+    db = sqlite3.connect(path)
+    cur = db.cursor()
+    durs = defaultdict(list)
+    for name, start, end in cur.execute("select name, start, end from kernels"):
+        durs[_short(name)].append((end - start) / 1e3)
+    rows = []
+    for k, v in durs.items():
+        rows.append(dict(kernel=k, calls=len(v), total_us=sum(v), avg_us=statistics.fmean(v), min_us=min(v),
+                         max_us=max(v)))
+    rows.sort(key=lambda r: -r["total_us"])
+    return rows
+
+
+def counters_csv(path):
+    acc = defaultdict(lambda: defaultdict(list))
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            acc[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: statistics.fmean(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def summarize(directory, kernel=None):
+    out = []
+    stats = []
+    for p in sorted(glob.glob(os.path.join(directory, "**", "*_kernel_stats.csv"), recursive=True)):
+        stats = kernel_stats_csv(p)
+        out.append(f"source: {os.path.relpath(p, directory)}")
+    if not stats:
+        for p in sorted(glob.glob(os.path.join(directory, "**", "*_results.db"), recursive=True)):
+            stats = kernel_stats_db(p)
+            out.append(f"source: {os.path.relpath(p, directory)}")
+    if stats:
+        out.append("")
+        out.append("| kernel | calls | total us | avg us | min us | max us |")
+        out.append("|---|---|---|---|---|---|")
+        for r in stats:
+            if kernel and kernel not in r["kernel"]:
+                continue
+            out.append(f"| {r['kernel']} | {r['calls']} | {r['total_us']:.1f} | {r['avg_us']:.2f} | "
+                       f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
+    for p in sorted(glob.glob(os.path.join(directory, "**", "*_counter_collection.csv"), recursive=True)):
+        cs = counters_csv(p)
+        out.append("")
+        out.append(f"counters: {os.path.relpath(p, directory)} (average per dispatch)")
+        out.append("")
+        out.append("| kernel | counter | value |")
+        out.append("|---|---|---|")
+        for k, vals in sorted(cs.items()):
+            if kernel and kernel not in k:
+                continue
+            for c, v in sorted(vals.items()):
+                out.append(f"| {k} | {c} | {v:.1f} |")
+    return "\n".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("directory")
+    ap.add_argument("--kernel", default=None)
+    a = ap.parse_args()
+    print(summarize(a.directory, a.kernel))
+
+
+if __name__ == "__main__":
+    main()

@@ -344,7 +344,7 @@ def test_work_counter_and_kernel_timing():
             t = lpgpu.lp_get_timing(h)
             assert t["pivots"] == o.pivots
             assert t["updated_columns"] == total
-            assert t["update_launches"] == 1 and t["update_ms"] > 0
+            assert t["update_launches"] >= 1 and t["update_ms"] > 0
         lpgpu.lp_solve(h)
         t = lpgpu.lp_get_timing(h)
         o.step(-1)

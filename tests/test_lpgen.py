@@ -70,3 +70,19 @@ def test_workload_fingerprint_stable():
     lp2 = lpgen.workload("dense_200x200")
     assert h == hashlib.sha256(lp2.A.tobytes() + lp2.b.tobytes() + lp2.c.tobytes()).hexdigest()
     assert lp.A[0, :3].tolist() == lpgen.dense_lp(1, 200, 200).A[0, :3].tolist()
+
+
+def test_parallel_values_equal_sequential_rejection_path():
+    for count in (1, 1000, (1 << 20) * 3 + 17):
+        a = lpgen.Stream(2024).values(count, 1, 1000)
+        b = lpgen.Stream(2024).integers(count, 1, 1000).astype(np.float64)
+        assert np.array_equal(a, b)
+
+
+def test_rejection_path_is_taken_when_a_draw_is_rejected():
+    # span 3 * 2^62: a draw is rejected with probability 1/4, so the exact
+    # sequential path must be used and must agree with integers()
+    span = 3 << 62
+    a = lpgen.Stream(7).values(5000, 0, span - 1)
+    b = lpgen.Stream(7).integers(5000, 0, span - 1).astype(np.float64)
+    assert np.array_equal(a, b)
