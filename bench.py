@@ -50,6 +50,33 @@ def update_bytes(m: int, n: int, cols: int, launches: int) -> float:
     return 16.0 * (m + 1) * cols + launches * (8.0 * (m + 1) + 16.0 * W)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_update_dense_8000x8000_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2211_10979_amd", "csrc", "plain_kernels.hpp")
+
+
+def committed_traffic(kernel):
+    """HBM bytes per update launch that applied a pivot, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    copy-kernel calibration). None unless that summary was taken on this
+    kernel instance built from the current source."""
+    import hashlib
+
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("|"):
+            k, v = line.split(":", 1)
+            kv[k.strip().lstrip("- ")] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != src:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_pivot_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def bench_plain(args, lpgpu, lpgen, torch):
     lp = lpgen.workload(args.workload)
     m, n = lp.m, lp.n
@@ -84,6 +111,9 @@ def bench_plain(args, lpgpu, lpgen, torch):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         rows, cols = lpgpu.lp_get_pivots(h)
+        info = lpgpu.lp_get_info(h)
+        kernel = (f"k_update<{info.update_block}, {info.update_cols}, {info.update_rows}, "
+                  f"{info.update_hints & 1}, {info.update_hints >> 1}>")
     finally:
         lpgpu.lp_destroy(h)
     from paper_2211_10979_amd.certify import certify
@@ -114,9 +144,11 @@ def bench_plain(args, lpgpu, lpgen, torch):
         per_launch_bytes = update_bytes(m, n, tot_cols, tot_piv) / tot_launch
         avg_ms = upd_ms / tot_launch
         ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        tr = committed_traffic(kernel)
+        traffic = None if tr is None else round(tr * tot_piv / tot_launch)  # per launch, as achieved
         out["roofline"] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                               frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
-                               kernel="k_update", avg_launch_us=round(avg_ms * 1e3, 2),
+                               frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
+                               kernel=kernel, avg_launch_us=round(avg_ms * 1e3, 2),
                                alg_bytes_per_launch=per_launch_bytes, launches=tot_launch,
                                pivots=tot_piv, alg_bytes_per_pivot=update_bytes(m, n, tot_cols, tot_piv) / tot_piv,
                                columns_per_pivot=tot_cols / tot_piv)

@@ -88,6 +88,10 @@ typedef struct {
     int32_t batch_unroll;   /* batched kernel: items in flight per thread (1, 2, 4, 8; 0 = auto) */
     int32_t update_hints;   /* update kernel cache hints: bit 0 non-temporal loads, bit 1
                                non-temporal stores (default 0) */
+    int32_t update_block;   /* update kernel threads per workgroup (64, 128, 256, 512, 1024;
+                               0 = auto); values other than 256 need cols_per_block and
+                               rows_per_thread <= 2 */
+    int32_t reserved;
 } lp_options;
 
 typedef struct {
@@ -104,6 +108,10 @@ typedef struct {
     int64_t ld;             /* column stride of the column-major device tableau, in doubles */
     size_t tableau_bytes;   /* ld * W * 8 */
     const double *tableau;  /* device pointer: T[i][j] at tableau[j*ld + i] */
+    int32_t update_block;   /* update kernel in use: threads per workgroup, */
+    int32_t update_cols;    /* listed columns per workgroup, */
+    int32_t update_rows;    /* row pairs per thread and column, */
+    int32_t update_hints;   /* cache hints (bit 0 loads, bit 1 stores non-temporal) */
 } lp_info;
 
 /* Library version string. Never fails. */

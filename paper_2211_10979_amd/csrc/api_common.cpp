@@ -54,6 +54,8 @@ int lp_options_default(lp_options *o) {
     o->batch_block = 0;
     o->batch_unroll = 0;
     o->update_hints = 0;
+    o->update_block = 0;
+    o->reserved = 0;
     return LP_OK;
 }
 

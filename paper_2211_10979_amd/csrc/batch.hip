@@ -184,6 +184,10 @@ struct lp_batch {
     int32_t *order = nullptr;    // LP indices, largest first
     int32_t *norder = nullptr;   // number of entries of `order`
     int32_t *head = nullptr;     // queue head
+    int32_t *tile_lp = nullptr;  // build tile -> LP
+    int64_t *tile_first = nullptr, *in_off_dev = nullptr;
+    int64_t ntiles = 0;
+    std::vector<BatchState> st_init;  // initial state of every LP
     BatchState init{};
     size_t lds = 0;
     BatchShape shape{};
@@ -206,7 +210,8 @@ void free_batch(lp_batch *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void *p : {(void *)b->tab, (void *)b->ints, (void *)b->inputs, (void *)b->out, (void *)b->out_off_dev,
-                    (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->norder, (void *)b->head})
+                    (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->norder, (void *)b->head,
+                    (void *)b->tile_lp, (void *)b->tile_first, (void *)b->in_off_dev})
         if (p) (void)hipFree(p);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
@@ -240,21 +245,15 @@ int capture_batch_graph(lp_batch *b) {
     return LP_OK;
 }
 
-// Initialization Step for every LP, from the stored inputs.
+// Initialization Step for every LP, from the stored inputs: one build launch
+// over all tiles, one launch for the lists, one copy of the states.
 int rebuild_all(lp_batch *b) {
-    for (int32_t k = 0; k < b->count; ++k) {
-        const BatchDesc &d = b->desc_host[k];
-        const double *A = b->inputs + b->in_off[k];
-        const double *bb = A + (int64_t)d.m * d.n;
-        const double *c = bb + d.m;
-        dim3 gs((unsigned)((d.n + kBuildTile - 1) / kBuildTile), (unsigned)((d.ld + kBuildTile - 1) / kBuildTile));
-        hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, b->stream, d.T, d.ld, d.m, d.n, A, c);
-        const int64_t nslack = (int64_t)(d.m + 1) * (d.ld / 2);
-        hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, b->stream, d.T, d.ld,
-                           d.m, d.n, bb);
-        hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, b->stream, d, b->state + k, b->init);
-    }
+    hipLaunchKernelGGL(k_batch_build, dim3((unsigned)b->ntiles), dim3(256), 0, b->stream, b->desc, b->inputs,
+                       b->in_off_dev, b->tile_lp, b->tile_first);
+    hipLaunchKernelGGL(k_batch_init_all, dim3((unsigned)b->count), dim3(256), 0, b->stream, b->desc);
     LP_HIP_CHECK(hipGetLastError());
+    LP_HIP_CHECK(hipMemcpyAsync(b->state, b->st_init.data(), b->st_init.size() * sizeof(BatchState),
+                                hipMemcpyHostToDevice, b->stream));
     b->solved = false;
     return LP_OK;
 }
@@ -423,22 +422,34 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     b->init.status = LP_RUNNING;
     b->init.eps_d = o.eps_dual;
     b->init.eps_p = o.eps_pivot;
-    b->init.max_pivots = 0;  // per LP below
-    b->st_host.resize(count);
-    b->out_host.resize((size_t)out_total);
-    // per-LP iteration caps differ: built by the init kernel from init, then patched
-    if (int rc = rebuild_all(b)) return fail(rc);
-    {
-        std::vector<BatchState> st(count);
-        for (int32_t k = 0; k < count; ++k) {
-            st[k] = b->init;
-            st[k].max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m[k] + n[k]);
-        }
-        if (hipStreamSynchronize(b->stream) != hipSuccess ||
-            hipMemcpy(b->state, st.data(), count * sizeof(BatchState), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(set_error(LP_E_DEVICE, "state init failed"));
-        b->st_host = st;
+    b->st_init.resize(count);
+    for (int32_t k = 0; k < count; ++k) {
+        b->st_init[k] = b->init;
+        b->st_init[k].max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m[k] + n[k]);
     }
+    b->st_host = b->st_init;
+    b->out_host.resize((size_t)out_total);
+    {
+        std::vector<int64_t> first(count + 1, 0);
+        for (int32_t k = 0; k < count; ++k) {
+            const int64_t rt = (b->ld[k] + 63) / 64;
+            first[k + 1] = first[k] + (int64_t)((n[k] + 63) / 64) * rt + (int64_t)((m[k] + 1 + 63) / 64) * rt;
+        }
+        b->ntiles = first[count];
+        std::vector<int32_t> tl((size_t)b->ntiles);
+        for (int32_t k = 0; k < count; ++k)
+            for (int64_t t = first[k]; t < first[k + 1]; ++t) tl[(size_t)t] = k;
+        if (int rc = dmalloc((void **)&b->tile_lp, tl.size() * sizeof(int32_t))) return fail(rc);
+        if (int rc = dmalloc((void **)&b->tile_first, first.size() * sizeof(int64_t))) return fail(rc);
+        if (int rc = dmalloc((void **)&b->in_off_dev, count * sizeof(int64_t))) return fail(rc);
+        if (hipMemcpy(b->tile_lp, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->tile_first, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(b->in_off_dev, b->in_off.data(), count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "tile table copy failed"));
+    }
+    if (int rc = rebuild_all(b)) return fail(rc);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(set_error(LP_E_DEVICE, "build failed"));
     if (int rc = set_batch_lds_limit(b->lds)) return fail(rc);
 
     // kernel shape: explicit option, else the autotune cache, else a default
@@ -471,16 +482,8 @@ int lp_batch_solve(lp_batch *b) {
 int lp_batch_reset(lp_batch *b) {
     if (!b) return set_error(LP_E_INVAL, "NULL batch");
     DeviceGuard g(b->device);
-    std::vector<BatchState> st(b->count);
-    for (int32_t k = 0; k < b->count; ++k) {
-        st[k] = b->init;
-        st[k].max_pivots = b->st_host[k].max_pivots;
-    }
     if (int rc = rebuild_all(b)) return rc;
-    LP_HIP_CHECK(hipMemcpyAsync(b->state, st.data(), st.size() * sizeof(BatchState), hipMemcpyHostToDevice,
-                                b->stream));
     LP_HIP_CHECK(hipStreamSynchronize(b->stream));
-    b->solved = false;
     return LP_OK;
 }
 

@@ -271,6 +271,77 @@ __global__ __launch_bounds__(BT) void k_batch(const BatchDesc *__restrict__ desc
     }
 }
 
+// Initialization Step of every LP of a batch in one launch. The tiles of all
+// tableaux are numbered consecutively: LP k owns tiles [first[k], first[k+1]);
+// its first ceil(n/64)*rt tiles transpose 64x64 blocks of its row-major A
+// (with -c in row 0) through LDS, the next ceil((m+1)/64)*rt fill the slack
+// identity and the RHS; rt = ceil(ld/64) row tiles per column.
+static __global__ __launch_bounds__(256) void k_batch_build(const BatchDesc *__restrict__ desc,
+                                                            const double *__restrict__ inputs,
+                                                            const int64_t *__restrict__ in_off,
+                                                            const int32_t *__restrict__ tile_lp,
+                                                            const int64_t *__restrict__ first) {
+    __shared__ double tile[64][65];
+    const int32_t k = tile_lp[blockIdx.x];
+    const BatchDesc d = desc[k];
+    const int64_t local = (int64_t)blockIdx.x - first[k];
+    const int32_t m = d.m, n = d.n;
+    const int64_t ld = d.ld;
+    const int64_t rt = (ld + 63) / 64;
+    const int64_t ns = (int64_t)((n + 63) / 64) * rt;
+    const double *A = inputs + in_off[k];
+    const double *b = A + (int64_t)m * n;
+    const double *c = b + m;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (local < ns) {
+        const int64_t j0 = (local / rt) * 64, i0 = (local % rt) * 64;
+        for (int q = 0; q < 16; ++q) {
+            const int64_t i = i0 + ty + 4 * q, j = j0 + tx;
+            double v = 0.0;
+            if (j < n) {
+                if (i == 0)
+                    v = -c[j];
+                else if (i <= m)
+                    v = A[(i - 1) * n + j];
+            }
+            tile[ty + 4 * q][tx] = v;
+        }
+        __syncthreads();
+        for (int q = 0; q < 16; ++q) {
+            const int64_t j = j0 + ty + 4 * q, i = i0 + tx;
+            if (j < n && i < ld) d.T[j * ld + i] = tile[tx][ty + 4 * q];
+        }
+    } else {
+        const int64_t l2 = local - ns;
+        const int64_t s0 = (l2 / rt) * 64, i0 = (l2 % rt) * 64;
+        for (int q = 0; q < 16; ++q) {
+            const int64_t s = s0 + ty + 4 * q, i = i0 + tx;  // column n+s, row i
+            if (s > m || i >= ld) continue;
+            double v;
+            if (s < m)
+                v = (i == s + 1) ? 1.0 : 0.0;
+            else
+                v = (i >= 1 && i <= m) ? b[i - 1] : 0.0;
+            d.T[(n + s) * ld + i] = v;
+        }
+    }
+}
+
+// Rewrite lists, positions and bases of every LP: workgroup k takes LP k.
+static __global__ __launch_bounds__(256) void k_batch_init_all(const BatchDesc *__restrict__ desc) {
+    const BatchDesc d = desc[blockIdx.x];
+    const int32_t m = d.m, n = d.n;
+    if (threadIdx.x == 0) {
+        d.cols[n] = 0;
+        d.cols[n + 1] = n + m;
+    }
+    for (int32_t t = threadIdx.x; t < n + m; t += blockDim.x) {
+        if (t < m) d.basis[t] = n + t;
+        if (t < n) d.cols[t] = t;
+        d.pos[t] = t < n ? t : -1;
+    }
+}
+
 // Initial rewrite list, positions, basis and state of one LP (grid-stride).
 static __global__ void k_batch_init_lp(BatchDesc d, BatchState *st, BatchState init) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -31,6 +31,8 @@ struct DevState {
     double eps_d, eps_p;
     int32_t fresh;       // 1: no pricing partials yet, scan row 0 instead
     int32_t nparts;      // number of pricing partials written by the update kernel
+    int32_t leave;       // column leaving the basis at the current pivot
+    int32_t pq;          // position of the entering column in the rewrite list
 };
 
 // (value, index) pair of the two-stage argmin.

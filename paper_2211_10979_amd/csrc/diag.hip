@@ -17,11 +17,18 @@ __global__ void k_diag_arith(int64_t count, const double *__restrict__ a, const 
     fmav[k] = fma(a[k], b[k], c[k]);
 }
 
-// Grid-stride copy of 16-byte vectors.
+// Plain copy: each thread moves U 16-byte vectors, B*U apart, loads first.
+template <int U>
 __global__ __launch_bounds__(256) void k_diag_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
                                                    int64_t nvec) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nvec; k += stride) dst[k] = src[k];
+    const int64_t base = (int64_t)blockIdx.x * 256 * U + threadIdx.x;
+    double2 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (base + u * 256 < nvec) x[u] = src[base + u * 256];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (base + u * 256 < nvec) dst[base + u * 256] = x[u];
 }
 
 }  // namespace
@@ -44,10 +51,11 @@ extern "C" int lp_diag_copy(int32_t device, size_t bytes, int32_t reps, double *
         hipEventCreate(&e1) != hipSuccess) {
         rc = set_error(LP_E_DEVICE, "setup failed");
     } else {
-        const unsigned blocks = 256u * 8u;
-        hipLaunchKernelGGL(k_diag_copy, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);  // warm-up
+        const unsigned blocks = (unsigned)((nvec + 256 * 2 - 1) / (256 * 2));
+        hipLaunchKernelGGL(k_diag_copy<2>, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);  // warm-up
         (void)hipEventRecord(e0, nullptr);
-        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_diag_copy, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);
+        for (int r = 0; r < reps; ++r)
+            hipLaunchKernelGGL(k_diag_copy<2>, dim3(blocks), dim3(256), 0, nullptr, src, dst, nvec);
         (void)hipEventRecord(e1, nullptr);
         float t = 0.f;
         if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -1,5 +1,6 @@
 // Host side of the single-LP solver: context lifetime, the captured pivot
 // graph, and the C entry points lp_create ... lp_destroy.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,16 +36,21 @@ struct UpdateConfig {
     int nt;         // bit 0: non-temporal loads, bit 1: non-temporal stores
 };
 
-// Small m: one chunk of 64 or 128 pairs; otherwise 256 threads with `rv`
-// pairs each.
-UpdateConfig pick_update_config(int32_t m, int cols, int rv) {
+// Small m: one chunk of 64 or 128 pairs; otherwise `block` threads (256 by
+// default) with `rv` pairs each. Defaults from a sweep on MI355X: one column
+// and one pair per thread for tall tableaux (the most independent, shortest
+// streams: 5.5 TB/s at m = 8000), four columns per workgroup below 4096 rows.
+UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
     if (nvec <= 128) {
-        const int block = nvec <= 64 ? 64 : 128;
-        return {block, cols, 1, 1, 0};
+        const int b = nvec <= 64 ? 64 : 128;
+        return {b, cols > 0 ? cols : 4, 1, 1, 0};
     }
-    const int64_t span = 256 * (int64_t)rv;
-    return {256, cols, rv, (int)((nvec + span - 1) / span), 0};
+    if (cols <= 0) cols = nvec > 2048 ? 1 : 4;
+    if (rv <= 0) rv = 1;
+    if (block <= 0) block = 256;
+    const int64_t span = block * (int64_t)rv;
+    return {block, cols, rv, (int)((nvec + span - 1) / span), 0};
 }
 
 bool valid_cols(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
@@ -133,6 +139,9 @@ int validate_opts(const lp_options &o) {
     if (o.rows_per_thread != 0 && !valid_rv(o.rows_per_thread))
         return set_error(LP_E_INVAL, "rows_per_thread must be 0 (auto) or one of 1, 2, 4, 8");
     if (o.update_hints < 0 || o.update_hints > 3) return set_error(LP_E_INVAL, "update_hints must be in [0, 3]");
+    if (o.update_block != 0 && o.update_block != 64 && o.update_block != 128 && o.update_block != 256 &&
+        o.update_block != 512 && o.update_block != 1024)
+        return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
     return LP_OK;
 }
@@ -159,9 +168,15 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->eps_p = o.eps_pivot;
     h->max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m + n);
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
-    h->ucfg = pick_update_config(m, o.cols_per_block > 0 ? o.cols_per_block : 4,
-                                 o.rows_per_thread > 0 ? o.rows_per_thread : 1);
+    h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block);
     if (h->ucfg.block == 256) h->ucfg.nt = o.update_hints & 3;
+    const bool big_block_ok = h->ucfg.block == 256 || (h->ucfg.cols <= 2 && h->ucfg.rv <= 2) ||
+                              (h->ucfg.block <= 128 && h->ucfg.rv == 1 && h->ucfg.rowchunks == 1);
+    if ((o.update_block > 0 && h->ucfg.block != o.update_block) || !big_block_ok) {
+        delete h;
+        return set_error(LP_E_INVAL, "update_block needs m + 1 > 256, and values other than 256 need "
+                                     "cols_per_block and rows_per_thread <= 2");
+    }
     h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
     h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
     h->use_graph = o.use_graph != 0;
@@ -259,24 +274,42 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     return LP_OK;
 }
 
-void launch_update(lp_ctx *h) {
+// Enqueues the update kernel; with events, the dispatch itself records them
+// at its start and end (timing mode).
+void launch_update(lp_ctx *h, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const UpdateConfig &u = h->ucfg;
     const dim3 grid((unsigned)((int64_t)u.rowchunks * h->nparts)), block((unsigned)u.block);
 #define LP_UPD(B, C, V, NL, NS)                                                                        \
     if (u.block == B && u.cols == C && u.rv == V && u.nt == (NL | (NS << 1))) {                        \
-        hipLaunchKernelGGL((k_update<B, C, V, NL, NS>), grid, block, 0, h->stream, h->T, h->ld, h->m,  \
-                           h->n, u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);                  \
+        if (e0)                                                                                        \
+            hipExtLaunchKernelGGL((k_update<B, C, V, NL, NS>), grid, block, 0, h->stream, e0, e1, 0,   \
+                                  h->T, h->ld, h->m, h->n, u.rowchunks, (const int32_t *)h->cols,      \
+                                  (const double *)h->Rl, (const double *)h->F,                         \
+                                  (const DevState *)h->st, h->parts);                                  \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_update<B, C, V, NL, NS>), grid, block, 0, h->stream, h->T, h->ld,    \
+                               h->m, h->n, u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);        \
         return;                                                                                        \
     }
 #define LP_UPD_V(C, V) LP_UPD(256, C, V, 0, 0) LP_UPD(256, C, V, 1, 0) LP_UPD(256, C, V, 0, 1) \
     LP_UPD(256, C, V, 1, 1)
 #define LP_UPD_C(C) LP_UPD(64, C, 1, 0, 0) LP_UPD(128, C, 1, 0, 0) LP_UPD_V(C, 1) LP_UPD_V(C, 2) \
     LP_UPD_V(C, 4) LP_UPD_V(C, 8)
+#define LP_UPD_B(B) LP_UPD(B, 1, 1, 0, 0) LP_UPD(B, 1, 2, 0, 0) LP_UPD(B, 2, 1, 0, 0) LP_UPD(B, 2, 2, 0, 0)
+    LP_UPD_B(512)
+    LP_UPD_B(1024)
+    LP_UPD(64, 1, 2, 0, 0)
+    LP_UPD(64, 2, 2, 0, 0)
+    LP_UPD(64, 2, 1, 0, 0)
+    LP_UPD(128, 1, 2, 0, 0)
+    LP_UPD(128, 2, 2, 0, 0)
+    LP_UPD(128, 2, 1, 0, 0)
     LP_UPD_C(1)
     LP_UPD_C(2)
     LP_UPD_C(4)
     LP_UPD_C(8)
     LP_UPD_C(16)
+#undef LP_UPD_B
 #undef LP_UPD_C
 #undef LP_UPD_V
 #undef LP_UPD
@@ -287,10 +320,13 @@ void launch_update(lp_ctx *h) {
 int enqueue_chunk(lp_ctx *h, int slot) {
     for (int k = 0; k < h->chunk; ++k) {
         hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts, h->st,
-                           h->F, h->basis, h->log_r, h->log_q, h->cols, h->pos, h->Rl, h->cols_done);
-        if (h->timing) LP_HIP_CHECK(hipEventRecord(h->ev_upd[slot][2 * k], h->stream));
-        launch_update(h);
-        if (h->timing) LP_HIP_CHECK(hipEventRecord(h->ev_upd[slot][2 * k + 1], h->stream));
+                           h->F, h->basis, h->log_r, h->log_q, h->pos);
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)(((int64_t)h->n + 2 + 255) / 256)), dim3(256), 0, h->stream, h->T,
+                           h->ld, h->m, h->n, h->st, h->cols, h->pos, h->Rl, h->cols_done);
+        if (h->timing)
+            launch_update(h, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]);
+        else
+            launch_update(h);
     }
     LP_HIP_CHECK(hipGetLastError());
     return LP_OK;
@@ -536,6 +572,10 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
     info->ld = h->ld;
     info->tableau_bytes = lp_tableau_bytes(h->m, h->n);
     info->tableau = h->T;
+    info->update_block = h->ucfg.block;
+    info->update_cols = h->ucfg.cols;
+    info->update_rows = h->ucfg.rv;
+    info->update_hints = h->ucfg.nt;
     return LP_OK;
 }
 

@@ -89,13 +89,11 @@ static __global__ void k_init(DevState *st, DevState init, int32_t *__restrict__
 
 static __global__ void k_set_stop(DevState *st, int64_t stop_at) { st->stop_at = stop_at; }
 
-// Steps 1 and 2 for the next pivot, and the inputs of Step 3; one workgroup
-// of 1024 threads.
+// Steps 1 and 2 for the next pivot; one workgroup of 1024 threads.
 //   Step 1   final stage of the argmin over the update's per-group partials
 //            (a scan of row 0 before the first pivot);
-//   Step 2   ratio test over column q;
-//   Step 3   inputs: F = column q, the rewrite list with q and the leaving
-//            column swapped, and R (normalised pivot row) by list position.
+//   Step 2   ratio test over column q, copying column q to F on the way;
+//   then the decision (r, q, p, leaving column), the basis and the log.
 // Basic columns other than the leaving one are exact unit vectors with a zero
 // in row r and in row 0, so leaving them out of R, of the rewrite and of the
 // Step 1 scan changes no value and no decision.
@@ -103,11 +101,9 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
                                                 const ArgMin *__restrict__ parts, DevState *__restrict__ st,
                                                 double *__restrict__ F, int32_t *__restrict__ basis,
                                                 int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
-                                                int32_t *__restrict__ cols, int32_t *__restrict__ pos,
-                                                double *__restrict__ Rl, unsigned long long *__restrict__ cols_done) {
+                                                const int32_t *__restrict__ pos) {
     __shared__ double sv[16];
     __shared__ int32_t si[16];
-    __shared__ int32_t scount[16];
     const int tid = threadIdx.x, nt = blockDim.x;
     const DevState s = *st;
     if (s.status != LP_RUNNING || s.pivots >= s.stop_at) {
@@ -115,16 +111,6 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         return;
     }
     const int64_t W = (int64_t)n + m + 1;
-
-    // Rewrite-list entries this thread reads in Step 3's inputs: loaded now,
-    // off the critical path (they do not depend on q or r).
-    constexpr int kPre = 8;
-    int32_t cpre[kPre];
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) {
-        const int32_t t = tid + k * nt;
-        cpre[k] = t < n ? cols[t] : 0;
-    }
 
     // Step 1: most negative objective-row entry, lowest column on ties.
     double v = __builtin_inf();
@@ -190,37 +176,14 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         return;
     }
 
-    // Inputs of Step 3. The leaving column takes q's place in the list.
-    const double p = colq[r];
-    const int32_t leave = basis[r - 1];
-    int32_t nz = 0;
-    auto stage_R = [&](int32_t t, int32_t listed) {
-        const int32_t j = t == pq ? leave : (t == n ? q : (t == n + 1 ? (int32_t)(W - 1) : listed));
-        const double R = T[(int64_t)j * ld + r] / p;
-        Rl[t] = R;
-        nz += R != 0.0;
-    };
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) {
-        const int32_t t = tid + k * nt;
-        if (t < n + 2) stage_R(t, cpre[k]);
-    }
-    for (int32_t t = tid + kPre * nt; t < n + 2; t += nt) stage_R(t, t < n ? cols[t] : 0);
-    // count of rewritten columns (nonzero R), summed over the block
-    for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
-    if ((tid & 63) == 0) scount[tid >> 6] = nz;
-    __syncthreads();  // also orders every read of cols/pos above before the writes below
+    // Decision made: the staging kernel prepares Step 3's inputs.
     if (tid == 0) {
-        int32_t tot = 0;
-        for (int w = 0; w < (nt + 63) / 64; ++w) tot += scount[w];
-        *cols_done += (unsigned long long)tot;
-        cols[pq] = leave;
-        pos[leave] = pq;
-        pos[q] = -1;
-        cols[n] = q;
+        const int32_t leave = basis[r - 1];
         st->r = r;
         st->q = q;
-        st->p = p;
+        st->p = colq[r];
+        st->leave = leave;
+        st->pq = pq;
         basis[r - 1] = q;
         if (s.pivots < s.log_cap) {
             log_r[s.pivots] = r;
@@ -229,6 +192,36 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         st->pivots = s.pivots + 1;
         st->fresh = 0;
         st->go = 1;
+    }
+}
+
+// Inputs of Step 3 for the pivot k_select decided, one list position per
+// thread: R_t = T[r][j_t] / p for the rewrite list with the leaving column in
+// the entering column's place, and the count of nonzero R. Workgroup 0 then
+// swaps the two columns in the list itself; no thread of this kernel reads
+// the two entries it writes (positions pq and n), so the swap is race-free.
+static __global__ __launch_bounds__(256) void k_stage(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                     const DevState *__restrict__ st, int32_t *__restrict__ cols,
+                                                     int32_t *__restrict__ pos, double *__restrict__ Rl,
+                                                     unsigned long long *__restrict__ cols_done) {
+    if (!st->go) return;
+    const int32_t r = st->r, q = st->q, leave = st->leave, pq = st->pq;
+    const double p = st->p;
+    const int32_t t = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+    bool nz = false;
+    if (t < n + 2) {
+        const int32_t j = t == pq ? leave : (t == n ? q : (t == n + 1 ? n + m : cols[t]));
+        const double R = T[(int64_t)j * ld + r] / p;
+        Rl[t] = R;
+        nz = R != 0.0;
+    }
+    const unsigned long long cnt = __popcll(__ballot(nz));
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(cols_done, cnt);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cols[pq] = leave;
+        pos[leave] = pq;
+        pos[q] = -1;
+        cols[n] = q;
     }
 }
 

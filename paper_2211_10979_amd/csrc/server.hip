@@ -187,7 +187,7 @@ static __global__ void k_extract_one(BatchDesc d, double *out) {
 
 struct lp_server {
     int device = 0;
-    hipStream_t sched = nullptr, copy = nullptr;
+    hipStream_t sched = nullptr;
     size_t budget = 0;
     int32_t max_slots = 0;
     lp_options opt{};
@@ -196,7 +196,9 @@ struct lp_server {
     size_t lds = 0;
     int64_t step_budget = 8;
     Arena *arena = nullptr;
-    double *staging = nullptr;  // device staging of one LP's A, b, c
+    static constexpr int kAdmitters = 4;
+    double *staging[kAdmitters] = {};  // device staging of one LP's A, b, c per admission worker
+    hipStream_t copy_streams[kAdmitters] = {};
     size_t staging_bytes = 0;
     BatchDesc *desc = nullptr;
     BatchState *state = nullptr;
@@ -220,7 +222,7 @@ struct lp_server {
     int64_t submitted = 0, completed = 0, rejected = 0, ticks = 0;
     std::vector<double> lat_ms;
     int last_error = LP_OK;
-    std::thread admit_thr, sched_thr;
+    std::thread admit_thr[kAdmitters], sched_thr;
 };
 
 namespace {
@@ -230,9 +232,13 @@ void server_fail(lp_server *s, int code) {
     if (!s->last_error) s->last_error = code;
 }
 
-// Admission: allocate, copy, build, publish the descriptor; then ready.
-void admission_loop(lp_server *s) {
+// Admission worker `w`: allocate, copy, build, publish the descriptor; then
+// ready. Workers take requests from the queue in arrival order; each has its
+// own copy stream and staging buffer, so their copies and builds overlap.
+void admission_loop(lp_server *s, int w) {
     DeviceGuard g(s->device);
+    hipStream_t copy = s->copy_streams[w];
+    double *staging = s->staging[w];
     for (;;) {
         Request *r = nullptr;
         Layout L{};
@@ -293,18 +299,18 @@ void admission_loop(lp_server *s) {
         init.max_pivots = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
         init.eps_d = s->opt.eps_dual;
         init.eps_p = s->opt.eps_pivot;
-        const double *A = s->staging, *bb = A + (int64_t)m * n, *c = bb + m;
-        bool ok = hipMemcpyAsync(s->staging, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice,
-                                 s->copy) == hipSuccess;
+        const double *A = staging, *bb = A + (int64_t)m * n, *c = bb + m;
+        bool ok = hipMemcpyAsync(staging, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 copy) == hipSuccess;
         dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((d.ld + kBuildTile - 1) / kBuildTile));
-        hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, s->copy, d.T, d.ld, m, n, A, c);
+        hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, copy, d.T, d.ld, m, n, A, c);
         const int64_t nslack = (int64_t)(m + 1) * (d.ld / 2);
-        hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, s->copy, d.T, d.ld,
-                           m, n, bb);
-        hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, s->copy, d, s->state + r->slot, init);
-        ok = ok && hipMemcpyAsync(s->desc + r->slot, &d, sizeof(BatchDesc), hipMemcpyHostToDevice, s->copy) ==
+        hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, copy, d.T, d.ld, m,
+                           n, bb);
+        hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, copy, d, s->state + r->slot, init);
+        ok = ok && hipMemcpyAsync(s->desc + r->slot, &d, sizeof(BatchDesc), hipMemcpyHostToDevice, copy) ==
                        hipSuccess;
-        ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(s->copy) == hipSuccess;
+        ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(copy) == hipSuccess;
         std::vector<double>().swap(r->in);
         if (!ok) {  // the request fails; its memory and slot are returned
             s->arena->release(r->block, r->bytes);
@@ -433,18 +439,21 @@ void free_server(lp_server *s) {
     if (!s) return;
     DeviceGuard g(s->device);
     if (s->sched) (void)hipStreamSynchronize(s->sched);
-    if (s->copy) (void)hipStreamSynchronize(s->copy);
+    for (auto cs : s->copy_streams)
+        if (cs) (void)hipStreamSynchronize(cs);
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    for (void *p : {(void *)s->staging, (void *)s->desc, (void *)s->state, (void *)s->order, (void *)s->norder,
-                    (void *)s->head})
+    for (void *p : {(void *)s->desc, (void *)s->state, (void *)s->order, (void *)s->norder, (void *)s->head})
+        if (p) (void)hipFree(p);
+    for (auto p : s->staging)
         if (p) (void)hipFree(p);
     if (s->st_pin) (void)hipHostFree(s->st_pin);
     if (s->order_pin) (void)hipHostFree(s->order_pin);
     delete s->arena;
     for (auto &kv : s->reqs) delete kv.second;
     if (s->sched) (void)hipStreamDestroy(s->sched);
-    if (s->copy) (void)hipStreamDestroy(s->copy);
+    for (auto cs : s->copy_streams)
+        if (cs) (void)hipStreamDestroy(cs);
     delete s;
 }
 
@@ -488,7 +497,8 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
         }
         return LP_OK;
     };
-    if (int rc = dmalloc((void **)&s->staging, s->staging_bytes)) return fail(rc);
+    for (auto &p : s->staging)
+        if (int rc = dmalloc((void **)&p, s->staging_bytes)) return fail(rc);
     if (int rc = dmalloc((void **)&s->desc, (size_t)s->max_slots * sizeof(BatchDesc))) return fail(rc);
     if (int rc = dmalloc((void **)&s->state, (size_t)s->max_slots * sizeof(BatchState))) return fail(rc);
     if (int rc = dmalloc((void **)&s->order, (size_t)s->max_slots * sizeof(int32_t))) return fail(rc);
@@ -500,9 +510,11 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
             hipSuccess)
         return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
     std::memset(s->st_pin, 0, (size_t)s->max_slots * sizeof(BatchState));
-    if (hipStreamCreateWithFlags(&s->sched, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) != hipSuccess)
+    if (hipStreamCreateWithFlags(&s->sched, hipStreamNonBlocking) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "hipStreamCreate failed"));
+    for (auto &cs : s->copy_streams)
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "hipStreamCreate failed"));
     if (hipMemset(s->state, 0, (size_t)s->max_slots * sizeof(BatchState)) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (int rc = set_batch_lds_limit(s->lds)) return fail(rc);
@@ -533,7 +545,7 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
         return fail(set_error(LP_E_DEVICE, "hipGraphInstantiate failed"));
     s->slots.assign((size_t)s->max_slots, nullptr);
     for (int i = s->max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
-    s->admit_thr = std::thread(admission_loop, s);
+    for (int w = 0; w < lp_server::kAdmitters; ++w) s->admit_thr[w] = std::thread(admission_loop, s, w);
     s->sched_thr = std::thread(scheduler_loop, s);
     *out = s;
     return LP_OK;
@@ -664,7 +676,8 @@ void lp_server_destroy(lp_server *s) {
     }
     s->cv_admit.notify_all();
     s->cv_ready.notify_all();
-    if (s->admit_thr.joinable()) s->admit_thr.join();
+    for (auto &t : s->admit_thr)
+        if (t.joinable()) t.join();
     if (s->sched_thr.joinable()) s->sched_thr.join();
     free_server(s);
 }

@@ -53,6 +53,8 @@ class lp_options(ctypes.Structure):
         ("batch_block", ctypes.c_int32),
         ("batch_unroll", ctypes.c_int32),
         ("update_hints", ctypes.c_int32),
+        ("update_block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -74,6 +76,10 @@ class lp_info(ctypes.Structure):
         ("ld", ctypes.c_int64),
         ("tableau_bytes", ctypes.c_size_t),
         ("tableau", ctypes.c_void_p),
+        ("update_block", ctypes.c_int32),
+        ("update_cols", ctypes.c_int32),
+        ("update_rows", ctypes.c_int32),
+        ("update_hints", ctypes.c_int32),
     ]
 
 

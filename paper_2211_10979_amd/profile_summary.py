@@ -24,7 +24,8 @@ from collections import defaultdict
 
 
 def _short(name: str) -> str:
-    return name.split("(")[0].replace("void ", "").strip()
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0].strip()
 
 
 def kernel_stats_csv(path):
