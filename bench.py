@@ -267,29 +267,33 @@ def bench_serve(args, lpgpu, lpgen):
         solo_res.append((res, x))
     solo_makespan = finish - arrivals[0]
 
-    log("serving: server")
-    s = lpgpu.lp_server_create(int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
-    tickets = [None] * count
-    try:
-        t0 = time.perf_counter()
+    def serve(arr_times):
+        s = lpgpu.lp_server_create(int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
+        tickets = [None] * count
+        try:
+            t0 = time.perf_counter()
 
-        def submitter():
-            for k, (lp, arr) in enumerate(zip(lps, arrivals)):
-                wait = arr - arrivals[0] - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(wait)
-                tickets[k] = lpgpu.lp_server_submit(s, lp.A, lp.b, lp.c)
+            def submitter():
+                for k, (lp, arr) in enumerate(zip(lps, arr_times)):
+                    wait = arr - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                    tickets[k] = lpgpu.lp_server_submit(s, lp.A, lp.b, lp.c)
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        th.join()
-        served = []
-        for k, lp in enumerate(lps):
-            served.append(lpgpu.lp_server_wait(s, tickets[k], lp.m, lp.n))
-        makespan = time.perf_counter() - t0
-        st = lpgpu.lp_server_get_stats(s)
-    finally:
-        lpgpu.lp_server_destroy(s)
+            th = threading.Thread(target=submitter)
+            th.start()
+            th.join()
+            out = [lpgpu.lp_server_wait(s, tickets[k], lp.m, lp.n) for k, lp in enumerate(lps)]
+            span = time.perf_counter() - t0
+            st = lpgpu.lp_server_get_stats(s)
+        finally:
+            lpgpu.lp_server_destroy(s)
+        return out, span, st
+
+    log("serving: server, Poisson arrivals")
+    served, makespan, st = serve(arrivals - arrivals[0])
+    log("serving: server, all requests at once")
+    burst, burst_span, burst_st = serve(np.zeros(count))
     same = all(sr[0]["pivots"] == so[0]["pivots"] and np.array_equal(sr[1], so[1])
                for sr, so in zip(served, solo_res))
     cert = all(certify(lp.A, lp.b, lp.c, x, y, r["objective"])[0] for (r, x, y), lp in zip(served[:200], lps))
@@ -302,7 +306,12 @@ def bench_serve(args, lpgpu, lpgen):
                 one_at_a_time_solves_per_s=round(count / solo_makespan, 1),
                 one_at_a_time_p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3),
                 one_at_a_time_p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3),
-                identical_to_one_at_a_time=bool(same), certificates_ok_first_200=bool(cert))
+                saturated_solves_per_s=round(count / burst_span, 1),
+                saturated_p50_ms=round(burst_st["p50_ms"], 3), saturated_p99_ms=round(burst_st["p99_ms"], 3),
+                saturated_peak_resident_gb=round(burst_st["peak_bytes"] / (1 << 30), 3),
+                identical_to_one_at_a_time=bool(same and all(
+                    b[0]["pivots"] == so[0]["pivots"] and np.array_equal(b[1], so[1]) for b, so in zip(burst, solo_res))),
+                certificates_ok_first_200=bool(cert))
 
 
 def cpu_baseline(args, lp, gpu_log):

@@ -34,8 +34,12 @@ size_t batch_lds_bytes(int32_t m, int32_t n) {
 }
 
 bool batch_fits(int32_t m, int32_t n, size_t lds_limit) {
+    return batch_size_ok(m, n) && batch_lds_bytes(m, n) <= lds_limit;
+}
+
+bool batch_size_ok(int32_t m, int32_t n) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
-    return nvec < 4096 && ((int64_t)n + 2) * nvec < (int64_t)1 << 24 && batch_lds_bytes(m, n) <= lds_limit;
+    return nvec < 4096 && ((int64_t)n + 2) * nvec < (int64_t)1 << 24;
 }
 
 uint64_t nvec_magic(int32_t nvec) { return (((uint64_t)1 << 36) + (uint64_t)nvec - 1) / (uint64_t)nvec; }
@@ -178,6 +182,7 @@ struct lp_batch {
     int32_t *ints = nullptr;     // basis, lists, logs
     double *inputs = nullptr;    // A, b, c of every LP, kept for rebuilds
     double *out = nullptr;       // x, y, objective of every LP
+    double *scratch = nullptr;   // global work areas of LPs whose F/R exceed the LDS limit
     int64_t *out_off_dev = nullptr;
     BatchDesc *desc = nullptr;
     BatchState *state = nullptr;
@@ -209,7 +214,8 @@ void free_batch(lp_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (void *p : {(void *)b->tab, (void *)b->ints, (void *)b->inputs, (void *)b->out, (void *)b->out_off_dev,
+    for (void *p : {(void *)b->tab, (void *)b->ints, (void *)b->inputs, (void *)b->out, (void *)b->scratch,
+                    (void *)b->out_off_dev,
                     (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->norder, (void *)b->head,
                     (void *)b->tile_lp, (void *)b->tile_first, (void *)b->in_off_dev})
         if (p) (void)hipFree(p);
@@ -295,11 +301,11 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     int ndev = 0;
     LP_HIP_CHECK(hipGetDeviceCount(&ndev));
     if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
-    const size_t lds_limit = device_lds_limit(o.device);
+    const size_t lds_limit = std::min<size_t>(device_lds_limit(o.device), 64 * 1024);
     for (int32_t k = 0; k < count; ++k) {
         if (m[k] < 1 || n[k] < 1 || !A[k] || !bv[k] || !cv[k])
             return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": bad size or NULL input");
-        if (!batch_fits(m[k], n[k], lds_limit))
+        if (!batch_size_ok(m[k], n[k]))
             return set_error(LP_E_INVAL, "LP " + std::to_string(k) + " is too large for the batched kernel");
         for (int64_t t = 0; t < (int64_t)m[k] * n[k]; ++t)
             if (!std::isfinite(A[k][t])) return set_error(LP_E_INVAL, "LP " + std::to_string(k) + ": non-finite A");
@@ -334,8 +340,8 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
 
     // layout
-    int64_t tab_total = 0, int_total = 0, in_total = 0, out_total = 0;
-    std::vector<int64_t> tab_off(count), int_off(count), logcap(count);
+    int64_t tab_total = 0, int_total = 0, in_total = 0, out_total = 0, scr_total = 0;
+    std::vector<int64_t> tab_off(count), int_off(count), logcap(count), scr_off(count, -1);
     b->ld.resize(count);
     b->out_off.resize(count);
     b->in_off.resize(count);
@@ -354,7 +360,12 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         in_total += (int64_t)m[k] * n[k] + m[k] + n[k];
         b->out_off[k] = out_total;
         out_total += (int64_t)n[k] + m[k] + 1;
-        b->lds = std::max(b->lds, batch_lds_bytes(m[k], n[k]));
+        if (batch_lds_bytes(m[k], n[k]) <= lds_limit) {
+            b->lds = std::max(b->lds, batch_lds_bytes(m[k], n[k]));
+        } else {
+            scr_off[k] = scr_total;
+            scr_total += ((int64_t)batch_lds_bytes(m[k], n[k]) + 255) / 256 * 32;  // in doubles, 256-byte aligned
+        }
         mmax = std::max(mmax, m[k]);
         nmax = std::max(nmax, n[k]);
     }
@@ -369,6 +380,8 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     if (int rc = dmalloc((void **)&b->ints, int_total * sizeof(int32_t))) return fail(rc);
     if (int rc = dmalloc((void **)&b->inputs, in_total * sizeof(double))) return fail(rc);
     if (int rc = dmalloc((void **)&b->out, out_total * sizeof(double))) return fail(rc);
+    if (scr_total)
+        if (int rc = dmalloc((void **)&b->scratch, scr_total * sizeof(double))) return fail(rc);
     if (int rc = dmalloc((void **)&b->out_off_dev, count * sizeof(int64_t))) return fail(rc);
     if (int rc = dmalloc((void **)&b->desc, count * sizeof(BatchDesc))) return fail(rc);
     if (int rc = dmalloc((void **)&b->state, count * sizeof(BatchState))) return fail(rc);
@@ -393,7 +406,7 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         d.nvec = (m[k] + 2) / 2;
         d.magic = nvec_magic(d.nvec);
         d.pad = 0;
-        d.scratch = nullptr;
+        d.scratch = scr_off[k] >= 0 ? b->scratch + scr_off[k] : nullptr;
     }
     // inputs, staged through one host buffer
     {

@@ -22,6 +22,8 @@ extern const int kNumBatchShapes;
 size_t batch_lds_bytes(int32_t m, int32_t n);
 // Whether an LP can run in the batched kernel under a per-workgroup LDS limit.
 bool batch_fits(int32_t m, int32_t n, size_t lds_limit);
+// Size limits of the batched kernel's (column, row pair) item split.
+bool batch_size_ok(int32_t m, int32_t n);
 uint64_t nvec_magic(int32_t nvec);
 size_t device_lds_limit(int device);
 int device_cus(int device);

@@ -142,6 +142,11 @@ struct Request {
     double *out = nullptr;
 };
 
+// LPs whose tableau exceeds this go to the large-LP lane: one workgroup per
+// LP would take milliseconds per pivot there, while the single-LP kernels
+// spread each pivot over the whole GPU.
+constexpr size_t kLargeTableauBytes = (size_t)16 << 20;
+
 // Device bytes of one resident LP: tableau, lists and logs, extraction
 // output, and the global work area when F/R do not fit in LDS.
 struct Layout {
@@ -223,6 +228,15 @@ struct lp_server {
     std::vector<double> lat_ms;
     int last_error = LP_OK;
     std::thread admit_thr[kAdmitters], sched_thr;
+    // large-LP lane: single-LP multi-workgroup kernels on their own streams
+    static constexpr int kLargeWorkers = 2;
+    std::deque<Request *> pending_large;
+    int large_busy = 0;
+    hipStream_t large_streams[kLargeWorkers] = {};
+    double *large_staging[kLargeWorkers] = {};
+    DevState *large_pin[kLargeWorkers] = {};  // two pinned state slots per worker
+    std::thread large_thr[kLargeWorkers];
+    int64_t large_done = 0;
 };
 
 namespace {
@@ -387,6 +401,213 @@ void harvest(lp_server *s, const std::vector<int> &fin) {
     s->cv_done.notify_all();
 }
 
+
+// ---- large-LP lane -------------------------------------------------------
+
+// Arena layout of one large LP for the single-LP kernels.
+struct LargeLayout {
+    size_t tab, F, parts, st, basis, logs, cols, pos, Rl, cnt, out, total;
+    int64_t log_cap;
+    int nparts, cols_per_block, block, rowchunks;
+};
+
+LargeLayout large_layout_of(int32_t m, int32_t n, int64_t max_pivots, bool record) {
+    LargeLayout L{};
+    const int64_t ld = padded_ld(m), W = (int64_t)n + m + 1, nvec = ((int64_t)m + 2) / 2;
+    L.log_cap = record ? std::min<int64_t>(max_pivots, 4 * ((int64_t)m + n) + 64) : 0;
+    L.block = nvec <= 64 ? 64 : (nvec <= 128 ? 128 : 256);
+    L.cols_per_block = nvec > 2048 ? 1 : 4;
+    L.rowchunks = (int)((nvec + L.block - 1) / L.block);
+    L.nparts = (int)(((int64_t)n + 2 + L.cols_per_block - 1) / L.cols_per_block);
+    L.tab = align_up((size_t)(ld * W) * sizeof(double));
+    L.F = align_up((size_t)ld * sizeof(double));
+    L.parts = align_up((size_t)L.nparts * sizeof(ArgMin));
+    L.st = align_up(sizeof(DevState));
+    L.basis = align_up((size_t)m * sizeof(int32_t));
+    L.logs = align_up((size_t)(2 * L.log_cap + 1) * sizeof(int32_t));
+    L.cols = align_up(((size_t)n + 2) * sizeof(int32_t));
+    L.pos = align_up(((size_t)n + m) * sizeof(int32_t));
+    L.Rl = align_up(((size_t)n + 2) * sizeof(double));
+    L.cnt = align_up(sizeof(unsigned long long));
+    L.out = align_up(((size_t)n + m + 1) * sizeof(double));
+    L.total = L.tab + L.F + L.parts + L.st + L.basis + L.logs + L.cols + L.pos + L.Rl + L.cnt + L.out;
+    return L;
+}
+
+struct LargeLP {
+    double *T, *F, *Rl, *out;
+    ArgMin *parts;
+    DevState *st;
+    int32_t *basis, *log_r, *log_q, *cols, *pos;
+    unsigned long long *cnt;
+};
+
+template <int B, int C>
+void large_update(const LargeLayout &L, hipStream_t st, const LargeLP &d, int64_t ld, int32_t m, int32_t n) {
+    hipLaunchKernelGGL((k_update<B, C, 1, 0, 0>), dim3((unsigned)((int64_t)L.rowchunks * L.nparts)), dim3(B), 0, st,
+                       d.T, ld, m, n, L.rowchunks, d.cols, d.Rl, d.F, d.st, d.parts);
+}
+
+void large_pivot(const LargeLayout &L, hipStream_t st, const LargeLP &d, int64_t ld, int32_t m, int32_t n) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st, d.T, ld, m, n, d.parts, d.st, d.F, d.basis, d.log_r,
+                       d.log_q, d.pos);
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)(((int64_t)n + 2 + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
+                       d.st, d.cols, d.pos, d.Rl, d.cnt);
+    if (L.block == 256 && L.cols_per_block == 1)
+        large_update<256, 1>(L, st, d, ld, m, n);
+    else if (L.block == 256)
+        large_update<256, 4>(L, st, d, ld, m, n);
+    else if (L.block == 128)
+        large_update<128, 4>(L, st, d, ld, m, n);
+    else
+        large_update<64, 4>(L, st, d, ld, m, n);
+}
+
+// Builds, solves and harvests one large LP on worker w's stream. Pivots go
+// in chunks of 4, two chunks in flight, the state read back through pinned
+// memory between them.
+bool run_large(lp_server *s, int w, Request *r, const LargeLayout &L, char *block) {
+    hipStream_t st = s->large_streams[w];
+    const int32_t m = r->m, n = r->n;
+    const int64_t ld = padded_ld(m);
+    char *p = block;
+    LargeLP d{};
+    d.T = (double *)p;
+    p += L.tab;
+    d.F = (double *)p;
+    p += L.F;
+    d.parts = (ArgMin *)p;
+    p += L.parts;
+    d.st = (DevState *)p;
+    p += L.st;
+    d.basis = (int32_t *)p;
+    p += L.basis;
+    d.log_r = (int32_t *)p;
+    d.log_q = d.log_r + L.log_cap;
+    p += L.logs;
+    d.cols = (int32_t *)p;
+    p += L.cols;
+    d.pos = (int32_t *)p;
+    p += L.pos;
+    d.Rl = (double *)p;
+    p += L.Rl;
+    d.cnt = (unsigned long long *)p;
+    p += L.cnt;
+    d.out = (double *)p;
+
+    double *stg = s->large_staging[w];
+    const double *A = stg, *bb = A + (int64_t)m * n, *c = bb + m;
+    bool ok = hipMemcpyAsync(stg, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice, st) ==
+              hipSuccess;
+    dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
+    hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, st, d.T, ld, m, n, A, c);
+    const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
+    hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n, bb);
+    DevState init{};
+    init.status = LP_RUNNING;
+    init.stop_at = INT64_MAX;
+    init.max_pivots = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
+    init.log_cap = L.log_cap;
+    init.eps_d = s->opt.eps_dual;
+    init.eps_p = s->opt.eps_pivot;
+    init.fresh = 1;
+    init.nparts = L.nparts;
+    const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, st, d.st, init, d.basis, m, n,
+                       d.F, ld, d.cols, d.pos, d.cnt);
+    ok = ok && hipGetLastError() == hipSuccess;
+
+    DevState *pin = s->large_pin[w];
+    constexpr int kChunk = 4;
+    auto chunk = [&](int slot) {
+        for (int k = 0; k < kChunk; ++k) large_pivot(L, st, d, ld, m, n);
+        return hipMemcpyAsync(&pin[slot], d.st, sizeof(DevState), hipMemcpyDeviceToHost, st) == hipSuccess;
+    };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ok = ok && hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) == hipSuccess;
+    int slot = 0;
+    ok = ok && chunk(0) && hipEventRecord(ev[0], st) == hipSuccess;
+    while (ok) {
+        ok = chunk(slot ^ 1) && hipEventRecord(ev[slot ^ 1], st) == hipSuccess &&
+             hipEventSynchronize(ev[slot]) == hipSuccess;
+        if (!ok || pin[slot].status != LP_RUNNING) break;
+        slot ^= 1;
+    }
+    hipLaunchKernelGGL(k_extract, dim3(1), dim3(1024), 0, st, d.T, ld, m, n, d.basis, d.out);
+    std::vector<double> tmp((size_t)n + m + 1);
+    DevState fin{};
+    ok = ok && hipMemcpyAsync(tmp.data(), d.out, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st) ==
+                   hipSuccess &&
+         hipMemcpyAsync(&fin, d.st, sizeof(DevState), hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+    if (ok) {
+        const int64_t k = std::min<int64_t>(fin.pivots, L.log_cap);
+        r->rows.resize((size_t)k);
+        r->cols.resize((size_t)k);
+        if (k > 0)
+            ok = hipMemcpy(r->rows.data(), d.log_r, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost) ==
+                     hipSuccess &&
+                 hipMemcpy(r->cols.data(), d.log_q, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess;
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipStreamSynchronize(st);
+    std::vector<double>().swap(r->in);  // the input copy has completed
+    r->x.assign(tmp.begin(), tmp.begin() + n);
+    r->y.assign(tmp.begin() + n, tmp.begin() + n + m);
+    r->objective = tmp[(size_t)n + m];
+    r->status = ok ? fin.status : LP_NUMERICAL;
+    r->pivots = fin.pivots;
+    return ok;
+}
+
+void large_loop(lp_server *s, int w) {
+    DeviceGuard g(s->device);
+    for (;;) {
+        Request *r = nullptr;
+        LargeLayout L{};
+        {
+            std::unique_lock<std::mutex> lock(s->mu);
+            s->cv_admit.wait(lock, [&] { return s->stopping || !s->pending_large.empty(); });
+            if (s->pending_large.empty()) return;  // stopping and drained
+            r = s->pending_large.front();
+            const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)r->m + r->n);
+            L = large_layout_of(r->m, r->n, maxp, s->opt.record_pivots != 0);
+            if (s->bytes_in_use + L.total > s->budget) {
+                s->cv_admit.wait_for(lock, std::chrono::milliseconds(2));
+                continue;
+            }
+            s->pending_large.pop_front();
+            s->bytes_in_use += L.total;
+            s->peak = std::max(s->peak, s->bytes_in_use);
+            s->large_busy++;
+        }
+        char *block = (char *)s->arena->alloc(L.total);
+        if (!block) {
+            std::lock_guard<std::mutex> lock(s->mu);
+            s->bytes_in_use -= L.total;
+            s->pending_large.push_front(r);
+            s->large_busy--;
+            std::this_thread::sleep_for(std::chrono::milliseconds(1));
+            continue;
+        }
+        const bool ok = run_large(s, w, r, L, block);
+        s->arena->release(block, L.total);
+        std::lock_guard<std::mutex> lock(s->mu);
+        if (!ok && !s->last_error) s->last_error = LP_E_DEVICE;
+        s->bytes_in_use -= L.total;
+        s->large_busy--;
+        r->t_done = Clock::now();
+        r->done = true;
+        s->completed++;
+        s->large_done++;
+        s->lat_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+        s->cv_done.notify_all();
+        s->cv_admit.notify_all();
+    }
+}
+
 void scheduler_loop(lp_server *s) {
     DeviceGuard g(s->device);
     std::vector<int> active;
@@ -447,6 +668,15 @@ void free_server(lp_server *s) {
         if (p) (void)hipFree(p);
     for (auto p : s->staging)
         if (p) (void)hipFree(p);
+    for (auto p : s->large_staging)
+        if (p) (void)hipFree(p);
+    for (auto p : s->large_pin)
+        if (p) (void)hipHostFree(p);
+    for (auto cs : s->large_streams)
+        if (cs) {
+            (void)hipStreamSynchronize(cs);
+            (void)hipStreamDestroy(cs);
+        }
     if (s->st_pin) (void)hipHostFree(s->st_pin);
     if (s->order_pin) (void)hipHostFree(s->order_pin);
     delete s->arena;
@@ -499,6 +729,14 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
     };
     for (auto &p : s->staging)
         if (int rc = dmalloc((void **)&p, s->staging_bytes)) return fail(rc);
+    for (auto &p : s->large_staging)
+        if (int rc = dmalloc((void **)&p, s->staging_bytes)) return fail(rc);
+    for (auto &p : s->large_pin)
+        if (hipHostMalloc((void **)&p, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+            return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
+    for (auto &cs : s->large_streams)
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "hipStreamCreate failed"));
     if (int rc = dmalloc((void **)&s->desc, (size_t)s->max_slots * sizeof(BatchDesc))) return fail(rc);
     if (int rc = dmalloc((void **)&s->state, (size_t)s->max_slots * sizeof(BatchState))) return fail(rc);
     if (int rc = dmalloc((void **)&s->order, (size_t)s->max_slots * sizeof(int32_t))) return fail(rc);
@@ -546,6 +784,7 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
     s->slots.assign((size_t)s->max_slots, nullptr);
     for (int i = s->max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     for (int w = 0; w < lp_server::kAdmitters; ++w) s->admit_thr[w] = std::thread(admission_loop, s, w);
+    for (int w = 0; w < lp_server::kLargeWorkers; ++w) s->large_thr[w] = std::thread(large_loop, s, w);
     s->sched_thr = std::thread(scheduler_loop, s);
     *out = s;
     return LP_OK;
@@ -566,7 +805,9 @@ int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const 
         if (!std::isfinite(c[j])) return set_error(LP_E_INVAL, "non-finite c");
     const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
     const Layout L = layout_of(m, n, maxp, s->opt.record_pivots != 0, s->lds);
-    if (L.total > s->budget) {
+    const size_t need = L.tab > kLargeTableauBytes ? large_layout_of(m, n, maxp, s->opt.record_pivots != 0).total
+                                                   : L.total;
+    if (need > s->budget) {
         std::lock_guard<std::mutex> lock(s->mu);
         s->rejected++;
         return set_error(LP_E_BUDGET, "LP larger than the server budget");
@@ -588,10 +829,13 @@ int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const 
         r->ticket = s->next_ticket++;
         r->t_submit = Clock::now();
         s->reqs[r->ticket] = r;
-        s->pending.push_back(r);
+        if (L.tab > kLargeTableauBytes)
+            s->pending_large.push_back(r);
+        else
+            s->pending.push_back(r);
         s->submitted++;
     }
-    s->cv_admit.notify_one();
+    s->cv_admit.notify_all();
     *ticket = r->ticket;
     return LP_OK;
 }
@@ -655,7 +899,7 @@ int lp_server_get_stats(lp_server *s, lp_server_stats *st) {
     st->rejected = s->rejected;
     int64_t resident = 0;
     for (auto *r : s->slots) resident += r != nullptr;
-    st->resident_now = resident + (int64_t)s->ready.size();
+    st->resident_now = resident + (int64_t)s->ready.size() + s->large_busy;
     st->bytes_in_use = s->bytes_in_use;
     st->peak_bytes = s->peak;
     st->ticks = s->ticks;
@@ -677,6 +921,8 @@ void lp_server_destroy(lp_server *s) {
     s->cv_admit.notify_all();
     s->cv_ready.notify_all();
     for (auto &t : s->admit_thr)
+        if (t.joinable()) t.join();
+    for (auto &t : s->large_thr)
         if (t.joinable()) t.join();
     if (s->sched_thr.joinable()) s->sched_thr.join();
     free_server(s);

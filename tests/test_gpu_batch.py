@@ -161,3 +161,17 @@ def test_autotuner_writes_and_reuses_its_cache(monkeypatch):
             assert lpgpu.lp_batch_get_shape(h2) == shape
         finally:
             lpgpu.lp_batch_destroy(h2)
+
+
+def test_lp_beyond_the_lds_limit_uses_a_global_work_area():
+    """F, R and the list of a 3300 x 3300 LP exceed 64 KiB: that LP keeps them
+    in global memory, next to LPs that use LDS, with the same pivots."""
+    big = lpgen.dense_lp(17, 3300, 3300)
+    lps = [(big.A, big.b, big.c)] + mixed_lps(19, 5, 20, 200)
+    say("batch with a 3300 x 3300 LP")
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_solve(h)
+        check_batch(h, lps)
+    finally:
+        lpgpu.lp_batch_destroy(h)
