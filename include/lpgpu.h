@@ -91,7 +91,9 @@ typedef struct {
     int32_t update_block;   /* update kernel threads per workgroup (64, 128, 256, 512, 1024;
                                0 = auto); values other than 256 need cols_per_block and
                                rows_per_thread <= 2 */
-    int32_t reserved;
+    int32_t update_grid_stride; /* > 0: grid-stride update kernel with this many workgroups per
+                               compute unit (block 64..512), one column per tile (default 0) */
+    int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
 } lp_options;
 
 typedef struct {

@@ -34,6 +34,8 @@ struct UpdateConfig {
     int rv;         // row pairs (double2) per thread and column
     int rowchunks;  // row chunks of block*rv pairs covering rows 0..m
     int nt;         // bit 0: non-temporal loads, bit 1: non-temporal stores
+    int gs_per_cu;  // > 0: grid-stride kernel with this many workgroups per CU
+    int gs_unroll;  // tiles in flight per thread in the grid-stride kernel
 };
 
 // Small m: one chunk of 64 or 128 pairs; otherwise `block` threads (256 by
@@ -44,13 +46,19 @@ UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
     if (nvec <= 128) {
         const int b = nvec <= 64 ? 64 : 128;
-        return {b, cols > 0 ? cols : 4, 1, 1, 0};
+        return {b, cols > 0 ? cols : 4, 1, 1, 0, 0, 0};
     }
     if (cols <= 0) cols = nvec > 2048 ? 1 : 4;
     if (rv <= 0) rv = 1;
     if (block <= 0) block = 256;
     const int64_t span = block * (int64_t)rv;
-    return {block, cols, rv, (int)((nvec + span - 1) / span), 0};
+    return {block, cols, rv, (int)((nvec + span - 1) / span), 0, 0, 0};
+}
+
+int device_cu_count(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
+    return prop.multiProcessorCount;
 }
 
 bool valid_cols(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
@@ -79,6 +87,7 @@ struct lp_ctx {
     double eps_d = 1e-9, eps_p = 1e-9;
     int64_t max_pivots = 0, log_cap = 0;
     int nparts = 0;
+    int cus = 256;
     UpdateConfig ucfg{};
     unsigned long long *cols_done = nullptr;  // device counter of rewritten columns
     int chunk = 8;
@@ -139,6 +148,11 @@ int validate_opts(const lp_options &o) {
     if (o.rows_per_thread != 0 && !valid_rv(o.rows_per_thread))
         return set_error(LP_E_INVAL, "rows_per_thread must be 0 (auto) or one of 1, 2, 4, 8");
     if (o.update_hints < 0 || o.update_hints > 3) return set_error(LP_E_INVAL, "update_hints must be in [0, 3]");
+    if (o.update_grid_stride < 0 || o.update_grid_stride > 32)
+        return set_error(LP_E_INVAL, "update_grid_stride must be in [0, 32]");
+    if (o.update_unroll != 0 && o.update_unroll != 1 && o.update_unroll != 2 && o.update_unroll != 4 &&
+        o.update_unroll != 8)
+        return set_error(LP_E_INVAL, "update_unroll must be 0 (auto) or one of 1, 2, 4, 8");
     if (o.update_block != 0 && o.update_block != 64 && o.update_block != 128 && o.update_block != 256 &&
         o.update_block != 512 && o.update_block != 1024)
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
@@ -170,6 +184,18 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
     h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block);
     if (h->ucfg.block == 256) h->ucfg.nt = o.update_hints & 3;
+    if (o.update_grid_stride > 0) {  // grid-stride kernel: one column, one pair per thread per tile
+        h->ucfg.cols = 1;
+        h->ucfg.rv = 1;
+        h->ucfg.rowchunks = (int)((((int64_t)m + 2) / 2 + h->ucfg.block - 1) / h->ucfg.block);
+        h->ucfg.gs_per_cu = o.update_grid_stride;
+        h->ucfg.gs_unroll = o.update_unroll > 0 ? o.update_unroll : 4;
+        h->ucfg.nt = 0;
+    }
+    if (h->ucfg.gs_per_cu > 0 && h->ucfg.block > 512) {
+        delete h;
+        return set_error(LP_E_INVAL, "the grid-stride update kernel takes at most 512 threads per workgroup");
+    }
     const bool big_block_ok = h->ucfg.block == 256 || (h->ucfg.cols <= 2 && h->ucfg.rv <= 2) ||
                               (h->ucfg.block <= 128 && h->ucfg.rv == 1 && h->ucfg.rowchunks == 1);
     if ((o.update_block > 0 && h->ucfg.block != o.update_block) || !big_block_ok) {
@@ -178,6 +204,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
                                      "cols_per_block and rows_per_thread <= 2");
     }
     h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
+    h->cus = device_cu_count(o.device);
     h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
     h->use_graph = o.use_graph != 0;
     h->timing = o.time_kernels != 0;
@@ -278,6 +305,27 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
 // at its start and end (timing mode).
 void launch_update(lp_ctx *h, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const UpdateConfig &u = h->ucfg;
+    if (u.gs_per_cu > 0) {
+        const dim3 ggrid((unsigned)(u.gs_per_cu * h->cus)), gblock((unsigned)u.block);
+#define LP_GS(B, U)                                                                                        \
+    if (u.block == B && u.gs_unroll == U) {                                                                \
+        if (e0)                                                                                            \
+            hipExtLaunchKernelGGL((k_update_gs<B, U>), ggrid, gblock, 0, h->stream, e0, e1, 0, h->T,       \
+                                  h->ld, h->m, h->n, u.rowchunks, (const int32_t *)h->cols,                \
+                                  (const double *)h->Rl, (const double *)h->F, (const DevState *)h->st,    \
+                                  h->parts);                                                               \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_update_gs<B, U>), ggrid, gblock, 0, h->stream, h->T, h->ld, h->m, h->n,  \
+                               u.rowchunks, h->cols, h->Rl, h->F, h->st, h->parts);                        \
+        return;                                                                                            \
+    }
+        LP_GS(64, 1) LP_GS(64, 2) LP_GS(64, 4) LP_GS(64, 8)
+        LP_GS(128, 1) LP_GS(128, 2) LP_GS(128, 4) LP_GS(128, 8)
+        LP_GS(256, 1) LP_GS(256, 2) LP_GS(256, 4) LP_GS(256, 8)
+        LP_GS(512, 1) LP_GS(512, 2) LP_GS(512, 4) LP_GS(512, 8)
+#undef LP_GS
+        return;
+    }
     const dim3 grid((unsigned)((int64_t)u.rowchunks * h->nparts)), block((unsigned)u.block);
 #define LP_UPD(B, C, V, NL, NS)                                                                        \
     if (u.block == B && u.cols == C && u.rv == V && u.nt == (NL | (NS << 1))) {                        \

@@ -345,6 +345,62 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
     if (row0) parts[g] = ArgMin{val, idx};
 }
 
+// Step 3, grid-stride form: a fixed grid walks the (row chunk, column) tiles
+// of one column and B row pairs each, U tiles in flight per thread (all U
+// loads issued before the first store). Tile t covers column list position
+// t / rowchunks and row chunk t % rowchunks. Same arithmetic and Step 1
+// partials (one per list position) as k_update<B, 1, 1>.
+template <int B, int U>
+__global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                 int32_t rowchunks, const int32_t *__restrict__ cols,
+                                                 const double *__restrict__ Rl, const double *__restrict__ F,
+                                                 const DevState *__restrict__ st, ArgMin *__restrict__ parts) {
+    if (!st->go) return;
+    const int32_t r = st->r;
+    const int32_t nvec = (m + 2) / 2;
+    const int64_t tiles = (int64_t)rowchunks * (n + 2);
+    const double2 *F2 = reinterpret_cast<const double2 *>(F);
+    const int32_t rhs = n + m;
+    for (int64_t t0 = blockIdx.x; t0 < tiles; t0 += (int64_t)gridDim.x * U) {
+        double2 x[U], f[U];
+        double2 *addr[U];
+        double Rt[U];
+        int32_t v[U];
+        bool live[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t t = t0 + (int64_t)u * gridDim.x;
+            const int32_t g = (int32_t)(t / rowchunks), rc = (int32_t)(t % rowchunks);
+            v[u] = rc * B + (int32_t)threadIdx.x;
+            live[u] = t < tiles && v[u] < nvec;
+            if (t < tiles) {
+                Rt[u] = Rl[g];
+                addr[u] = reinterpret_cast<double2 *>(T + (int64_t)cols[g] * ld) + v[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (live[u]) {
+                x[u] = *addr[u];
+                f[u] = F2[v[u]];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+            double2 y;
+            y.x = (2 * v[u] == r) ? Rt[u] : fma(-f[u].x, Rt[u], x[u].x);
+            y.y = (2 * v[u] + 1 == r) ? Rt[u] : fma(-f[u].y, Rt[u], x[u].y);
+            *addr[u] = y;
+            if (v[u] == 0) {  // row 0 of list position g: its Step 1 partial
+                const int64_t t = t0 + (int64_t)u * gridDim.x;
+                const int32_t g = (int32_t)(t / rowchunks);
+                const int32_t j = cols[g];
+                parts[g] = ArgMin{j != rhs ? y.x : __builtin_inf(), j != rhs ? j : kNoIndex};
+            }
+        }
+    }
+}
+
 // Finalization: x (n), y (m) and the objective into out[0 .. n+m].
 static __global__ __launch_bounds__(1024) void k_extract(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                  const int32_t *__restrict__ basis, double *__restrict__ out) {

@@ -54,7 +54,8 @@ class lp_options(ctypes.Structure):
         ("batch_unroll", ctypes.c_int32),
         ("update_hints", ctypes.c_int32),
         ("update_block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("update_grid_stride", ctypes.c_int32),
+        ("update_unroll", ctypes.c_int32),
     ]
 
 

@@ -225,6 +225,9 @@ def test_general_row_layout_large_m():
                                   dict(cols_per_block=8), dict(cols_per_block=16),
                                   dict(cols_per_block=1, rows_per_thread=8), dict(cols_per_block=2, rows_per_thread=4),
                                   dict(cols_per_block=16, rows_per_thread=2), dict(rows_per_thread=8),
+                                  dict(update_grid_stride=4, update_unroll=2), dict(update_grid_stride=1),
+                                  dict(update_grid_stride=8, update_unroll=8, update_block=512),
+                                  dict(update_block=128, cols_per_block=2), dict(update_block=1024, cols_per_block=1),
                                   dict(use_graph=0), dict(chunk_pivots=1), dict(chunk_pivots=33)])
 def test_launch_options_do_not_change_results(opts):
     A, b, c = rand_lp(5, 333, 444, 1, 9, signed=True)
