@@ -77,7 +77,7 @@ typedef struct {
                                lp_tableau_bytes(m, n) bytes and 256-byte aligned; it must
                                outlive the context                            (default NULL) */
     size_t device_buffer_bytes;
-    int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto */
+    int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto (4) */
     int32_t cols_per_block; /* update kernel: listed columns per workgroup (1, 2, 4, 8, 16; 0 = auto) */
     int32_t use_graph;      /* 1 = replay a captured hipGraph, 0 = plain launches (default 1) */
     int32_t time_kernels;   /* 1 = time every update kernel with HIP events (lp_get_timing); the
@@ -94,6 +94,8 @@ typedef struct {
     int32_t update_grid_stride; /* > 0: grid-stride update kernel with this many workgroups per
                                compute unit (block 64..512), one column per tile (default 0) */
     int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
+    int32_t select_workgroups; /* Steps 1-2 kernel: workgroups (1..64; 0 = 1) */
+    int32_t reserved;
 } lp_options;
 
 typedef struct {

@@ -90,6 +90,9 @@ struct lp_ctx {
     int cus = 256;
     UpdateConfig ucfg{};
     unsigned long long *cols_done = nullptr;  // device counter of rewritten columns
+    RatioPart *rparts = nullptr;              // multi-workgroup select: ratio partials
+    uint32_t *ticket = nullptr;               // multi-workgroup select: arrival counter
+    int select_wgs = 1;                       // workgroups of the select kernel
     int chunk = 8;
     bool use_graph = true;
     bool timing = false;
@@ -120,6 +123,8 @@ void free_ctx(lp_ctx *h) {
             if (e) (void)hipEventDestroy(e);
     }
     if (h->cols_done) (void)hipFree(h->cols_done);
+    if (h->rparts) (void)hipFree(h->rparts);
+    if (h->ticket) (void)hipFree(h->ticket);
     if (h->own_T && h->T) (void)hipFree(h->T);
     if (h->F) (void)hipFree(h->F);
     if (h->parts) (void)hipFree(h->parts);
@@ -148,6 +153,8 @@ int validate_opts(const lp_options &o) {
     if (o.rows_per_thread != 0 && !valid_rv(o.rows_per_thread))
         return set_error(LP_E_INVAL, "rows_per_thread must be 0 (auto) or one of 1, 2, 4, 8");
     if (o.update_hints < 0 || o.update_hints > 3) return set_error(LP_E_INVAL, "update_hints must be in [0, 3]");
+    if (o.select_workgroups < 0 || o.select_workgroups > 64)
+        return set_error(LP_E_INVAL, "select_workgroups must be in [0, 64]");
     if (o.update_grid_stride < 0 || o.update_grid_stride > 32)
         return set_error(LP_E_INVAL, "update_grid_stride must be in [0, 32]");
     if (o.update_unroll != 0 && o.update_unroll != 1 && o.update_unroll != 2 && o.update_unroll != 4 &&
@@ -205,7 +212,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     }
     h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
     h->cus = device_cu_count(o.device);
-    h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 8;
+    h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 4;
+    h->select_wgs = o.select_workgroups > 0 ? o.select_workgroups : 1;
     h->use_graph = o.use_graph != 0;
     h->timing = o.time_kernels != 0;
 
@@ -249,6 +257,10 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     }
     if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->cols_done, sizeof(unsigned long long))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->rparts, 64 * sizeof(RatioPart))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->ticket, sizeof(uint32_t))) return fail(rc);
+    if (hipMemset(h->ticket, 0, sizeof(uint32_t)) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (int rc = dev_alloc((void **)&h->cols, ((size_t)n + 2) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->Rl, ((size_t)n + 2) * sizeof(double))) return fail(rc);
@@ -367,8 +379,13 @@ void launch_update(lp_ctx *h, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) 
 // each update kernel in timing mode.
 int enqueue_chunk(lp_ctx *h, int slot) {
     for (int k = 0; k < h->chunk; ++k) {
-        hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts, h->st,
-                           h->F, h->basis, h->log_r, h->log_q, h->pos);
+        if (h->select_wgs > 1)
+            hipLaunchKernelGGL(k_select_mw, dim3((unsigned)h->select_wgs), dim3(1024), 0, h->stream, h->T, h->ld,
+                               h->m, h->n, h->parts, h->st, h->F, h->basis, h->log_r, h->log_q, h->pos, h->rparts,
+                               h->ticket);
+        else
+            hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->parts,
+                               h->st, h->F, h->basis, h->log_r, h->log_q, h->pos);
         hipLaunchKernelGGL(k_stage, dim3((unsigned)(((int64_t)h->n + 2 + 255) / 256)), dim3(256), 0, h->stream, h->T,
                            h->ld, h->m, h->n, h->st, h->cols, h->pos, h->Rl, h->cols_done);
         if (h->timing)

@@ -195,6 +195,132 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     }
 }
 
+// Steps 1 and 2 spread over G workgroups of 1024 threads. Every workgroup
+// reduces all Step 1 partials itself (so all agree on q without waiting for
+// each other), then takes rows [1 + w*span, ...) of the ratio test and of the
+// copy of column q to F, and writes one (ratio, row) partial. The last
+// workgroup to finish (atomic ticket, device-scope fences around it) reduces
+// those partials and records the decision exactly as k_select does.
+struct RatioPart {
+    double v;
+    int32_t i;
+    int32_t bad;
+};
+
+static __global__ __launch_bounds__(1024) void k_select_mw(const double *__restrict__ T, int64_t ld, int32_t m,
+                                                           int32_t n, const ArgMin *__restrict__ parts,
+                                                           DevState *__restrict__ st, double *__restrict__ F,
+                                                           int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
+                                                           int32_t *__restrict__ log_q, const int32_t *__restrict__ pos,
+                                                           RatioPart *__restrict__ rparts, uint32_t *__restrict__ ticket) {
+    __shared__ double sv[16];
+    __shared__ int32_t si[16];
+    __shared__ uint32_t s_last;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int G = gridDim.x, w = blockIdx.x;
+    const DevState s = *st;
+    if (s.status != LP_RUNNING || s.pivots >= s.stop_at) {
+        if (w == 0 && tid == 0) st->go = 0;
+        return;
+    }
+    const int64_t W = (int64_t)n + m + 1;
+    double v = __builtin_inf();
+    int32_t q = kNoIndex;
+    if (s.fresh) {
+        for (int32_t j = tid; j < n + m; j += nt) {
+            const double t = T[(int64_t)j * ld];
+            if (lex_less(t, j, v, q)) {
+                v = t;
+                q = j;
+            }
+        }
+    } else {
+        for (int32_t k = tid; k < s.nparts; k += nt) {
+            const ArgMin a = parts[k];
+            if (lex_less(a.v, a.i, v, q)) {
+                v = a.v;
+                q = a.i;
+            }
+        }
+    }
+    block_argmin(v, q, sv, si);
+    if (v != v || v >= -s.eps_d) {
+        if (w == 0 && tid == 0) {
+            st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            st->go = 0;
+        }
+        return;
+    }
+    const double *colq = T + (int64_t)q * ld;
+    const double *rhs = T + (W - 1) * ld;
+    const int32_t span = (m + G - 1) / G;
+    const int32_t i0 = 1 + w * span, i1 = min(m, i0 + span - 1);
+    double rv = __builtin_inf();
+    int32_t r = kNoIndex;
+    int bad = 0;
+    if (w == 0 && tid == 0) F[0] = colq[0];
+    for (int32_t i = i0 + tid; i <= i1; i += nt) {
+        const double a = colq[i], bb = rhs[i];
+        F[i] = a;
+        if (a != a || bb != bb) {
+            bad = 1;
+        } else if (a > s.eps_p) {
+            const double ratio = bb / a;
+            if (ratio != ratio)
+                bad = 1;
+            else if (lex_less(ratio, i, rv, r)) {
+                rv = ratio;
+                r = i;
+            }
+        }
+    }
+    bad = __syncthreads_or(bad);
+    block_argmin(rv, r, sv, si);
+    if (tid == 0) {
+        rparts[w] = RatioPart{rv, r, bad};
+        __threadfence();
+        s_last = atomicAdd(ticket, 1u) == (uint32_t)(G - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // last workgroup: the decision
+    rv = __builtin_inf();
+    r = kNoIndex;
+    bad = 0;
+    for (int k = tid; k < G; k += nt) {
+        const RatioPart pr = rparts[k];
+        bad |= pr.bad;
+        if (lex_less(pr.v, pr.i, rv, r)) {
+            rv = pr.v;
+            r = pr.i;
+        }
+    }
+    bad = __syncthreads_or(bad);
+    block_argmin(rv, r, sv, si);
+    if (tid != 0) return;
+    *ticket = 0;  // ready for the next launch (ordered by the kernel boundary)
+    if (bad || r == kNoIndex || s.pivots >= s.max_pivots) {
+        st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+        st->go = 0;
+        return;
+    }
+    const int32_t leave = basis[r - 1];
+    st->r = r;
+    st->q = q;
+    st->p = colq[r];
+    st->leave = leave;
+    st->pq = pos[q];
+    basis[r - 1] = q;
+    if (s.pivots < s.log_cap) {
+        log_r[s.pivots] = r;
+        log_q[s.pivots] = q;
+    }
+    st->pivots = s.pivots + 1;
+    st->fresh = 0;
+    st->go = 1;
+}
+
 // Inputs of Step 3 for the pivot k_select decided, one list position per
 // thread: R_t = T[r][j_t] / p for the rewrite list with the leaving column in
 // the entering column's place, and the count of nonzero R. Workgroup 0 then

@@ -56,6 +56,8 @@ class lp_options(ctypes.Structure):
         ("update_block", ctypes.c_int32),
         ("update_grid_stride", ctypes.c_int32),
         ("update_unroll", ctypes.c_int32),
+        ("select_workgroups", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -200,6 +202,14 @@ def _ip(a):
 
 def lp_version() -> str:
     return library().lp_version().decode()
+
+
+def lp_last_error() -> str:
+    return library().lp_last_error().decode()
+
+
+def lp_error_string(code: int) -> str:
+    return library().lp_error_string(code).decode()
 
 
 def lp_tableau_bytes(m: int, n: int) -> int:

@@ -68,7 +68,10 @@ def test_null_arguments_are_rejected_without_a_device(lpgpu):
     assert lib.lp_solve(None) == lpgpu.LP_E_INVAL
     assert lib.lp_get_solution(None, None, None, None) == lpgpu.LP_E_INVAL
     lib.lp_destroy(None)  # NULL-safe
-    assert lpgpu.lp_last_error() if hasattr(lpgpu, "lp_last_error") else True
+    lib.lp_batch_destroy(None)
+    lib.lp_server_destroy(None)
+    assert lib.lp_solve(None) == lpgpu.LP_E_INVAL
+    assert "NULL" in lpgpu.lp_last_error()
 
 
 def test_oracle_and_library_share_no_code():

@@ -228,6 +228,7 @@ def test_general_row_layout_large_m():
                                   dict(update_grid_stride=4, update_unroll=2), dict(update_grid_stride=1),
                                   dict(update_grid_stride=8, update_unroll=8, update_block=512),
                                   dict(update_block=128, cols_per_block=2), dict(update_block=1024, cols_per_block=1),
+                                  dict(select_workgroups=2), dict(select_workgroups=7), dict(select_workgroups=64),
                                   dict(use_graph=0), dict(chunk_pivots=1), dict(chunk_pivots=33)])
 def test_launch_options_do_not_change_results(opts):
     A, b, c = rand_lp(5, 333, 444, 1, 9, signed=True)
