@@ -41,17 +41,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def update_bytes(m: int, n: int, cols: int, launches: int) -> float:
-    """Algorithmic bytes of `launches` update kernels that rewrote `cols`
-    columns in total: each rewritten column is read and written once
-    (16 (m+1) B); every launch also reads the pivot column F (8 (m+1) B) and,
-    for every column, its pivot-row and row-0 entries (16 W B)."""
+def update_bytes(m: int, n: int, cols: int, pivots: int) -> float:
+    """Algorithmic bytes of the update passes that applied `pivots` pivots and
+    rewrote `cols` columns in total (a column counts once per pass, however
+    many pivots of the pass change it): each rewritten column is read and
+    written once (16 (m+1) B); every pivot also brings its pivot column F
+    (8 (m+1) B) and, for every column, its pivot-row and row-0 entries
+    (16 W B)."""
     W = n + m + 1
-    return 16.0 * (m + 1) * cols + launches * (8.0 * (m + 1) + 16.0 * W)
+    return 16.0 * (m + 1) * cols + pivots * (8.0 * (m + 1) + 16.0 * W)
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_update_dense_8000x8000_counters.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2211_10979_amd", "csrc", "plain_kernels.hpp")
+CSRC = os.path.join(ROOT, "paper_2211_10979_amd", "csrc")
+
+
+def kernel_source(kernel):
+    """The header that defines the update kernel instance `kernel`."""
+    name = "fused_kernels.hpp" if kernel.startswith("k_gupdate") else "plain_kernels.hpp"
+    return os.path.join(CSRC, name)
 
 
 def committed_traffic(kernel):
@@ -68,7 +76,7 @@ def committed_traffic(kernel):
         if ":" in line and not line.startswith("|"):
             k, v = line.split(":", 1)
             kv[k.strip().lstrip("- ")] = v.strip().strip("`")
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(kernel_source(kernel), "rb").read()).hexdigest()
     if kv.get("kernel") != kernel or kv.get("source_sha256") != src:
         return None
     try:
@@ -86,7 +94,8 @@ def bench_plain(args, lpgpu, lpgen, torch):
     dc = torch.from_numpy(lp.c).to(dev)
     torch.cuda.synchronize()
     h = lpgpu.lp_create_device(m, n, dA, db, dc, time_kernels=args.time_kernels, chunk_pivots=args.chunk,
-                               cols_per_block=args.cols_per_block, rows_per_thread=args.rows_per_thread)
+                               cols_per_block=args.cols_per_block, rows_per_thread=args.rows_per_thread,
+                               fuse_pivots=args.fuse)
     try:
         def step():
             lpgpu.lp_reload_device(h, dA, db, dc)
@@ -112,8 +121,12 @@ def bench_plain(args, lpgpu, lpgen, torch):
         elapsed = time.perf_counter() - t0
         rows, cols = lpgpu.lp_get_pivots(h)
         info = lpgpu.lp_get_info(h)
-        kernel = (f"k_update<{info.update_block}, {info.update_cols}, {info.update_rows}, "
-                  f"{info.update_hints & 1}, {info.update_hints >> 1}>")
+        fuse = info.update_fuse
+        if fuse > 1:
+            kernel = f"k_gupdate<{info.update_block}, {info.update_cols}, {info.update_rows}, {fuse}>"
+        else:
+            kernel = (f"k_update<{info.update_block}, {info.update_cols}, {info.update_rows}, "
+                      f"{info.update_hints & 1}, {info.update_hints >> 1}>")
     finally:
         lpgpu.lp_destroy(h)
     from paper_2211_10979_amd.certify import certify
@@ -131,6 +144,7 @@ def bench_plain(args, lpgpu, lpgen, torch):
         objective=res["objective"],
         certificates_ok=bool(ok),
         certificate_max_residual=max(resid.values()),
+        fuse_pivots=fuse,
         end_to_end_alg_gbs=alg_total / elapsed / 1e9,
         end_to_end_alg_frac=alg_total / elapsed / 1e9 / HBM_PEAK_GBS,
         device_solve_ms_per_step=solve_ms / args.steps,
@@ -347,6 +361,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_8000x8000")
     ap.add_argument("--chunk", type=int, default=0, help="pivots per graph replay (0 = library default)")
+    ap.add_argument("--fuse", type=int, default=0, help="pivots per update pass (0 = library default)")
     ap.add_argument("--cols-per-block", type=int, default=0)
     ap.add_argument("--rows-per-thread", type=int, default=0)
     ap.add_argument("--time-kernels", type=int, default=1)
@@ -407,7 +422,7 @@ def main():
         data="synthetic",
         config=dict(workload=args.workload, m=w["m"], n=w["n"], seed=w["seed"],
                     tableau=f"{w['m'] + 1}x{w['m'] + w['n'] + 1}", generator="A,b,c integer uniform [1,1000]",
-                    parallelism="single GPU"),
+                    pivots_per_update_pass=plain["fuse_pivots"], parallelism="single GPU"),
         roofline=roof,
         plain=plain,
     )

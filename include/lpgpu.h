@@ -77,7 +77,8 @@ typedef struct {
                                lp_tableau_bytes(m, n) bytes and 256-byte aligned; it must
                                outlive the context                            (default NULL) */
     size_t device_buffer_bytes;
-    int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto (4) */
+    int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto (4, or one group
+                               of fuse_pivots pivots when K > 1) */
     int32_t cols_per_block; /* update kernel: listed columns per workgroup (1, 2, 4, 8, 16; 0 = auto) */
     int32_t use_graph;      /* 1 = replay a captured hipGraph, 0 = plain launches (default 1) */
     int32_t time_kernels;   /* 1 = time every update kernel with HIP events (lp_get_timing); the
@@ -95,6 +96,17 @@ typedef struct {
                                compute unit (block 64..512), one column per tile (default 0) */
     int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
     int32_t select_workgroups; /* Steps 1-2 kernel: workgroups (1..64; 0 = 1) */
+    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..8; 0 = auto: 8 unless
+                               an option above asks for a form only K = 1 has). With K > 1 the
+                               solver decides K pivots one after the other, each from row 0,
+                               its pivot column and the RHS rebuilt by replaying the earlier
+                               pivots of the group on those vectors only, then rewrites every
+                               changed column once with all K pivots in order: the same
+                               arithmetic, so the same pivots and bit-identical tableaux as
+                               K = 1, with 1/K of the update traffic. K > 1 needs
+                               update_block 0 or <= 256, cols_per_block <= 8,
+                               rows_per_thread 0 or 1, update_hints 0, update_grid_stride 0 and
+                               select_workgroups <= 1. */
     int32_t reserved;
 } lp_options;
 
@@ -116,6 +128,8 @@ typedef struct {
     int32_t update_cols;    /* listed columns per workgroup, */
     int32_t update_rows;    /* row pairs per thread and column, */
     int32_t update_hints;   /* cache hints (bit 0 loads, bit 1 stores non-temporal) */
+    int32_t update_fuse;    /* pivots per pass over the tableau (fuse_pivots in use) */
+    int32_t reserved;
 } lp_info;
 
 /* Library version string. Never fails. */
@@ -206,8 +220,9 @@ typedef struct {
                                  after the solve ended, which return at once */
     int64_t update_launches;  /* number of update kernels in update_ms */
     int64_t pivots;           /* pivots performed since the tableau was built */
-    int64_t updated_columns;  /* tableau columns rewritten by Step 3, summed over those pivots
-                                 (columns whose normalised pivot-row entry is nonzero) */
+    int64_t updated_columns;  /* tableau columns rewritten by Step 3, summed over the update
+                                 passes (columns with a nonzero normalised pivot-row entry in
+                                 some pivot of the pass; one pass per pivot when K = 1) */
 } lp_timing;
 
 /* Timing and work counters of the context (see lp_timing). */

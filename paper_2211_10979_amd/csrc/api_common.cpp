@@ -58,6 +58,7 @@ int lp_options_default(lp_options *o) {
     o->update_grid_stride = 0;
     o->update_unroll = 0;
     o->select_workgroups = 0;
+    o->fuse_pivots = 0;
     o->reserved = 0;
     return LP_OK;
 }

@@ -1,0 +1,104 @@
+// Instances and launchers of the pivot-fusion kernels.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "fused_launch.hpp"
+
+namespace lpgpu {
+
+namespace {
+
+template <int J>
+void select_j(const FusedArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_gselect<J>), dim3(1), dim3(1024), 0, s, (const double *)a.T, a.ld, a.m, a.n, a.K,
+                       (const ArgMin *)a.parts, (const ArgMin *)a.sparts, a.nsparts, a.st, a.gs, a.Fk, a.Rk, a.D,
+                       a.cols, a.pos, a.basis, a.log_r, a.log_q);
+}
+
+template <int J>
+void stage_j(const FusedArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_gstage<J>), dim3((unsigned)a.nsparts), dim3(256), 0, s, (const double *)a.T, a.ld, a.m,
+                       a.n, a.K, (const GroupState *)a.gs, (const double *)a.Fk, a.Rk, a.D, (const int32_t *)a.cols,
+                       a.sparts);
+}
+
+template <int B, int C, int K>
+void update(const FusedArgs &a, unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (e0)
+        hipExtLaunchKernelGGL((k_gupdate<B, C, K>), dim3(grid), dim3(B), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n,
+                              a.rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                              (const GroupState *)a.gs, a.parts, a.cols_done);
+    else
+        hipLaunchKernelGGL((k_gupdate<B, C, K>), dim3(grid), dim3(B), 0, s, a.T, a.ld, a.m, a.n, a.rowchunks,
+                           (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, a.parts, a.cols_done);
+}
+
+using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
+
+template <int B, int C>
+UpdateFn pick_k(int K) {
+    switch (K) {
+        case 2: return update<B, C, 2>;
+        case 3: return update<B, C, 3>;
+        case 4: return update<B, C, 4>;
+        case 5: return update<B, C, 5>;
+        case 6: return update<B, C, 6>;
+        case 7: return update<B, C, 7>;
+        case 8: return update<B, C, 8>;
+        default: return nullptr;
+    }
+}
+
+// Tile shapes with instances: 64, 128 or 256 threads (one row pair each) by
+// 1, 2, 4 or 8 list slots.
+UpdateFn find_update(int block, int cols, int rv, int K) {
+    if (rv != 1) return nullptr;
+#define LP_FSHAPE(B, C) \
+    if (block == B && cols == C) return pick_k<B, C>(K);
+    LP_FSHAPE(256, 1) LP_FSHAPE(256, 2) LP_FSHAPE(256, 4) LP_FSHAPE(256, 8)
+    LP_FSHAPE(128, 1) LP_FSHAPE(128, 2) LP_FSHAPE(128, 4) LP_FSHAPE(128, 8)
+    LP_FSHAPE(64, 1) LP_FSHAPE(64, 2) LP_FSHAPE(64, 4) LP_FSHAPE(64, 8)
+#undef LP_FSHAPE
+    return nullptr;
+}
+
+}  // namespace
+
+bool fused_update_supported(int block, int cols, int rv, int K) { return find_update(block, cols, rv, K) != nullptr; }
+
+void launch_fused_select(const FusedArgs &a, int j, hipStream_t s) {
+    switch (j) {
+        case 0: select_j<0>(a, s); break;
+        case 1: select_j<1>(a, s); break;
+        case 2: select_j<2>(a, s); break;
+        case 3: select_j<3>(a, s); break;
+        case 4: select_j<4>(a, s); break;
+        case 5: select_j<5>(a, s); break;
+        case 6: select_j<6>(a, s); break;
+        case 7: select_j<7>(a, s); break;
+        default: break;
+    }
+}
+
+void launch_fused_stage(const FusedArgs &a, int j, hipStream_t s) {
+    switch (j) {
+        case 0: stage_j<0>(a, s); break;
+        case 1: stage_j<1>(a, s); break;
+        case 2: stage_j<2>(a, s); break;
+        case 3: stage_j<3>(a, s); break;
+        case 4: stage_j<4>(a, s); break;
+        case 5: stage_j<5>(a, s); break;
+        case 6: stage_j<6>(a, s); break;
+        case 7: stage_j<7>(a, s); break;
+        default: break;
+    }
+}
+
+void launch_fused_update(const FusedArgs &a, int block, int cols, int rv, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+    const unsigned grid = (unsigned)((int64_t)a.rowchunks * a.nparts);
+    if (UpdateFn f = find_update(block, cols, rv, a.K)) f(a, grid, s, e0, e1);
+}
+
+}  // namespace lpgpu

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "fused_launch.hpp"
 #include "plain_kernels.hpp"
 
 using namespace lpgpu;
@@ -39,16 +40,21 @@ struct UpdateConfig {
 };
 
 // Small m: one chunk of 64 or 128 pairs; otherwise `block` threads (256 by
-// default) with `rv` pairs each. Defaults from a sweep on MI355X: one column
-// and one pair per thread for tall tableaux (the most independent, shortest
-// streams: 5.5 TB/s at m = 8000), four columns per workgroup below 4096 rows.
-UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block) {
+// default) with `rv` pairs each. Defaults from sweeps on MI355X: for one
+// pivot per pass, one column and one pair per thread for tall tableaux (the
+// most independent, shortest streams: 5.5 TB/s at m = 8000) and four columns
+// per workgroup below 4096 rows; with pivot fusion, kFusedCols columns (the
+// group's pivot columns are then loaded once per kFusedCols columns).
+constexpr int kFusedCols = 4;
+constexpr int kAutoFuse = 8;
+
+UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fused) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
     if (nvec <= 128) {
         const int b = nvec <= 64 ? 64 : 128;
         return {b, cols > 0 ? cols : 4, 1, 1, 0, 0, 0};
     }
-    if (cols <= 0) cols = nvec > 2048 ? 1 : 4;
+    if (cols <= 0) cols = fused ? kFusedCols : (nvec > 2048 ? 1 : 4);
     if (rv <= 0) rv = 1;
     if (block <= 0) block = 256;
     const int64_t span = block * (int64_t)rv;
@@ -93,7 +99,13 @@ struct lp_ctx {
     RatioPart *rparts = nullptr;              // multi-workgroup select: ratio partials
     uint32_t *ticket = nullptr;               // multi-workgroup select: arrival counter
     int select_wgs = 1;                       // workgroups of the select kernel
-    int chunk = 8;
+    int chunk = 4;                            // pivots (K = 1) or groups (K > 1) per replay
+    int fuse = 1;                             // pivots per update pass (K)
+    int64_t Lg = 0;                           // list slots: n + 2 (K = 1) or n + 1 + K
+    GroupState *gs = nullptr;                 // K > 1: decisions of the current group
+    double *D = nullptr;                      // K > 1: row-0 entry of every slot during a group
+    ArgMin *sparts = nullptr;                 // K > 1: Step 1 partials of the staging kernel
+    int nsparts = 0;
     bool use_graph = true;
     bool timing = false;
     // Two captured chunk graphs used alternately, so that the events of one
@@ -136,6 +148,9 @@ void free_ctx(lp_ctx *h) {
     if (h->cols) (void)hipFree(h->cols);
     if (h->pos) (void)hipFree(h->pos);
     if (h->Rl) (void)hipFree(h->Rl);
+    if (h->gs) (void)hipFree(h->gs);
+    if (h->D) (void)hipFree(h->D);
+    if (h->sparts) (void)hipFree(h->sparts);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -164,6 +179,7 @@ int validate_opts(const lp_options &o) {
         o.update_block != 512 && o.update_block != 1024)
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
+    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 8]");
     return LP_OK;
 }
 
@@ -189,7 +205,17 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->eps_p = o.eps_pivot;
     h->max_pivots = o.max_pivots > 0 ? o.max_pivots : 50 * ((int64_t)m + n);
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
-    h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block);
+    // Pivot fusion: the given K, or kAutoFuse unless an option asks for a
+    // form that only the one-pivot kernels have.
+    const bool one_pivot_form = o.update_grid_stride > 0 || o.update_hints != 0 || o.select_workgroups > 1 ||
+                                o.rows_per_thread > 1 || o.cols_per_block > 8 || o.update_block > 256;
+    h->fuse = o.fuse_pivots > 0 ? o.fuse_pivots : (one_pivot_form ? 1 : kAutoFuse);
+    h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, h->fuse > 1);
+    if (o.fuse_pivots == 0 && h->fuse > 1 &&
+        !fused_update_supported(h->ucfg.block, h->ucfg.cols, h->ucfg.rv, h->fuse)) {
+        h->fuse = 1;
+        h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, false);
+    }
     if (h->ucfg.block == 256) h->ucfg.nt = o.update_hints & 3;
     if (o.update_grid_stride > 0) {  // grid-stride kernel: one column, one pair per thread per tile
         h->ucfg.cols = 1;
@@ -203,16 +229,32 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         delete h;
         return set_error(LP_E_INVAL, "the grid-stride update kernel takes at most 512 threads per workgroup");
     }
-    const bool big_block_ok = h->ucfg.block == 256 || (h->ucfg.cols <= 2 && h->ucfg.rv <= 2) ||
+    // (the fused kernels' shapes are checked below)
+    const bool big_block_ok = h->fuse > 1 || h->ucfg.block == 256 || (h->ucfg.cols <= 2 && h->ucfg.rv <= 2) ||
                               (h->ucfg.block <= 128 && h->ucfg.rv == 1 && h->ucfg.rowchunks == 1);
     if ((o.update_block > 0 && h->ucfg.block != o.update_block) || !big_block_ok) {
         delete h;
         return set_error(LP_E_INVAL, "update_block needs m + 1 > 256, and values other than 256 need "
                                      "cols_per_block and rows_per_thread <= 2");
     }
-    h->nparts = (int)(((int64_t)n + 2 + h->ucfg.cols - 1) / h->ucfg.cols);
+    if (h->fuse > 1) {
+        const UpdateConfig &u = h->ucfg;
+        if (u.gs_per_cu > 0 || u.nt != 0 || o.select_workgroups > 1 ||
+            !fused_update_supported(u.block, u.cols, u.rv, h->fuse)) {
+            delete h;
+            return set_error(LP_E_INVAL, "fuse_pivots > 1 needs update_block <= 256, cols_per_block <= 8, "
+                                         "rows_per_thread 1, update_hints 0, update_grid_stride 0 and "
+                                         "select_workgroups <= 1");
+        }
+    }
+    h->Lg = h->fuse > 1 ? (int64_t)n + 1 + h->fuse : (int64_t)n + 2;
+    h->nparts = (int)((h->Lg + h->ucfg.cols - 1) / h->ucfg.cols);
+    h->nsparts = (int)((h->Lg + 255) / 256);
     h->cus = device_cu_count(o.device);
-    h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 4;
+    if (h->fuse > 1)
+        h->chunk = o.chunk_pivots > 0 ? (o.chunk_pivots + h->fuse - 1) / h->fuse : 1;
+    else
+        h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 4;
     h->select_wgs = o.select_workgroups > 0 ? o.select_workgroups : 1;
     h->use_graph = o.use_graph != 0;
     h->timing = o.time_kernels != 0;
@@ -247,7 +289,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->T, tbytes)) return fail(rc);
         h->own_T = true;
     }
-    if (int rc = dev_alloc((void **)&h->F, (size_t)h->ld * sizeof(double))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->F, (size_t)h->fuse * h->ld * sizeof(double))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->parts, (size_t)h->nparts * sizeof(ArgMin))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->st, sizeof(DevState))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->basis, (size_t)m * sizeof(int32_t))) return fail(rc);
@@ -261,9 +303,16 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     if (int rc = dev_alloc((void **)&h->ticket, sizeof(uint32_t))) return fail(rc);
     if (hipMemset(h->ticket, 0, sizeof(uint32_t)) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-    if (int rc = dev_alloc((void **)&h->cols, ((size_t)n + 2) * sizeof(int32_t))) return fail(rc);
+    // the fused update reads the list and R of a whole slot group at once, so
+    // both are padded past the last slot
+    if (int rc = dev_alloc((void **)&h->cols, ((size_t)h->Lg + 16) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)n + 2) * sizeof(double))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)h->fuse * h->Lg + 16) * sizeof(double))) return fail(rc);
+    if (h->fuse > 1) {
+        if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->sparts, (size_t)h->nsparts * sizeof(ArgMin))) return fail(rc);
+    }
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
@@ -303,9 +352,15 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.eps_p = h->eps_p;
     init.fresh = 1;
     init.nparts = h->nparts;
-    const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
-    hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init, h->basis,
-                       m, n, h->F, ld, h->cols, h->pos, h->cols_done);
+    if (h->fuse > 1) {
+        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)h->fuse * ld), h->Lg);
+        hipLaunchKernelGGL(k_ginit, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
+                           h->gs, h->basis, m, n, (int32_t)h->fuse, h->F, ld, h->cols, h->pos, h->cols_done);
+    } else {
+        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
+        hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
+                           h->basis, m, n, h->F, ld, h->cols, h->pos, h->cols_done);
+    }
     LP_HIP_CHECK(hipGetLastError());
     h->pivots_host = 0;
     h->status_host = LP_RUNNING;
@@ -375,9 +430,56 @@ void launch_update(lp_ctx *h, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) 
 #undef LP_UPD
 }
 
-// One chunk: `chunk` pivots of (select, update), with event records around
-// each update kernel in timing mode.
+FusedArgs fused_args(lp_ctx *h) {
+    FusedArgs a;
+    a.T = h->T;
+    a.ld = h->ld;
+    a.m = h->m;
+    a.n = h->n;
+    a.K = h->fuse;
+    a.rowchunks = h->ucfg.rowchunks;
+    a.nsparts = h->nsparts;
+    a.nparts = h->nparts;
+    a.st = h->st;
+    a.gs = h->gs;
+    a.Fk = h->F;
+    a.Rk = h->Rl;
+    a.D = h->D;
+    a.cols = h->cols;
+    a.pos = h->pos;
+    a.basis = h->basis;
+    a.log_r = h->log_r;
+    a.log_q = h->log_q;
+    a.parts = h->parts;
+    a.sparts = h->sparts;
+    a.cols_done = h->cols_done;
+    return a;
+}
+
+// One group of pivot fusion: K (select, stage) pairs, then one update pass.
+void enqueue_group(lp_ctx *h, hipEvent_t e0, hipEvent_t e1) {
+    const FusedArgs a = fused_args(h);
+    for (int j = 0; j < h->fuse; ++j) {
+        launch_fused_select(a, j, h->stream);
+        launch_fused_stage(a, j, h->stream);
+    }
+    const UpdateConfig &u = h->ucfg;
+    launch_fused_update(a, u.block, u.cols, u.rv, h->stream, e0, e1);
+}
+
+// One chunk: `chunk` pivots of (select, stage, update), or `chunk` groups of
+// pivot fusion, with event records around each update kernel in timing mode.
 int enqueue_chunk(lp_ctx *h, int slot) {
+    if (h->fuse > 1) {
+        for (int k = 0; k < h->chunk; ++k) {
+            if (h->timing)
+                enqueue_group(h, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]);
+            else
+                enqueue_group(h, nullptr, nullptr);
+        }
+        LP_HIP_CHECK(hipGetLastError());
+        return LP_OK;
+    }
     for (int k = 0; k < h->chunk; ++k) {
         if (h->select_wgs > 1)
             hipLaunchKernelGGL(k_select_mw, dim3((unsigned)h->select_wgs), dim3(1024), 0, h->stream, h->T, h->ld,
@@ -641,6 +743,8 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
     info->update_cols = h->ucfg.cols;
     info->update_rows = h->ucfg.rv;
     info->update_hints = h->ucfg.nt;
+    info->update_fuse = h->fuse;
+    info->reserved = 0;
     return LP_OK;
 }
 

@@ -57,6 +57,7 @@ class lp_options(ctypes.Structure):
         ("update_grid_stride", ctypes.c_int32),
         ("update_unroll", ctypes.c_int32),
         ("select_workgroups", ctypes.c_int32),
+        ("fuse_pivots", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -83,6 +84,8 @@ class lp_info(ctypes.Structure):
         ("update_cols", ctypes.c_int32),
         ("update_rows", ctypes.c_int32),
         ("update_hints", ctypes.c_int32),
+        ("update_fuse", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
