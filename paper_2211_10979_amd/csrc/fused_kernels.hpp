@@ -27,17 +27,19 @@
 // and D[t] (its row-0 entry after the pivots staged so far).
 //
 // Launches per group, on one stream:
-//   k_gselect(j), k_gstage(j)   for j = 0 .. K-1
+//   k_gselect<j>, k_gstage<j>   for j = 0 .. K-1
 //   k_gupdate                   applies the kdone pivots the group decided.
-// k_gselect(0) first closes the previous group: the columns that entered and
+// k_gselect<0> also closes the previous group: the columns that entered and
 // stay basic give up their slots to the appended columns that stay nonbasic.
 #pragma once
+
+#include <type_traits>
 
 #include "common.hpp"
 
 namespace lpgpu {
 
-constexpr int kMaxFuse = 8;
+constexpr int kMaxFuse = 16;
 
 // Decisions of the current group, resident in device memory.
 struct GroupState {
@@ -125,96 +127,231 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
     gs->napp = 0;
 }
 
-// Steps 1 and 2 of pivot J of the group; one workgroup of 1024 threads.
-//   Step 1  J = 0: final stage of the argmin over the update's partials (a
-//           scan of row 0 before the first pivot); J > 0: over the staging
-//           kernel's partials of row 0 after pivot J-1;
-//   Step 2  column q and the RHS column after the J earlier pivots, rebuilt
-//           from the tableau by the chain above; column q is kept as F_J.
-// The decision (r, q, p, leaving column), the basis, the log and, if the
-// leaving column is not in the list yet, its appended slot. J is a template
-// argument so that the chain's coefficients load without a wait per pivot.
-template <int J>
-__global__ __launch_bounds__(1024) void k_gselect(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                  int32_t K, const ArgMin *__restrict__ parts,
-                                                  const ArgMin *__restrict__ sparts, int32_t nsparts,
-                                                  DevState *__restrict__ st, GroupState *__restrict__ gs,
-                                                  double *__restrict__ Fk, double *__restrict__ Rk,
-                                                  double *__restrict__ D, int32_t *__restrict__ cols,
-                                                  int32_t *__restrict__ pos, int32_t *__restrict__ basis,
-                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q) {
-    __shared__ double sv[16];
-    __shared__ int32_t si[16];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t Lg = (int64_t)n + 1 + K;
-    if constexpr (J == 0) {
-        if (tid == 0) close_group(gs, cols, pos, n);
-        // appended slots start with R = 0 and a row-0 entry of 0: the exact
-        // values for a column that is basic (a unit vector) before it leaves
-        if (tid < K * K) Rk[(int64_t)(tid / K) * Lg + n + 1 + tid % K] = 0.0;
-        if (tid < K) D[n + 1 + tid] = 0.0;
-        __syncthreads();
-    }
-    const DevState s = *st;
-    if (s.status != LP_RUNNING || s.pivots >= s.stop_at) return;
-    if (J > 0 && gs->kdone != J) return;  // the group ended early
-    const int64_t W = (int64_t)n + m + 1;
+// Step 1 partial of the staging kernel: the best (row-0 value, column) of a
+// workgroup's slots, and the slot itself.
+struct SPart {
+    double v;
+    int32_t i;
+    int32_t t;
+};
 
-    // Step 1
-    double v = __builtin_inf();
-    int32_t q = kNoIndex;
-    if (J == 0 && s.fresh) {
-        for (int32_t c = tid; c < n + m; c += nt) {
-            const double t = T[(int64_t)c * ld];
-            if (lex_less(t, c, v, q)) {
-                v = t;
+// Step 2 partial of one select workgroup: its best (ratio, row), a NaN flag,
+// and, read by the thread that owns that row, the pivot value (the row's
+// entry of column q after the earlier pivots), the column basic in that row
+// and that column's slot (-1 when it has none).
+struct GRatio {
+    double v;
+    int32_t r;
+    int32_t bad;
+    double p;
+    int32_t leave;
+    int32_t lpos;
+};
+
+// Lexicographic argmin that carries an int payload along with the winner.
+__device__ __forceinline__ void wave_argmin_t(double &v, int32_t &i, int32_t &t) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int32_t oi = __shfl_xor(i, off, 64);
+        const int32_t ot = __shfl_xor(t, off, 64);
+        if (lex_less(ov, oi, v, i)) {
+            v = ov;
+            i = oi;
+            t = ot;
+        }
+    }
+}
+
+__device__ __forceinline__ void block_argmin_t(double &v, int32_t &i, int32_t &t, double *sv, int32_t *si,
+                                               int32_t *sl) {
+    wave_argmin_t(v, i, t);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        sv[wave] = v;
+        si[wave] = i;
+        sl[wave] = t;
+    }
+    __syncthreads();
+    v = lane < nw ? sv[lane] : __builtin_inf();
+    i = lane < nw ? si[lane] : kNoIndex;
+    t = lane < nw ? sl[lane] : -1;
+    wave_argmin_t(v, i, t);
+}
+
+// Step 1 partials reduced in batches of 8 loads, so that a thread's loads
+// are in flight together; `slot` gives the winner's slot (-1 for partials
+// that carry none).
+template <typename P>
+__device__ __forceinline__ void reduce_parts(const P *__restrict__ pp, int32_t np, int tid, int nt, double &v,
+                                             int32_t &q, int32_t &slot) {
+    for (int32_t k0 = tid; k0 < np; k0 += 8 * nt) {
+        P a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t k = k0 + u * nt;
+            if (k < np) a[u] = pp[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t k = k0 + u * nt;
+            if (k < np && lex_less(a[u].v, a[u].i, v, q)) {
+                v = a[u].v;
+                q = a[u].i;
+                if constexpr (std::is_same_v<P, SPart>) slot = a[u].t;
+            }
+        }
+    }
+}
+
+// Row 0 of columns [0, ncols) reduced in batches of 8 strided loads (the
+// first Step 1 of a solve, before any partials exist).
+__device__ __forceinline__ void scan_row0(const double *__restrict__ T, int64_t ld, int32_t ncols, int tid, int nt,
+                                          double &v, int32_t &q) {
+    for (int32_t c0 = tid; c0 < ncols; c0 += 8 * nt) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t c = c0 + u * nt;
+            t[u] = c < ncols ? T[(int64_t)c * ld] : __builtin_inf();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t c = c0 + u * nt;
+            if (c < ncols && lex_less(t[u], c, v, q)) {
+                v = t[u];
                 q = c;
             }
         }
-    } else {
-        const ArgMin *pp = J == 0 ? parts : sparts;
-        const int32_t np = J == 0 ? s.nparts : nsparts;
-        for (int32_t k = tid; k < np; k += nt) {
-            const ArgMin a = pp[k];
-            if (lex_less(a.v, a.i, v, q)) {
-                v = a.v;
-                q = a.i;
-            }
+    }
+}
+
+// Steps 1 and 2 of pivot J of the group (J is a template argument so that
+// the chain's coefficients load without a wait per pivot):
+//   Step 1  J = 0: final stage of the argmin over the update's partials (a
+//           scan of row 0 before the first pivot); J > 0: over the staging
+//           kernel's partials of row 0 after pivot J-1, which also name the
+//           entering column's slot;
+//   Step 2  column q and the RHS column after the J earlier pivots, rebuilt
+//           from the tableau by the chain above; column q is kept as F_J.
+// Then the decision (r, q, p, leaving column), the basis, the log and, if the
+// leaving column is not in the list yet, its appended slot.
+//
+// G workgroups of 256 threads, each taking rows [w*span, (w+1)*span) of
+// Step 2 (about one row per thread). A thread's first row is requested
+// before Step 1 finishes (its RHS and pivot-column entries, the column basic
+// in it and that column's slot), so that after Step 1 only column q remains
+// to load. Every workgroup runs Step 1 itself (the same reduction in the
+// same order, so all agree on q), writes one partial and takes a ticket; the
+// last to arrive (device-scope fences around the ticket) reduces the
+// partials and records the decision. Nothing waits for another workgroup, so
+// the launch cannot deadlock. For J = 0 the previous group is closed by that
+// last workgroup before it reads the list, or by workgroup 0 when no pivot
+// follows; no other workgroup reads the list, the slot map or the group's
+// count then (the slots read ahead by J = 0 are not used).
+template <int J>
+__global__ __launch_bounds__(256) void k_gselect(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                 int32_t K, const ArgMin *__restrict__ parts,
+                                                 const SPart *__restrict__ sparts, int32_t nsparts,
+                                                 DevState *__restrict__ st, GroupState *__restrict__ gs,
+                                                 double *__restrict__ Fk, double *__restrict__ Rk,
+                                                 double *__restrict__ D, int32_t *__restrict__ cols,
+                                                 int32_t *__restrict__ pos, int32_t *__restrict__ basis,
+                                                 int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
+                                                 GRatio *__restrict__ rparts, uint32_t *__restrict__ ticket) {
+    __shared__ double sv[4];
+    __shared__ int32_t si[4], sl[4];
+    __shared__ uint32_t s_last;
+    __shared__ double s_p;
+    __shared__ int32_t s_leave, s_lpos;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int G = gridDim.x, w = blockIdx.x;
+    const int64_t Lg = (int64_t)n + 1 + K;
+    const int64_t W = (int64_t)n + m + 1;
+    const double *rhs = T + (W - 1) * ld;
+
+    // read ahead: this thread's first row
+    const int32_t span = (m + 1 + G - 1) / G;
+    const int32_t i0 = w * span, i1 = min(m + 1, i0 + span);
+    const int32_t ia = i0 + tid;
+    const bool has_a = ia < i1;
+    double bb_a = 0.0;
+    double f_a[J > 0 ? J : 1];
+    int32_t leave_a = -1, lpos_a = -1;
+    if (has_a) {
+        bb_a = rhs[ia];
+#pragma unroll
+        for (int k = 0; k < J; ++k) f_a[k] = Fk[(int64_t)k * ld + ia];
+        if (ia >= 1) {
+            leave_a = basis[ia - 1];
+            lpos_a = pos[leave_a];
         }
     }
-    block_argmin(v, q, sv, si);
-    if (v != v || v >= -s.eps_d) {
-        if (tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
-        return;
-    }
-
-    // Step 2 on column q and the RHS after the J earlier pivots. Every
-    // nonbasic column has a slot; a missing one would be a broken list, which
-    // ends the solve instead of reading outside R.
-    const int32_t tq = pos[q];
-    if (tq < 0) {
-        if (tid == 0) st->status = LP_NUMERICAL;
-        return;
-    }
     int32_t rk[J > 0 ? J : 1];
-    double Rq[J > 0 ? J : 1], Rb[J > 0 ? J : 1];
+    double Rb[J > 0 ? J : 1];
 #pragma unroll
     for (int k = 0; k < J; ++k) {
         rk[k] = gs->r[k];
-        Rq[k] = Rk[(int64_t)k * Lg + tq];
         Rb[k] = Rk[(int64_t)k * Lg + n];
     }
+
+    const DevState s = *st;
+    if (s.status != LP_RUNNING || s.pivots >= s.stop_at || (J > 0 && gs->kdone != J)) {
+        if (J == 0 && w == 0 && tid == 0) close_group(gs, cols, pos, n);
+        return;
+    }
+
+    // Step 1
+    double v = __builtin_inf();
+    int32_t q = kNoIndex, tq = -1;
+    if (J == 0 && s.fresh)
+        scan_row0(T, ld, n + m, tid, nt, v, q);
+    else if (J == 0)
+        reduce_parts(parts, s.nparts, tid, nt, v, q, tq);
+    else
+        reduce_parts(sparts, nsparts, tid, nt, v, q, tq);
+    block_argmin_t(v, q, tq, sv, si, sl);
+    if (v != v || v >= -s.eps_d) {
+        if (w == 0 && tid == 0) {
+            st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            if (J == 0) close_group(gs, cols, pos, n);
+        }
+        return;
+    }
+    // every nonbasic column has a slot; a missing one (a broken list) ends
+    // the solve below instead of reading outside R
+    const int32_t tq_safe = tq < 0 ? 0 : tq;
+    double Rq[J > 0 ? J : 1];
+#pragma unroll
+    for (int k = 0; k < J; ++k) Rq[k] = Rk[(int64_t)k * Lg + tq_safe];
+
+    // Step 2 on this workgroup's rows of column q and the RHS after the J
+    // earlier pivots
     const double *colq = T + (int64_t)q * ld;
-    const double *rhs = T + (W - 1) * ld;
     double *Fj = Fk + (int64_t)J * ld;
     double rv = __builtin_inf();
     int32_t r = kNoIndex;
     int bad = 0;
-    for (int32_t i = tid; i <= m; i += nt) {
-        double a = colq[i], bb = rhs[i];
+    double p_best = 0.0;
+    int32_t leave_best = -1, lpos_best = -1;
+    for (int32_t i = ia; i < i1; i += nt) {
+        double a = colq[i], bb;
         double f[J > 0 ? J : 1];
+        int32_t leave_i = -1, lpos_i = -1;
+        if (i == ia) {
+            bb = bb_a;
 #pragma unroll
-        for (int k = 0; k < J; ++k) f[k] = Fk[(int64_t)k * ld + i];
+            for (int k = 0; k < J; ++k) f[k] = f_a[k];
+            leave_i = leave_a;
+            lpos_i = lpos_a;
+        } else {
+            bb = rhs[i];
+#pragma unroll
+            for (int k = 0; k < J; ++k) f[k] = Fk[(int64_t)k * ld + i];
+            leave_i = basis[i - 1];
+            lpos_i = pos[leave_i];
+        }
 #pragma unroll
         for (int k = 0; k < J; ++k) {
             if (i == rk[k]) {
@@ -236,27 +373,69 @@ __global__ __launch_bounds__(1024) void k_gselect(const double *__restrict__ T, 
             else if (lex_less(ratio, i, rv, r)) {
                 rv = ratio;
                 r = i;
+                p_best = a;
+                leave_best = leave_i;
+                lpos_best = lpos_i;
             }
         }
     }
+    const int32_t r_mine = r;
     bad = __syncthreads_or(bad);
     block_argmin(rv, r, sv, si);
-    if (bad || r == kNoIndex || s.pivots >= s.max_pivots) {
-        if (tid == 0) st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+    if (r != kNoIndex && r_mine == r) {  // the one thread that owns row r
+        s_p = p_best;
+        s_leave = leave_best;
+        s_lpos = lpos_best;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        rparts[w] = r == kNoIndex ? GRatio{rv, r, bad, 0.0, -1, -1} : GRatio{rv, r, bad, s_p, s_leave, s_lpos};
+        __threadfence();
+        s_last = atomicAdd(ticket, 1u) == (uint32_t)(G - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    // last workgroup: the decision (G <= 256: one partial per thread)
+    GRatio pr{__builtin_inf(), kNoIndex, 0, 0.0, -1, -1};
+    if (tid < G) pr = rparts[tid];
+    rv = pr.v;
+    r = pr.r;
+    int32_t wk = tid;
+    bad = __syncthreads_or(pr.bad);
+    block_argmin_t(rv, r, wk, sv, si, sl);
+    if (r != kNoIndex && wk == tid) {
+        s_p = pr.p;
+        s_leave = pr.leave;
+        s_lpos = pr.lpos;
+    }
+    if (J == 0) {
+        if (tid == 0) close_group(gs, cols, pos, n);
+        // appended slots start with R = 0 and a row-0 entry of 0: the exact
+        // values for a column that is basic (a unit vector) before it leaves
+        if (tid < K * K) Rk[(int64_t)(tid / K) * Lg + n + 1 + tid % K] = 0.0;
+        if (tid < K) D[n + 1 + tid] = 0.0;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    *ticket = 0;  // ready for the next launch (ordered by the kernel boundary)
+    if (J > 0 && tq < 0) {
+        st->status = LP_NUMERICAL;
         return;
     }
-    if (tid != 0) return;
-    // p = entry r of column q after the J earlier pivots, by the same chain
-    double p = colq[r];
-#pragma unroll
-    for (int k = 0; k < J; ++k) p = (r == rk[k]) ? Rq[k] : fma(-Fk[(int64_t)k * ld + r], Rq[k], p);
-    const int32_t leave = basis[r - 1];
+    if (bad || r == kNoIndex || s.pivots >= s.max_pivots) {
+        st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+        return;
+    }
+    const int32_t leave = s_leave;
+    const int32_t lpos = J == 0 ? pos[leave] : s_lpos;  // J = 0: the slot map after closing
     const int32_t na = gs->napp;
     gs->r[J] = r;
     gs->q[J] = q;
     gs->l[J] = leave;
-    gs->p[J] = p;
-    if (pos[leave] < 0) {
+    gs->p[J] = s_p;
+    if (lpos < 0) {
         cols[n + 1 + na] = leave;
         pos[leave] = n + 1 + na;
         gs->napp = na + 1;
@@ -275,15 +454,15 @@ __global__ __launch_bounds__(1024) void k_gselect(const double *__restrict__ T, 
 // after the J earlier pivots (chain from the tableau), R_J[t] = that / p_J,
 // and the slot's row-0 entry after pivot J, D[t] = fma(-F_J[0], R_J[t], D[t])
 // (row 0 is never a pivot row). Each workgroup then reduces its slots'
-// (D, column) pairs to one Step 1 partial for pivot J+1.
+// (D, column) pairs to one Step 1 partial for pivot J+1, with the slot.
 template <int J>
 __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                 int32_t K, const GroupState *__restrict__ gs,
                                                 const double *__restrict__ Fk, double *__restrict__ Rk,
                                                 double *__restrict__ D, const int32_t *__restrict__ cols,
-                                                ArgMin *__restrict__ sparts) {
+                                                SPart *__restrict__ sparts) {
     __shared__ double sv[4];
-    __shared__ int32_t si[4];
+    __shared__ int32_t si[4], sl[4];
     if (gs->kdone <= J) return;
     const int64_t Lg = (int64_t)n + 1 + K;
     const int32_t r = gs->r[J];
@@ -298,7 +477,7 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
     const double f0 = Fk[(int64_t)J * ld];
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double v = __builtin_inf();
-    int32_t idx = kNoIndex;
+    int32_t idx = kNoIndex, slot = -1;
     if (t < Lg) {
         const int32_t c = cols[t];
         if (c >= 0) {
@@ -317,39 +496,42 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
             if (c != n + m) {
                 v = d;
                 idx = c;
+                slot = (int32_t)t;
             }
         }
     }
-    block_argmin(v, idx, sv, si);
-    if (threadIdx.x == 0) sparts[blockIdx.x] = ArgMin{v, idx};
+    block_argmin_t(v, idx, slot, sv, si, sl);
+    if (threadIdx.x == 0) sparts[blockIdx.x] = SPart{v, idx, slot};
 }
 
 // Step 3 for the whole group in one pass over (row chunk, slot group) tiles:
 // every listed column is read once, has the group's pivots applied in order,
-// and is written once. A row chunk is B row pairs (one double2 per thread);
-// a slot group is C consecutive list slots. The row-chunk-0 workgroup of each
-// slot group reduces its new row-0 entries to one Step 1 partial and counts
-// the columns the group changed (some R_k nonzero).
+// and is written once. A row chunk is B rows (one per thread: with two, the
+// compiler runs one row's whole chain before the other's and keeps every R
+// entry of the tile live in between); a slot group is C consecutive list
+// slots. The row-chunk-0 workgroup of each slot group reduces its new row-0
+// entries to one Step 1 partial and counts the columns the group changed
+// (some R_k nonzero).
 //
-// KF is the group size of the context. Full slot groups take a straight-line
-// path: the pivot-column loads, then the tile's columns, one wait, the chain,
-// and stores predicated on the row range (threads past the last row pair load
-// row pair 0 and store nothing), so the last row chunk needs no separate
-// code. A group cut short (the solve ended, or a pivot budget ran out) has
-// kd < KF pivots; the missing ones are applied as exact identities, with
-// R = 0, F = 0 and no pivot row: fma(-0, 0, x) returns x for every x,
-// signed zeros, infinities and NaN included. The last, partial slot group
-// takes a plain loop.
+// KF >= the context's group size K (instances exist for a few sizes). Full
+// slot groups take a straight-line path: the pivot-column loads, the tile's
+// columns, the tile's R entries into LDS, one barrier, the chain, and stores
+// predicated on the row range (threads past row m load row 0 and store
+// nothing), so the last row chunk needs no separate code. Pivots the group
+// did not reach (kd <= k < KF) are applied as exact identities, with R = 0,
+// F = 0 and no pivot row: fma(-0, 0, x) returns x for every x, signed zeros,
+// infinities and NaN included. The last, partial slot group takes a plain
+// loop.
 template <int B, int C, int KF>
-__global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+__global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t ld, int32_t m, int32_t n, int64_t Lg,
                                                int32_t rowchunks, const int32_t *__restrict__ cols,
                                                const double *__restrict__ Rk, const double *__restrict__ Fk,
                                                const GroupState *__restrict__ gs, ArgMin *__restrict__ parts,
                                                unsigned long long *__restrict__ cols_done) {
+    __shared__ double sR[C][KF];
     const int kd = gs->kdone;
     if (kd == 0) return;
     const int32_t Lv = n + 1 + gs->napp;
-    const int64_t Lg = (int64_t)n + 1 + KF;
     const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
     const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
     const int32_t c0 = g * C;
@@ -358,42 +540,48 @@ __global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t l
         if (row0) parts[g] = ArgMin{__builtin_inf(), kNoIndex};
         return;
     }
-    const int32_t nvec = (m + 2) / 2;
-    const int32_t v = rc * B + (int32_t)threadIdx.x;
-    const bool live = v < nvec;
-    const int32_t vs = live ? v : 0;
-    const int32_t i0 = 2 * v;
-    const int64_t ldv = ld / 2;
-    const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
+    const int32_t i = rc * B + (int32_t)threadIdx.x;
+    const bool live = i <= m;
+    const int32_t is = live ? i : 0;
 
     if (c0 + C <= Lv) {
         int32_t rk[KF];
-        double2 f[KF];
+        double f[KF];
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
             const bool on = k < kd;
             rk[k] = on ? gs->r[k] : -1;
-            f[k] = F2[k * ldv + vs];
-            if (!on) f[k] = double2{0.0, 0.0};
+            f[k] = Fk[(int64_t)k * ld + is];
+            if (!on) f[k] = 0.0;
         }
-        double2 *p[C];
-        double Rj[C][KF];
+        double *p[C];
+        double x[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            p[c] = reinterpret_cast<double2 *>(T + (int64_t)cols[c0 + c] * ld) + vs;
-#pragma unroll
-            for (int k = 0; k < KF; ++k) Rj[c][k] = k < kd ? Rk[(int64_t)k * Lg + c0 + c] : 0.0;
-        }
-        double2 x[C];
+        for (int c = 0; c < C; ++c) p[c] = T + (int64_t)cols[c0 + c] * ld + is;
 #pragma unroll
         for (int c = 0; c < C; ++c) x[c] = *p[c];
+        for (int t = threadIdx.x; t < C * KF; t += B) {  // C * KF may exceed B
+            const int k = t % KF, c = t / KF;
+            sR[c][k] = k < kd ? Rk[(int64_t)k * Lg + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        const int32_t wrow0 = rc * B + (int32_t)(threadIdx.x & ~63u);  // first row of this wave
 #pragma unroll
-        for (int k = 0; k < KF; ++k)
+        for (int k = 0; k < KF; ++k) {
+            double R[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                x[c].x = (i0 == rk[k]) ? Rj[c][k] : fma(-f[k].x, Rj[c][k], x[c].x);
-                x[c].y = (i0 + 1 == rk[k]) ? Rj[c][k] : fma(-f[k].y, Rj[c][k], x[c].y);
+                R[c] = sR[c][k];
+                x[c] = fma(-f[k], R[c], x[c]);
             }
+            // only the wave that holds pivot row r_k replaces that row's
+            // entries by R (a uniform test; the fma results there are dropped)
+            if ((uint32_t)(rk[k] - wrow0) < 64u) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (i == rk[k]) x[c] = R[c];
+            }
+        }
         if (live) {
 #pragma unroll
             for (int c = 0; c < C; ++c) *p[c] = x[c];
@@ -405,13 +593,12 @@ __global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t l
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const int32_t jc = cols[c0 + c];
-                if (jc != n + m && lex_less(x[c].x, jc, val, idx)) {
-                    val = x[c].x;
+                if (jc != n + m && lex_less(x[c], jc, val, idx)) {
+                    val = x[c];
                     idx = jc;
                 }
                 bool nz = false;
-#pragma unroll
-                for (int k = 0; k < KF; ++k) nz |= Rj[c][k] != 0.0;
+                for (int k = 0; k < kd; ++k) nz |= Rk[(int64_t)k * Lg + c0 + c] != 0.0;
                 changed += nz;
             }
             parts[g] = ArgMin{val, idx};
@@ -427,22 +614,20 @@ __global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t l
     unsigned long long changed = 0;
     for (int c = 0; c < cn; ++c) {
         const int32_t jc = cols[c0 + c];
-        double2 *cp = reinterpret_cast<double2 *>(T + (int64_t)jc * ld) + vs;
-        double2 x = *cp;
+        double *cp = T + (int64_t)jc * ld + is;
+        double x = *cp;
         bool nz = false;
 #pragma unroll 1
         for (int k = 0; k < kd; ++k) {
             const double R = Rk[(int64_t)k * Lg + c0 + c];
-            const double2 ff = F2[k * ldv + vs];
             const int32_t r = gs->r[k];
             nz |= R != 0.0;
-            x.x = (i0 == r) ? R : fma(-ff.x, R, x.x);
-            x.y = (i0 + 1 == r) ? R : fma(-ff.y, R, x.y);
+            x = (i == r) ? R : fma(-Fk[(int64_t)k * ld + is], R, x);
         }
         if (live) *cp = x;
         changed += nz;
-        if (row0 && jc != n + m && lex_less(x.x, jc, val, idx)) {
-            val = x.x;
+        if (row0 && jc != n + m && lex_less(x, jc, val, idx)) {
+            val = x;
             idx = jc;
         }
     }

@@ -10,9 +10,9 @@ namespace {
 
 template <int J>
 void select_j(const FusedArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_gselect<J>), dim3(1), dim3(1024), 0, s, (const double *)a.T, a.ld, a.m, a.n, a.K,
-                       (const ArgMin *)a.parts, (const ArgMin *)a.sparts, a.nsparts, a.st, a.gs, a.Fk, a.Rk, a.D,
-                       a.cols, a.pos, a.basis, a.log_r, a.log_q);
+    hipLaunchKernelGGL((k_gselect<J>), dim3((unsigned)a.select_wgs), dim3(256), 0, s, (const double *)a.T, a.ld, a.m,
+                       a.n, a.K, (const ArgMin *)a.parts, (const SPart *)a.sparts, a.nsparts, a.st, a.gs, a.Fk, a.Rk,
+                       a.D, a.cols, a.pos, a.basis, a.log_r, a.log_q, a.rparts, a.ticket);
 }
 
 template <int J>
@@ -22,32 +22,33 @@ void stage_j(const FusedArgs &a, hipStream_t s) {
                        a.sparts);
 }
 
-template <int B, int C, int K>
+template <int B, int C, int KF>
 void update(const FusedArgs &a, unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
     if (e0)
-        hipExtLaunchKernelGGL((k_gupdate<B, C, K>), dim3(grid), dim3(B), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n,
+        hipExtLaunchKernelGGL((k_gupdate<B, C, KF>), dim3(grid), dim3(B), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg,
                               a.rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
                               (const GroupState *)a.gs, a.parts, a.cols_done);
     else
-        hipLaunchKernelGGL((k_gupdate<B, C, K>), dim3(grid), dim3(B), 0, s, a.T, a.ld, a.m, a.n, a.rowchunks,
+        hipLaunchKernelGGL((k_gupdate<B, C, KF>), dim3(grid), dim3(B), 0, s, a.T, a.ld, a.m, a.n, Lg, a.rowchunks,
                            (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
                            (const GroupState *)a.gs, a.parts, a.cols_done);
 }
 
 using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
 
+// Update instances exist for groups of up to 2, 4, 8, 12 and 16 pivots; a
+// group size in between takes the next larger instance (its surplus pivots
+// are exact identities).
 template <int B, int C>
 UpdateFn pick_k(int K) {
-    switch (K) {
-        case 2: return update<B, C, 2>;
-        case 3: return update<B, C, 3>;
-        case 4: return update<B, C, 4>;
-        case 5: return update<B, C, 5>;
-        case 6: return update<B, C, 6>;
-        case 7: return update<B, C, 7>;
-        case 8: return update<B, C, 8>;
-        default: return nullptr;
-    }
+    if (K < 2) return nullptr;
+    if (K <= 2) return update<B, C, 2>;
+    if (K <= 4) return update<B, C, 4>;
+    if (K <= 8) return update<B, C, 8>;
+    if (K <= 12) return update<B, C, 12>;
+    if (K <= 16) return update<B, C, 16>;
+    return nullptr;
 }
 
 // Tile shapes with instances: 64, 128 or 256 threads (one row pair each) by
@@ -77,6 +78,14 @@ void launch_fused_select(const FusedArgs &a, int j, hipStream_t s) {
         case 5: select_j<5>(a, s); break;
         case 6: select_j<6>(a, s); break;
         case 7: select_j<7>(a, s); break;
+        case 8: select_j<8>(a, s); break;
+        case 9: select_j<9>(a, s); break;
+        case 10: select_j<10>(a, s); break;
+        case 11: select_j<11>(a, s); break;
+        case 12: select_j<12>(a, s); break;
+        case 13: select_j<13>(a, s); break;
+        case 14: select_j<14>(a, s); break;
+        case 15: select_j<15>(a, s); break;
         default: break;
     }
 }
@@ -91,6 +100,14 @@ void launch_fused_stage(const FusedArgs &a, int j, hipStream_t s) {
         case 5: stage_j<5>(a, s); break;
         case 6: stage_j<6>(a, s); break;
         case 7: stage_j<7>(a, s); break;
+        case 8: stage_j<8>(a, s); break;
+        case 9: stage_j<9>(a, s); break;
+        case 10: stage_j<10>(a, s); break;
+        case 11: stage_j<11>(a, s); break;
+        case 12: stage_j<12>(a, s); break;
+        case 13: stage_j<13>(a, s); break;
+        case 14: stage_j<14>(a, s); break;
+        case 15: stage_j<15>(a, s); break;
         default: break;
     }
 }

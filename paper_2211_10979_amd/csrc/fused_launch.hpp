@@ -13,7 +13,7 @@ struct FusedArgs {
     double *T;
     int64_t ld;
     int32_t m, n, K;
-    int32_t rowchunks;  // update tiles: row chunks
+    int32_t rowchunks;  // update tiles: row chunks of one row per thread
     int32_t nsparts;    // staging workgroups (= Step 1 partials of the staging kernel)
     int32_t nparts;     // update slot groups (= Step 1 partials of the update kernel)
     DevState *st;
@@ -22,9 +22,20 @@ struct FusedArgs {
     double *Rk;   // K rows of n + 1 + K doubles
     double *D;    // n + 1 + K doubles
     int32_t *cols, *pos, *basis, *log_r, *log_q;
-    ArgMin *parts, *sparts;
+    ArgMin *parts;
+    SPart *sparts;
     unsigned long long *cols_done;
+    int32_t select_wgs;  // workgroups of the select kernel (at most kMaxSelectWgs)
+    GRatio *rparts;      // their Step 2 partials
+    uint32_t *ticket;    // their arrival counter, zero between launches
 };
+
+// Select workgroups: enough for about one Step 2 row per thread.
+constexpr int kMaxSelectWgs = 64;
+inline int32_t select_workgroups_for(int32_t m) {
+    const int32_t g = (m + 1 + 255) / 256;
+    return g < 1 ? 1 : (g > kMaxSelectWgs ? kMaxSelectWgs : g);
+}
 
 // True when an update kernel instance exists for this tile shape and group size.
 bool fused_update_supported(int block, int cols, int rv, int K);

@@ -45,8 +45,8 @@ struct UpdateConfig {
 // most independent, shortest streams: 5.5 TB/s at m = 8000) and four columns
 // per workgroup below 4096 rows; with pivot fusion, kFusedCols columns (the
 // group's pivot columns are then loaded once per kFusedCols columns).
-constexpr int kFusedCols = 4;
-constexpr int kAutoFuse = 8;
+constexpr int kFusedCols = 8;
+constexpr int kAutoFuse = 12;
 
 UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fused) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
@@ -104,7 +104,8 @@ struct lp_ctx {
     int64_t Lg = 0;                           // list slots: n + 2 (K = 1) or n + 1 + K
     GroupState *gs = nullptr;                 // K > 1: decisions of the current group
     double *D = nullptr;                      // K > 1: row-0 entry of every slot during a group
-    ArgMin *sparts = nullptr;                 // K > 1: Step 1 partials of the staging kernel
+    SPart *sparts = nullptr;                  // K > 1: Step 1 partials of the staging kernel
+    GRatio *grparts = nullptr;                // K > 1: Step 2 partials of the select workgroups
     int nsparts = 0;
     bool use_graph = true;
     bool timing = false;
@@ -151,6 +152,7 @@ void free_ctx(lp_ctx *h) {
     if (h->gs) (void)hipFree(h->gs);
     if (h->D) (void)hipFree(h->D);
     if (h->sparts) (void)hipFree(h->sparts);
+    if (h->grparts) (void)hipFree(h->grparts);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -179,7 +181,7 @@ int validate_opts(const lp_options &o) {
         o.update_block != 512 && o.update_block != 1024)
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
-    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 8]");
+    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 16]");
     return LP_OK;
 }
 
@@ -311,7 +313,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     if (h->fuse > 1) {
         if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->sparts, (size_t)h->nsparts * sizeof(ArgMin))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->sparts, (size_t)h->nsparts * sizeof(SPart))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->grparts, kMaxSelectWgs * sizeof(GRatio))) return fail(rc);
     }
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
@@ -437,7 +440,7 @@ FusedArgs fused_args(lp_ctx *h) {
     a.m = h->m;
     a.n = h->n;
     a.K = h->fuse;
-    a.rowchunks = h->ucfg.rowchunks;
+    a.rowchunks = (int32_t)(((int64_t)h->m + h->ucfg.block) / h->ucfg.block);  // one row per thread
     a.nsparts = h->nsparts;
     a.nparts = h->nparts;
     a.st = h->st;
@@ -453,6 +456,9 @@ FusedArgs fused_args(lp_ctx *h) {
     a.parts = h->parts;
     a.sparts = h->sparts;
     a.cols_done = h->cols_done;
+    a.select_wgs = select_workgroups_for(h->m);
+    a.rparts = h->grparts;
+    a.ticket = h->ticket;
     return a;
 }
 

@@ -3,7 +3,7 @@ over the tableau) against the CPU oracle, through the C ABI.
 
 Bar: as for one pivot per pass — identical pivot log, basis and status, and
 the tableau equal element by element after every group and at the end — for
-every group size K in 1..8, including LPs on which a column leaves and enters
+every group size K in 1..16, including LPs on which a column leaves and enters
 again, or enters and leaves again, inside one group.
 """
 
@@ -87,7 +87,7 @@ def solve_and_compare(A, b, c, **opts):
         o.close()
 
 
-@pytest.mark.parametrize("K", [2, 3, 4, 5, 8])
+@pytest.mark.parametrize("K", [2, 3, 4, 5, 8, 11, 16])
 def test_degenerate_battery(K):
     """120 small LPs; the battery contains in-group re-entries of both kinds."""
     say(f"fused K={K}: degenerate battery")
@@ -101,7 +101,7 @@ def test_degenerate_battery(K):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K", [2, 4, 7, 8])
+@pytest.mark.parametrize("K", [2, 4, 7, 8, 13, 16])
 def test_group_boundaries_by_stepping(K):
     """lp_step budgets that cut groups short and ones that span several
     groups: the tableau matches the oracle's after every step."""
@@ -131,7 +131,7 @@ def test_group_boundaries_by_stepping(K):
         o.close()
 
 
-@pytest.mark.parametrize("K", [1, 3, 4, 8])
+@pytest.mark.parametrize("K", [1, 3, 4, 8, 16])
 def test_dense_2000_full_solve(K):
     lp = lpgen.workload("dense_2000x2000")
     say(f"fused K={K}: dense_2000x2000")
@@ -145,7 +145,9 @@ def test_dense_2000_full_solve(K):
                                   dict(use_graph=0), dict(chunk_pivots=9), dict(time_kernels=1),
                                   dict(cols_per_block=2, fuse_pivots=8), dict(cols_per_block=4, fuse_pivots=6),
                                   dict(cols_per_block=8, fuse_pivots=7),
-                                  dict(cols_per_block=4, fuse_pivots=8, time_kernels=1)])
+                                  dict(cols_per_block=4, fuse_pivots=8, time_kernels=1),
+                                  dict(cols_per_block=8, fuse_pivots=16, time_kernels=1),
+                                  dict(cols_per_block=2, fuse_pivots=12), dict(cols_per_block=1, fuse_pivots=9)])
 def test_update_shapes(opts):
     A, b, c = degenerate_lp(7, 1)
     lp = lpgen.dense_lp(9, 333, 444)
@@ -229,7 +231,7 @@ def test_work_counter_counts_the_union_of_a_group():
 def test_options_are_checked():
     lp = lpgen.dense_lp(2, 600, 200)  # m + 1 > 256: every update option applies
     A, b, c = lp.A, lp.b, lp.c
-    for bad in (dict(fuse_pivots=9), dict(fuse_pivots=-1), dict(fuse_pivots=4, cols_per_block=16),
+    for bad in (dict(fuse_pivots=17), dict(fuse_pivots=-1), dict(fuse_pivots=4, cols_per_block=16),
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
                 dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1)):
@@ -244,6 +246,6 @@ def test_options_are_checked():
         lpgpu.lp_destroy(h)
     h = lpgpu.lp_create(A, b, c)
     try:
-        assert lpgpu.lp_get_info(h).update_fuse == 8
+        assert lpgpu.lp_get_info(h).update_fuse == 12
     finally:
         lpgpu.lp_destroy(h)
