@@ -47,7 +47,9 @@ enum {
     LP_UNBOUNDED = 1,  /* Step 2 found no eligible row */
     LP_ITER_LIMIT = 2, /* max_pivots pivots done, another one needed */
     LP_NUMERICAL = 3,  /* a NaN reached Step 1 or Step 2 */
-    LP_RUNNING = 4     /* not finished (lp_step budget ran out, or not solved yet) */
+    LP_RUNNING = 4,    /* not finished (lp_step budget ran out, or not solved yet) */
+    LP_STALLED = 5     /* a wait of the one-launch decision kernel timed out (its workgroups
+                          were not all resident); the solve was abandoned */
 };
 
 /* Return codes. */
@@ -96,7 +98,7 @@ typedef struct {
                                compute unit (block 64..512), one column per tile (default 0) */
     int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
     int32_t select_workgroups; /* Steps 1-2 kernel: workgroups (1..64; 0 = 1) */
-    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..16; 0 = auto: 12 unless
+    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..16; 0 = auto: 16 unless
                                an option above asks for a form only K = 1 has). With K > 1 the
                                solver decides K pivots one after the other, each from row 0,
                                its pivot column and the RHS rebuilt by replaying the earlier
@@ -107,7 +109,12 @@ typedef struct {
                                update_block 0 or <= 256, cols_per_block <= 8,
                                rows_per_thread 0 or 1, update_hints 0, update_grid_stride 0 and
                                select_workgroups <= 1. */
-    int32_t reserved;
+    int32_t decide_kernel;  /* K > 1: 0 = auto (one launch for all decisions of a group when
+                               G = max(m + 1, n + 1 + K) / 256 rounded up is at most 128
+                               workgroups, else two launches per pivot); 1 = two launches per
+                               pivot */
+    int32_t decide_spin;    /* polls before a grid-barrier wait of the decision kernel gives up
+                               with LP_STALLED (0 = default, about 0.2 s) */
 } lp_options;
 
 typedef struct {

@@ -59,7 +59,8 @@ int lp_options_default(lp_options *o) {
     o->update_unroll = 0;
     o->select_workgroups = 0;
     o->fuse_pivots = 0;
-    o->reserved = 0;
+    o->decide_kernel = 0;
+    o->decide_spin = 0;
     return LP_OK;
 }
 

@@ -73,55 +73,74 @@ static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int3
 // basic give their slots below n to the appended columns that are nonbasic
 // at the end; the two counts are equal, since the group started with n
 // nonbasic columns in slots 0..n-1 and ends with n nonbasic columns, each of
-// which is either one that stayed in its slot or an appended one. The
-// group's columns are held in registers (fully unrolled loops, no local
-// arrays indexed at run time).
-static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, int32_t *__restrict__ pos, int32_t n) {
+// which is either one that stayed in its slot or an appended one. All reads
+// (the group, its appended slots, the slots of its entered columns) are
+// issued in one batch and the pairing is done in registers (fully unrolled
+// loops, no local arrays indexed at run time), so the close costs about two
+// memory round trips.
+static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                                   int32_t n) {
     const int kd = gs->kdone;
     if (kd == 0) return;
     const int na = gs->napp;
-    int32_t qk[kMaxFuse], lk[kMaxFuse];
+    int32_t qk[kMaxFuse], lk[kMaxFuse], app[kMaxFuse], pq[kMaxFuse];
 #pragma unroll
     for (int k = 0; k < kMaxFuse; ++k) {
         qk[k] = k < kd ? gs->q[k] : -1;
         lk[k] = k < kd ? gs->l[k] : -1;
     }
+#pragma unroll
+    for (int k = 0; k < kMaxFuse; ++k) {
+        app[k] = k < na ? cols[n + 1 + k] : -1;
+        pq[k] = k < kd ? pos[qk[k]] : -1;
+    }
     // the last event of the group decides: entered -> basic, left -> nonbasic
-    auto basic_at_end = [&](int32_t c) {
-        bool b = false;
+    bool qb[kMaxFuse], ab[kMaxFuse];  // entered column k / appended column s basic at the end
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k) {
-            if (qk[k] == c) b = true;
-            if (lk[k] == c) b = false;
+    for (int k = 0; k < kMaxFuse; ++k) {
+        bool bq = false, ba = false;
+#pragma unroll
+        for (int e = 0; e < kMaxFuse; ++e) {
+            if (qk[e] == qk[k]) bq = true;
+            if (lk[e] == qk[k]) bq = false;
+            if (qk[e] == app[k]) ba = true;
+            if (lk[e] == app[k]) ba = false;
         }
-        return b;
-    };
-    int next = 0;  // entered columns before `next` have been examined
-    for (int32_t s = n + 1; s < n + 1 + na; ++s) {
-        const int32_t c = cols[s];
-        if (basic_at_end(c)) {
-            pos[c] = -1;  // left and entered again within the group
-        } else {
-            // the next entered column that is still basic and holds a slot below n
-            int32_t t = -1;
+        qb[k] = bq;
+        ab[k] = ba;
+    }
+    bool free_k[kMaxFuse];  // entered column k still basic and holding a slot below n
 #pragma unroll
-            for (int k = 0; k < kMaxFuse; ++k) {
-                if (t < 0 && k >= next && k < kd) {
-                    const int32_t e = qk[k];
-                    const int32_t te = pos[e];
-                    if (te >= 0 && te < n && basic_at_end(e)) {
-                        pos[e] = -1;
-                        t = te;
-                        next = k + 1;
+    for (int k = 0; k < kMaxFuse; ++k) {
+        bool first = true;  // a column entered twice holds its slot once
+#pragma unroll
+        for (int e = 0; e < k; ++e) first &= qk[e] != qk[k];
+        free_k[k] = k < kd && first && pq[k] >= 0 && pq[k] < n && qb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxFuse; ++k)
+        if (k < kd && qb[k] && pq[k] >= 0) pos[qk[k]] = -1;
+#pragma unroll
+    for (int s = 0; s < kMaxFuse; ++s) {
+        if (s < na) {
+            const int32_t c = app[s];
+            if (ab[s]) {
+                pos[c] = -1;  // left and entered again within the group
+            } else {
+                int32_t t = -1;
+#pragma unroll
+                for (int k = 0; k < kMaxFuse; ++k)
+                    if (t < 0 && free_k[k]) {
+                        t = pq[k];
+                        free_k[k] = false;
                     }
+                if (t >= 0) {
+                    cols[t] = c;
+                    pos[c] = t;
                 }
             }
-            if (t >= 0) {
-                cols[t] = c;
-                pos[c] = t;
-            }
+            cols[n + 1 + s] = -1;
         }
-        cols[s] = -1;
     }
     gs->kdone = 0;
     gs->napp = 0;
@@ -502,6 +521,291 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
     }
     block_argmin_t(v, idx, slot, sv, si, sl);
     if (threadIdx.x == 0) sparts[blockIdx.x] = SPart{v, idx, slot};
+}
+
+// ---------------------------------------------------------------------------
+// All decisions of a group in one launch.
+//
+// k_gdecide runs the group's Steps 1-2 and the Step 3 inputs (what k_gselect
+// and k_gstage compute, with the same arithmetic in the same order) for up
+// to K pivots in one launch of G workgroups of 256 threads, G*256 covering
+// both the rows 0..m and the list slots. Thread (w, x) owns row w*256+x and
+// slot w*256+x for the whole group, and keeps their chain state in
+// registers across pivots: the row's entries of the group's pivot columns
+// (F_k[i]), the slot's normalised pivot-row entries (R_k[t]), its row-0
+// entry, its column, and the row's basic column. Per pivot, two grid
+// barriers separate the phases:
+//   pricing (every workgroup, over all staging partials) and the ratio test
+//     of its rows -> one Step 2 partial per workgroup;   barrier
+//   the decision (every workgroup reduces all Step 2 partials, so all agree;
+//     workgroup 0 records it) and the Step 3 inputs of its slots -> one
+//     Step 1 partial per workgroup;                       barrier.
+// The barrier is a counter of arrivals; a workgroup waits for G arrivals per
+// barrier passed. The wait is bounded (spin_limit polls): if some workgroup
+// never arrives (the G workgroups were not all resident), the waiting ones
+// set LP_STALLED and leave, so every wave exits. The last workgroup to exit
+// resets the counter for the next launch.
+struct GridSync {
+    uint32_t count;  // barrier arrivals in this launch
+    uint32_t exits;  // workgroups that have left
+};
+
+__device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, uint32_t spin_limit,
+                                             DevState *st, int32_t *s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this workgroup's writes before its arrival
+        atomicAdd(&gsync->count, 1u);
+        uint32_t it = 0;
+        bool ok = true;
+        while (__hip_atomic_load(&gsync->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++it > spin_limit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (!ok) atomicExch(&st->status, (int32_t)LP_STALLED);
+        __threadfence();  // the others' writes before this workgroup reads
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+__device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                            int32_t K, const ArgMin *__restrict__ parts, SPart *__restrict__ sparts,
+                                            DevState *__restrict__ st, GroupState *__restrict__ gs,
+                                            double *__restrict__ Fk, double *__restrict__ Rk,
+                                            int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                                            int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
+                                            int32_t *__restrict__ log_q, GRatio *__restrict__ rparts,
+                                            GridSync *__restrict__ gsync, uint32_t spin_limit) {
+    __shared__ double sv[4];
+    __shared__ int32_t si[4], sl[4];
+    __shared__ int32_t s_ok;
+    __shared__ double s_p;
+    __shared__ int32_t s_leave, s_inlist;
+    const int tid = threadIdx.x, nt = 256;
+    const int G = gridDim.x, w = blockIdx.x;
+    const int64_t Lg = (int64_t)n + 1 + K;
+    const int64_t W = (int64_t)n + m + 1;
+    uint32_t nbar = 0;
+
+    if (w == 0 && tid == 0) close_group(gs, cols, pos, n);
+    if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+
+    const DevState s0 = *st;
+    if (s0.status != LP_RUNNING) return;
+
+    // this thread's row and slot, and their state at the start of the group
+    const int32_t i = w * 256 + tid;
+    const bool has_row = i <= m;
+    const int32_t is = has_row ? i : 0;
+    const double rhs0 = T[(W - 1) * ld + is];
+    int32_t basis_i = (has_row && i >= 1) ? basis[i - 1] : -1;
+    bool inlist_i = basis_i >= 0 && pos[basis_i] >= 0;
+    const int32_t t = w * 256 + tid;
+    const bool has_slot = t < Lg;
+    int32_t c_t = has_slot ? cols[t] : -1;
+    double D_t = c_t >= 0 ? T[(int64_t)c_t * ld] : 0.0;
+    double frow[kMaxFuse], rslot[kMaxFuse];
+    int32_t rk[kMaxFuse];
+#pragma unroll
+    for (int k = 0; k < kMaxFuse; ++k) {
+        frow[k] = 0.0;
+        rslot[k] = 0.0;
+        rk[k] = -1;
+    }
+    int32_t napp = 0;
+
+    for (int j = 0; j < K; ++j) {
+        if (s0.pivots + j >= s0.stop_at) break;
+
+        // Step 1
+        double v = __builtin_inf();
+        int32_t q = kNoIndex, tq = -1;
+        if (j == 0 && s0.fresh)
+            scan_row0(T, ld, n + m, tid, nt, v, q);
+        else if (j == 0)
+            reduce_parts(parts, s0.nparts, tid, nt, v, q, tq);
+        else
+            reduce_parts(sparts, G, tid, nt, v, q, tq);
+        block_argmin_t(v, q, tq, sv, si, sl);
+        if (v != v || v >= -s0.eps_d) {
+            if (w == 0 && tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            break;
+        }
+        if (j > 0 && tq < 0) {  // a broken list ends the solve instead of reading outside R
+            if (w == 0 && tid == 0) st->status = LP_NUMERICAL;
+            break;
+        }
+
+        // Step 2 on this thread's row of column q and the RHS after the j
+        // earlier pivots; the row's entry of column q is kept as F_j[i]. The
+        // coefficients of all kMaxFuse steps are loaded in one batch (index
+        // clamped into the buffer) and the steps k >= j are masked out by
+        // selects, so that no load waits behind another.
+        const double *colq = T + (int64_t)q * ld;
+        const int32_t tqs = tq < 0 ? 0 : tq;
+        double Rq[kMaxFuse], Rb[kMaxFuse];
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k) {
+            const int64_t kk = k < K ? k : K - 1;
+            Rq[k] = Rk[kk * Lg + tqs];
+            Rb[k] = Rk[kk * Lg + n];
+        }
+        double a = colq[is], bb = rhs0;
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k) {
+            const bool on = k < j, piv = i == rk[k];
+            const double na = piv ? Rq[k] : fma(-frow[k], Rq[k], a);
+            const double nb = piv ? Rb[k] : fma(-frow[k], Rb[k], bb);
+            a = on ? na : a;
+            bb = on ? nb : bb;
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k)
+            if (k == j) frow[k] = a;
+        if (has_row) Fk[(int64_t)j * ld + i] = a;
+        double rv = __builtin_inf();
+        int32_t r = kNoIndex;
+        int bad = 0;
+        if (has_row && i >= 1) {
+            if (a != a || bb != bb) {
+                bad = 1;
+            } else if (a > s0.eps_p) {
+                const double ratio = bb / a;
+                if (ratio != ratio) {
+                    bad = 1;
+                } else {
+                    rv = ratio;
+                    r = i;
+                }
+            }
+        }
+        const int32_t r_mine = r;
+        bad = __syncthreads_or(bad);
+        block_argmin(rv, r, sv, si);
+        if (r != kNoIndex && r_mine == r) {  // the one thread that owns row r
+            s_p = a;
+            s_leave = basis_i;
+            s_inlist = inlist_i;
+        }
+        __syncthreads();
+        if (tid == 0)  // (lpos carries "the leaving column has a slot" here)
+            rparts[w] = r == kNoIndex ? GRatio{rv, r, bad, 0.0, -1, 0} : GRatio{rv, r, bad, s_p, s_leave, s_inlist};
+        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+
+        // the decision, reduced by every workgroup from all Step 2 partials
+        GRatio pr{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0};
+        if (tid < G) pr = rparts[tid];
+        rv = pr.v;
+        r = pr.r;
+        int32_t wk = tid;
+        bad = __syncthreads_or(pr.bad);
+        block_argmin_t(rv, r, wk, sv, si, sl);
+        if (r != kNoIndex && wk == tid) {
+            s_p = pr.p;
+            s_leave = pr.leave;
+            s_inlist = pr.lpos;
+        }
+        __syncthreads();
+        if (bad || r == kNoIndex || s0.pivots + j >= s0.max_pivots) {
+            if (w == 0 && tid == 0)
+                st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+            break;
+        }
+        const double p = s_p;
+        const int32_t leave = s_leave;
+        const int32_t aslot = s_inlist ? -1 : n + 1 + napp;  // appended slot of the leaving column
+        if (aslot >= 0) ++napp;
+        if (w == 0 && tid == 0) {
+            gs->r[j] = r;
+            gs->q[j] = q;
+            gs->l[j] = leave;
+            gs->p[j] = p;
+            gs->napp = napp;
+            gs->kdone = j + 1;
+            if (aslot >= 0) {
+                cols[aslot] = leave;
+                pos[leave] = aslot;
+            }
+            basis[r - 1] = q;
+            const int64_t pv = s0.pivots + j;
+            if (pv < s0.log_cap) {
+                log_r[pv] = r;
+                log_q[pv] = q;
+            }
+            st->pivots = pv + 1;
+            st->fresh = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k)
+            if (k == j) rk[k] = r;
+        if (i == r) {
+            basis_i = q;
+            inlist_i = true;
+        }
+        if (t == aslot) c_t = leave;
+
+        // Step 3 inputs of this thread's slot: the pivot-row entry after the
+        // j earlier pivots, R_j[t] = that / p, and the row-0 entry after
+        // pivot j (R = 0 for a slot not filled yet: its column is a unit
+        // vector that no pivot of the group has changed)
+        double Fr[kMaxFuse];  // F_k[r], one batch as above
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k) Fr[k] = Fk[(int64_t)(k < K ? k : K - 1) * ld + r];
+        const double F0 = Fk[(int64_t)j * ld];
+        double R = 0.0;
+        if (c_t >= 0) {
+            double y = T[(int64_t)c_t * ld + r];
+#pragma unroll
+            for (int k = 0; k < kMaxFuse; ++k) {
+                const double ny = (r == rk[k]) ? rslot[k] : fma(-Fr[k], rslot[k], y);
+                y = k < j ? ny : y;
+            }
+            R = y / p;
+            D_t = fma(-F0, R, D_t);
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxFuse; ++k)
+            if (k == j) rslot[k] = R;
+        if (has_slot) Rk[(int64_t)j * Lg + t] = R;
+        double dv = __builtin_inf();
+        int32_t di = kNoIndex, ds = -1;
+        if (c_t >= 0 && c_t != n + m) {
+            dv = D_t;
+            di = c_t;
+            ds = t;
+        }
+        block_argmin_t(dv, di, ds, sv, si, sl);
+        if (tid == 0) sparts[w] = SPart{dv, di, ds};
+        if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+    }
+}
+
+static __global__ __launch_bounds__(256) void k_gdecide(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                 int32_t K, const ArgMin *__restrict__ parts,
+                                                 SPart *__restrict__ sparts, DevState *__restrict__ st,
+                                                 GroupState *__restrict__ gs, double *__restrict__ Fk,
+                                                 double *__restrict__ Rk, int32_t *__restrict__ cols,
+                                                 int32_t *__restrict__ pos, int32_t *__restrict__ basis,
+                                                 int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
+                                                 GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
+                                                 uint32_t spin_limit) {
+    decide_body(T, ld, m, n, K, parts, sparts, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
+                    spin_limit);
+    // every workgroup leaves through here; the last one resets the barrier
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&gsync->exits, 1u) == (uint32_t)gridDim.x - 1) {
+            gsync->count = 0;
+            gsync->exits = 0;
+            __threadfence();
+        }
+    }
 }
 
 // Step 3 for the whole group in one pass over (row chunk, slot group) tiles:

@@ -28,7 +28,20 @@ struct FusedArgs {
     int32_t select_wgs;  // workgroups of the select kernel (at most kMaxSelectWgs)
     GRatio *rparts;      // their Step 2 partials
     uint32_t *ticket;    // their arrival counter, zero between launches
+    int32_t decide_wgs;  // > 0: workgroups of the one-launch decision kernel
+    GridSync *gsync;     // its barrier counters, zero between launches
+    uint32_t decide_spin;
 };
+
+// The one-launch decision kernel: G workgroups of 256 threads, one row and
+// one list slot per thread; used when G <= kMaxDecideWgs.
+constexpr int kMaxDecideWgs = 128;
+inline int32_t decide_workgroups_for(int32_t m, int64_t Lg) {
+    const int64_t rows = (int64_t)m + 1;
+    const int64_t span = rows > Lg ? rows : Lg;
+    return (int32_t)((span + 255) / 256);
+}
+constexpr uint32_t kDefaultDecideSpin = 1u << 22;
 
 // Select workgroups: enough for about one Step 2 row per thread.
 constexpr int kMaxSelectWgs = 64;
@@ -39,6 +52,9 @@ inline int32_t select_workgroups_for(int32_t m) {
 
 // True when an update kernel instance exists for this tile shape and group size.
 bool fused_update_supported(int block, int cols, int rv, int K);
+
+// All decisions of a group in one launch (a.decide_wgs > 0).
+void launch_fused_decide(const FusedArgs &a, hipStream_t s);
 
 // Steps 1-2 (select) and the Step 3 inputs (stage) of pivot j of a group.
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s);

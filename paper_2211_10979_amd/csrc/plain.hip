@@ -46,7 +46,7 @@ struct UpdateConfig {
 // per workgroup below 4096 rows; with pivot fusion, kFusedCols columns (the
 // group's pivot columns are then loaded once per kFusedCols columns).
 constexpr int kFusedCols = 8;
-constexpr int kAutoFuse = 12;
+constexpr int kAutoFuse = 16;
 
 UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fused) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
@@ -106,6 +106,9 @@ struct lp_ctx {
     double *D = nullptr;                      // K > 1: row-0 entry of every slot during a group
     SPart *sparts = nullptr;                  // K > 1: Step 1 partials of the staging kernel
     GRatio *grparts = nullptr;                // K > 1: Step 2 partials of the select workgroups
+    GridSync *gsync = nullptr;                // K > 1: barrier counters of the decision kernel
+    int decide_wgs = 0;                       // K > 1: > 0 = one-launch decision kernel, its workgroups
+    uint32_t decide_spin = kDefaultDecideSpin;
     int nsparts = 0;
     bool use_graph = true;
     bool timing = false;
@@ -153,6 +156,7 @@ void free_ctx(lp_ctx *h) {
     if (h->D) (void)hipFree(h->D);
     if (h->sparts) (void)hipFree(h->sparts);
     if (h->grparts) (void)hipFree(h->grparts);
+    if (h->gsync) (void)hipFree(h->gsync);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -182,6 +186,8 @@ int validate_opts(const lp_options &o) {
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
     if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 16]");
+    if (o.decide_kernel < 0 || o.decide_kernel > 1) return set_error(LP_E_INVAL, "decide_kernel must be 0 or 1");
+    if (o.decide_spin < 0) return set_error(LP_E_INVAL, "decide_spin must be >= 0");
     return LP_OK;
 }
 
@@ -313,8 +319,15 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     if (h->fuse > 1) {
         if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->sparts, (size_t)h->nsparts * sizeof(SPart))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->grparts, kMaxSelectWgs * sizeof(GRatio))) return fail(rc);
+        const int32_t g = decide_workgroups_for(m, h->Lg);
+        h->decide_wgs = (o.decide_kernel == 0 && g <= kMaxDecideWgs) ? g : 0;
+        h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
+        const size_t nsp = std::max<size_t>((size_t)h->nsparts, (size_t)kMaxDecideWgs);
+        if (int rc = dev_alloc((void **)&h->sparts, nsp * sizeof(SPart))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->grparts, kMaxDecideWgs * sizeof(GRatio))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->gsync, sizeof(GridSync))) return fail(rc);
+        if (hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     }
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
@@ -459,15 +472,23 @@ FusedArgs fused_args(lp_ctx *h) {
     a.select_wgs = select_workgroups_for(h->m);
     a.rparts = h->grparts;
     a.ticket = h->ticket;
+    a.decide_wgs = h->decide_wgs;
+    a.gsync = h->gsync;
+    a.decide_spin = h->decide_spin;
     return a;
 }
 
-// One group of pivot fusion: K (select, stage) pairs, then one update pass.
+// One group of pivot fusion: its decisions (one launch, or a select and a
+// stage launch per pivot), then one update pass.
 void enqueue_group(lp_ctx *h, hipEvent_t e0, hipEvent_t e1) {
     const FusedArgs a = fused_args(h);
-    for (int j = 0; j < h->fuse; ++j) {
-        launch_fused_select(a, j, h->stream);
-        launch_fused_stage(a, j, h->stream);
+    if (a.decide_wgs > 0) {
+        launch_fused_decide(a, h->stream);
+    } else {
+        for (int j = 0; j < h->fuse; ++j) {
+            launch_fused_select(a, j, h->stream);
+            launch_fused_stage(a, j, h->stream);
+        }
     }
     const UpdateConfig &u = h->ucfg;
     launch_fused_update(a, u.block, u.cols, u.rv, h->stream, e0, e1);

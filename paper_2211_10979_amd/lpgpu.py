@@ -24,8 +24,8 @@ except Exception:  # pragma: no cover - torch is optional
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblpgpu.so")
 
-LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL, LP_RUNNING = 0, 1, 2, 3, 4
-STATUS_NAMES = {0: "OPTIMAL", 1: "UNBOUNDED", 2: "ITER_LIMIT", 3: "NUMERICAL", 4: "RUNNING"}
+LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL, LP_RUNNING, LP_STALLED = 0, 1, 2, 3, 4, 5
+STATUS_NAMES = {0: "OPTIMAL", 1: "UNBOUNDED", 2: "ITER_LIMIT", 3: "NUMERICAL", 4: "RUNNING", 5: "STALLED"}
 LP_OK, LP_E_INVAL, LP_E_NEG_RHS, LP_E_NOMEM, LP_E_DEVICE, LP_E_STATE, LP_E_PENDING, LP_E_BUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 
 
@@ -58,7 +58,8 @@ class lp_options(ctypes.Structure):
         ("update_unroll", ctypes.c_int32),
         ("select_workgroups", ctypes.c_int32),
         ("fuse_pivots", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("decide_kernel", ctypes.c_int32),
+        ("decide_spin", ctypes.c_int32),
     ]
 
 

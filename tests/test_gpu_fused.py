@@ -87,27 +87,29 @@ def solve_and_compare(A, b, c, **opts):
         o.close()
 
 
-@pytest.mark.parametrize("K", [2, 3, 4, 5, 8, 11, 16])
-def test_degenerate_battery(K):
-    """120 small LPs; the battery contains in-group re-entries of both kinds."""
-    say(f"fused K={K}: degenerate battery")
+@pytest.mark.parametrize("K,decide", [(2, 0), (3, 0), (4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (4, 1), (16, 1)])
+def test_degenerate_battery(K, decide):
+    """120 small LPs; the battery contains in-group re-entries of both kinds.
+    decide = 0: all decisions of a group in one launch; 1: two launches per
+    pivot."""
+    say(f"fused K={K} decide_kernel={decide}: degenerate battery")
     events = np.zeros(2, dtype=int)
     for seed in range(120):
         A, b, c = degenerate_lp(seed, seed % 4)
-        rows, cols = solve_and_compare(A, b, c, fuse_pivots=K)
+        rows, cols = solve_and_compare(A, b, c, fuse_pivots=K, decide_kernel=decide)
         events += group_events(A.shape[0], A.shape[1], rows, cols, K)
     # a column that has just left has a positive objective-row entry, so it
     # cannot enter at the next pivot: with K = 2 no group can re-enter one
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K", [2, 4, 7, 8, 13, 16])
-def test_group_boundaries_by_stepping(K):
+@pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (7, 1), (16, 1)])
+def test_group_boundaries_by_stepping(K, decide):
     """lp_step budgets that cut groups short and ones that span several
     groups: the tableau matches the oracle's after every step."""
     lp = lpgen.workload("dense_200x200")
-    say(f"fused K={K}: dense_200x200 stepping")
-    h = lpgpu.lp_create(lp.A, lp.b, lp.c, fuse_pivots=K)
+    say(f"fused K={K} decide_kernel={decide}: dense_200x200 stepping")
+    h = lpgpu.lp_create(lp.A, lp.b, lp.c, fuse_pivots=K, decide_kernel=decide)
     o = oracle.OracleLP(lp.A, lp.b, lp.c)
     try:
         budgets = [1, K, K + 1, 2 * K - 1, 3, 2 * K + 3]
@@ -131,11 +133,11 @@ def test_group_boundaries_by_stepping(K):
         o.close()
 
 
-@pytest.mark.parametrize("K", [1, 3, 4, 8, 16])
-def test_dense_2000_full_solve(K):
+@pytest.mark.parametrize("K,decide", [(1, 0), (3, 0), (4, 0), (8, 0), (12, 0), (16, 0), (12, 1)])
+def test_dense_2000_full_solve(K, decide):
     lp = lpgen.workload("dense_2000x2000")
-    say(f"fused K={K}: dense_2000x2000")
-    solve_and_compare(lp.A, lp.b, lp.c, fuse_pivots=K)
+    say(f"fused K={K} decide_kernel={decide}: dense_2000x2000")
+    solve_and_compare(lp.A, lp.b, lp.c, fuse_pivots=K, decide_kernel=decide)
 
 
 @pytest.mark.parametrize("opts", [dict(cols_per_block=1), dict(cols_per_block=2), dict(cols_per_block=8),
@@ -234,7 +236,8 @@ def test_options_are_checked():
     for bad in (dict(fuse_pivots=17), dict(fuse_pivots=-1), dict(fuse_pivots=4, cols_per_block=16),
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
-                dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1)):
+                dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1),
+                dict(decide_kernel=2), dict(decide_kernel=-1), dict(decide_spin=-5)):
         with pytest.raises(lpgpu.LPError) as e:
             lpgpu.lp_create(A, b, c, **bad)
         assert e.value.code == lpgpu.LP_E_INVAL
@@ -246,6 +249,18 @@ def test_options_are_checked():
         lpgpu.lp_destroy(h)
     h = lpgpu.lp_create(A, b, c)
     try:
-        assert lpgpu.lp_get_info(h).update_fuse == 12
+        assert lpgpu.lp_get_info(h).update_fuse == 16
     finally:
         lpgpu.lp_destroy(h)
+
+
+def test_decision_kernel_gives_up_instead_of_hanging():
+    """With a wait limit of one poll, the workgroups of the one-launch
+    decision kernel cannot all meet at a barrier: the solve stops with
+    LP_STALLED and every kernel exits; a normal context then solves."""
+    lp = lpgen.workload("dense_2000x2000")  # 8 decision workgroups
+    say("fused: stalled decision kernel")
+    g = lpgpu.solve(lp.A, lp.b, lp.c, decide_spin=1)
+    assert g["status"] == lpgpu.LP_STALLED
+    A, b, c = degenerate_lp(5, 1)
+    solve_and_compare(A, b, c, fuse_pivots=12)
