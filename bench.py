@@ -52,7 +52,6 @@ def update_bytes(m: int, n: int, cols: int, pivots: int) -> float:
     return 16.0 * (m + 1) * cols + pivots * (8.0 * (m + 1) + 16.0 * W)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_update_dense_8000x8000_counters.md")
 CSRC = os.path.join(ROOT, "paper_2211_10979_amd", "csrc")
 
 
@@ -62,25 +61,31 @@ def kernel_source(kernel):
     return os.path.join(CSRC, name)
 
 
-def committed_traffic(kernel):
-    """HBM bytes per update launch that applied a pivot, from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
-    copy-kernel calibration). None unless that summary was taken on this
-    kernel instance built from the current source."""
+def committed_traffic(kernel, workload):
+    """HBM bytes per update launch that applied pivots, from the committed
+    rocprofv3 counter summary of this kernel on this workload (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the copy-kernel calibration). None unless that
+    summary was taken on this kernel instance built from the current source."""
     import hashlib
 
-    if not os.path.exists(COUNTERS):
+    counters = os.path.join(ROOT, "profiles", f"{kernel.split('<')[0]}_{workload}_counters.md")
+    if not os.path.exists(counters):
         return None
     kv = {}
-    for line in open(COUNTERS):
-        if ":" in line and not line.startswith("|"):
-            k, v = line.split(":", 1)
-            kv[k.strip().lstrip("- ")] = v.strip().strip("`")
+    for line in open(counters):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            v = v.strip()
+            if v.startswith("`"):  # a quoted value, taken whole
+                v = v[1:].split("`", 1)[0]
+            elif v:
+                v = v.split()[0]
+            kv[k.strip()] = v
     src = hashlib.sha256(open(kernel_source(kernel), "rb").read()).hexdigest()
     if kv.get("kernel") != kernel or kv.get("source_sha256") != src:
         return None
     try:
-        return float(kv["traffic_bytes_per_pivot_launch"])
+        return float(kv["traffic_bytes_per_applied_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -105,8 +110,8 @@ def bench_plain(args, lpgpu, lpgen, torch):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        tot_piv = tot_cols = tot_launch = 0
-        upd_ms = 0.0
+        tot_piv = tot_cols = tot_launch = tot_applied = 0
+        upd_ms = upd_ms_applied = 0.0
         solve_ms = 0.0
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -115,7 +120,9 @@ def bench_plain(args, lpgpu, lpgen, torch):
             tot_piv += t["pivots"]
             tot_cols += t["updated_columns"]
             tot_launch += t["update_launches"]
+            tot_applied += t["applied_launches"]
             upd_ms += t["update_ms"]
+            upd_ms_applied += t["update_ms_applied"]
             solve_ms += t["solve_ms"]
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -153,18 +160,25 @@ def bench_plain(args, lpgpu, lpgen, torch):
         lp=lp,
     )
     if tot_launch:
-        # every update launch is timed, including the few that return at once
-        # after the optimum; they carry no algorithmic bytes
-        per_launch_bytes = update_bytes(m, n, tot_cols, tot_piv) / tot_launch
+        # every update launch is timed, including the one queued after the
+        # optimum (it returns at once and carries no algorithmic bytes), so
+        # that the average matches rocprofv3's over all dispatches; the
+        # launches that applied pivots are also reported on their own
+        alg = update_bytes(m, n, tot_cols, tot_piv)
+        per_launch_bytes = alg / tot_launch
         avg_ms = upd_ms / tot_launch
         ach = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-        tr = committed_traffic(kernel)
-        traffic = None if tr is None else round(tr * tot_piv / tot_launch)  # per launch, as achieved
+        tr = committed_traffic(kernel, args.workload)
+        traffic = None if tr is None else round(tr * tot_applied / tot_launch)  # per launch, as achieved
         out["roofline"] = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
                                kernel=kernel, avg_launch_us=round(avg_ms * 1e3, 2),
                                alg_bytes_per_launch=per_launch_bytes, launches=tot_launch,
-                               pivots=tot_piv, alg_bytes_per_pivot=update_bytes(m, n, tot_cols, tot_piv) / tot_piv,
+                               applied_launches=tot_applied,
+                               avg_applied_launch_us=round(upd_ms_applied / max(tot_applied, 1) * 1e3, 2),
+                               alg_bytes_per_applied_launch=alg / max(tot_applied, 1),
+                               achieved_applied=round(alg / max(upd_ms_applied, 1e-9) / 1e6, 1),
+                               pivots=tot_piv, alg_bytes_per_pivot=alg / tot_piv,
                                columns_per_pivot=tot_cols / tot_piv)
     return out
 

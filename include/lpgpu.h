@@ -230,6 +230,8 @@ typedef struct {
     int64_t updated_columns;  /* tableau columns rewritten by Step 3, summed over the update
                                  passes (columns with a nonzero normalised pivot-row entry in
                                  some pivot of the pass; one pass per pivot when K = 1) */
+    double update_ms_applied; /* the part of update_ms spent in launches that applied pivots */
+    int64_t applied_launches; /* those launches (the others were queued after the solve ended) */
 } lp_timing;
 
 /* Timing and work counters of the context (see lp_timing). */

@@ -120,6 +120,8 @@ struct lp_ctx {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
     double update_ms = 0.0;
     int64_t update_launches = 0;
+    double update_ms_applied = 0.0;  // part of update_ms in launches that applied pivots
+    int64_t applied_launches = 0;
     int64_t pivots_host = 0;
     int32_t status_host = LP_RUNNING;
     bool ran = false;
@@ -556,13 +558,19 @@ int launch_chunk(lp_ctx *h, int slot) {
 
 // Adds the times of every update launch of a finished chunk: those that
 // applied a pivot and the no-op ones queued after the solve ended.
-int harvest_timing(lp_ctx *h, int slot) {
+int harvest_timing(lp_ctx *h, int slot, int64_t advanced) {
     if (!h->timing) return LP_OK;
     for (int64_t k = 0; k < h->chunk; ++k) {
         float ms = 0.f;
         LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]));
         h->update_ms += ms;
         h->update_launches += 1;
+        // the chunk's launches run in order and only the first ones apply
+        // pivots: one per pivot, or one per group of `fuse` pivots
+        if (k < (advanced + h->fuse - 1) / h->fuse) {
+            h->update_ms_applied += ms;
+            h->applied_launches += 1;
+        }
     }
     return LP_OK;
 }
@@ -574,6 +582,9 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     DeviceGuard g(h->device);
     h->update_ms = 0.0;
     h->update_launches = 0;
+    h->update_ms_applied = 0.0;
+    h->applied_launches = 0;
+    int64_t last = h->pivots_host;  // pivots before the chunk being harvested
     hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
@@ -587,7 +598,8 @@ int run_until(lp_ctx *h, int64_t stop_at) {
         LP_HIP_CHECK(hipEventRecord(h->ev_slot[next], h->stream));
         LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
         const DevState s = h->host_st[slot];
-        if (int rc = harvest_timing(h, slot)) return rc;
+        if (int rc = harvest_timing(h, slot, s.pivots - last)) return rc;
+        last = s.pivots;
         if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
         slot = next;
     }
@@ -595,7 +607,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
     DevState s;
     LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
-    if (int rc = harvest_timing(h, slot ^ 1)) return rc;  // the chunk queued last
+    if (int rc = harvest_timing(h, slot ^ 1, s.pivots - last)) return rc;  // the chunk queued last
     h->pivots_host = s.pivots;
     h->status_host = s.status;
     float ms = 0.f;
@@ -786,6 +798,8 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t) {
     t->solve_ms = h->last_ms;
     t->update_ms = h->update_ms;
     t->update_launches = h->update_launches;
+    t->update_ms_applied = h->update_ms_applied;
+    t->applied_launches = h->applied_launches;
     t->pivots = s.pivots;
     t->updated_columns = (int64_t)cols;
     return LP_OK;

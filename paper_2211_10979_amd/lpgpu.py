@@ -97,6 +97,8 @@ class lp_timing(ctypes.Structure):
         ("update_launches", ctypes.c_int64),
         ("pivots", ctypes.c_int64),
         ("updated_columns", ctypes.c_int64),
+        ("update_ms_applied", ctypes.c_double),
+        ("applied_launches", ctypes.c_int64),
     ]
 
 

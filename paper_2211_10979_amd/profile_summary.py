@@ -8,7 +8,9 @@ Reads whatever the directory holds:
   * `*_results.db` (rocprofv3's SQLite output): the same per-kernel figures
     from its dispatch table;
   * `*_counter_collection.csv` (from --pmc): per-kernel average of each
-    counter over the dispatches of that kernel.
+    counter over the dispatches of that kernel (optionally only those whose
+    value reaches --min-value, e.g. to leave out launches that returned at
+    once).
 Durations are in microseconds.
 """
 
@@ -53,15 +55,23 @@ def kernel_stats_db(path):
     return rows
 
 
-def counters_csv(path):
+def counters_csv(path, min_value=0.0):
+    """Per kernel and counter: (dispatches, mean) over the dispatches whose
+    value is at least `min_value` (0: all of them)."""
     acc = defaultdict(lambda: defaultdict(list))
     with open(path) as f:
         for r in csv.DictReader(f):
             acc[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    return {k: {c: statistics.fmean(v) for c, v in cs.items()} for k, cs in acc.items()}
+    out = {}
+    for k, cs in acc.items():
+        out[k] = {}
+        for c, v in cs.items():
+            sel = [x for x in v if x >= min_value] or [0.0]
+            out[k][c] = (len(sel) if min_value > 0 else len(v), statistics.fmean(sel))
+    return out
 
 
-def summarize(directory, kernel=None):
+def summarize(directory, kernel=None, min_value=0.0):
     out = []
     stats = []
     for p in sorted(glob.glob(os.path.join(directory, "**", "*_kernel_stats.csv"), recursive=True)):
@@ -81,17 +91,18 @@ def summarize(directory, kernel=None):
             out.append(f"| {r['kernel']} | {r['calls']} | {r['total_us']:.1f} | {r['avg_us']:.2f} | "
                        f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
     for p in sorted(glob.glob(os.path.join(directory, "**", "*_counter_collection.csv"), recursive=True)):
-        cs = counters_csv(p)
+        cs = counters_csv(p, min_value)
         out.append("")
-        out.append(f"counters: {os.path.relpath(p, directory)} (average per dispatch)")
+        sel = f", dispatches with value >= {min_value:g}" if min_value > 0 else ""
+        out.append(f"counters: {os.path.relpath(p, directory)} (average per dispatch{sel})")
         out.append("")
-        out.append("| kernel | counter | value |")
-        out.append("|---|---|---|")
+        out.append("| kernel | counter | dispatches | value |")
+        out.append("|---|---|---|---|")
         for k, vals in sorted(cs.items()):
             if kernel and kernel not in k:
                 continue
-            for c, v in sorted(vals.items()):
-                out.append(f"| {k} | {c} | {v:.1f} |")
+            for c, (nd, v) in sorted(vals.items()):
+                out.append(f"| {k} | {c} | {nd} | {v:.1f} |")
     return "\n".join(out)
 
 
@@ -99,8 +110,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("directory")
     ap.add_argument("--kernel", default=None)
+    ap.add_argument("--min-value", type=float, default=0.0,
+                    help="counters: average only dispatches whose value is at least this")
     a = ap.parse_args()
-    print(summarize(a.directory, a.kernel))
+    print(summarize(a.directory, a.kernel, a.min_value))
 
 
 if __name__ == "__main__":

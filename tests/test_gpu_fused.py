@@ -225,6 +225,7 @@ def test_work_counter_counts_the_union_of_a_group():
             assert t["pivots"] == o.pivots
             assert t["updated_columns"] == total
             assert t["update_launches"] >= 1 and t["update_ms"] > 0
+            assert t["applied_launches"] == 1 and 0 < t["update_ms_applied"] <= t["update_ms"]
     finally:
         lpgpu.lp_destroy(h)
         o.close()
