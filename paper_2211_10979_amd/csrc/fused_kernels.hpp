@@ -53,8 +53,9 @@ struct GroupState {
 
 // State, slack basis, list and zeroed pivot-column buffers for a new solve.
 static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int32_t *__restrict__ basis, int32_t m,
-                               int32_t n, int32_t K, double *__restrict__ Fk, int64_t ld, int32_t *__restrict__ cols,
-                               int32_t *__restrict__ pos, unsigned long long *__restrict__ cols_done) {
+                               int32_t n, int32_t K, int32_t KF, double *__restrict__ Fk, int64_t ld,
+                               int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                               unsigned long long *__restrict__ cols_done) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
     if (idx == 0) {
@@ -64,8 +65,8 @@ static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int3
         *cols_done = 0;
     }
     if (idx < m) basis[idx] = n + (int32_t)idx;
-    if (idx < (int64_t)K * ld) Fk[idx] = 0.0;
-    if (idx < Lg) cols[idx] = idx < n ? (int32_t)idx : (idx == n ? n + m : -1);
+    if (idx < (int64_t)KF * ld) Fk[idx] = 0.0;
+    if (idx < Lg + 16) cols[idx] = idx < n ? (int32_t)idx : (idx == n ? n + m : -1);  // list + padding
     if (idx < (int64_t)n + m) pos[idx] = idx < n ? (int32_t)idx : -1;
 }
 
@@ -529,7 +530,11 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
 // k_gdecide runs the group's Steps 1-2 and the Step 3 inputs (what k_gselect
 // and k_gstage compute, with the same arithmetic in the same order) for up
 // to K pivots in one launch of G workgroups of 256 threads, G*256 covering
-// both the rows 0..m and the list slots. Thread (w, x) owns row w*256+x and
+// both the rows 0..m and the list slots. It starts by closing the previous
+// group and by reducing the slots' row-0 entries (the update pass leaves row
+// 0 in the tableau) to the first pivot's Step 1 partials, and ends by storing
+// identities for the pivots the group did not reach and counting the changed
+// columns, which is all the pure update pass needs. Thread (w, x) owns row w*256+x and
 // slot w*256+x for the whole group, and keeps their chain state in
 // registers across pivots: the row's entries of the group's pivot columns
 // (F_k[i]), the slot's normalised pivot-row entries (R_k[t]), its row-0
@@ -574,7 +579,8 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
 }
 
 __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                            int32_t K, const ArgMin *__restrict__ parts, SPart *__restrict__ sparts,
+                                            int32_t K, int32_t KF, SPart *__restrict__ sparts,
+                                            unsigned long long *__restrict__ cols_done,
                                             DevState *__restrict__ st, GroupState *__restrict__ gs,
                                             double *__restrict__ Fk, double *__restrict__ Rk,
                                             int32_t *__restrict__ cols, int32_t *__restrict__ pos,
@@ -609,6 +615,20 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
     const bool has_slot = t < Lg;
     int32_t c_t = has_slot ? cols[t] : -1;
     double D_t = c_t >= 0 ? T[(int64_t)c_t * ld] : 0.0;
+    {
+        // Step 1 partials of the group's first pivot: the slots' row-0
+        // entries after the previous update
+        double dv = __builtin_inf();
+        int32_t di = kNoIndex, ds = -1;
+        if (c_t >= 0 && c_t != n + m) {
+            dv = D_t;
+            di = c_t;
+            ds = t;
+        }
+        block_argmin_t(dv, di, ds, sv, si, sl);
+        if (tid == 0) sparts[w] = SPart{dv, di, ds};
+    }
+    if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     double frow[kMaxFuse], rslot[kMaxFuse];
     int32_t rk[kMaxFuse];
 #pragma unroll
@@ -618,6 +638,7 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         rk[k] = -1;
     }
     int32_t napp = 0;
+    int kd = 0;  // pivots decided in this group
 
     for (int j = 0; j < K; ++j) {
         if (s0.pivots + j >= s0.stop_at) break;
@@ -625,18 +646,13 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         // Step 1
         double v = __builtin_inf();
         int32_t q = kNoIndex, tq = -1;
-        if (j == 0 && s0.fresh)
-            scan_row0(T, ld, n + m, tid, nt, v, q);
-        else if (j == 0)
-            reduce_parts(parts, s0.nparts, tid, nt, v, q, tq);
-        else
-            reduce_parts(sparts, G, tid, nt, v, q, tq);
+        reduce_parts(sparts, G, tid, nt, v, q, tq);
         block_argmin_t(v, q, tq, sv, si, sl);
         if (v != v || v >= -s0.eps_d) {
             if (w == 0 && tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
             break;
         }
-        if (j > 0 && tq < 0) {  // a broken list ends the solve instead of reading outside R
+        if (tq < 0) {  // a broken list ends the solve instead of reading outside R
             if (w == 0 && tid == 0) st->status = LP_NUMERICAL;
             break;
         }
@@ -740,6 +756,7 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
             st->pivots = pv + 1;
             st->fresh = 0;
         }
+        kd = j + 1;
 #pragma unroll
         for (int k = 0; k < kMaxFuse; ++k)
             if (k == j) rk[k] = r;
@@ -783,19 +800,33 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
         if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     }
+
+    // The update pass applies KF pivots: the ones the group did not reach
+    // become exact identities (F = 0, R = 0, no pivot row).
+    for (int k = kd; k < KF; ++k) {
+        if (has_row) Fk[(int64_t)k * ld + i] = 0.0;
+        if (has_slot) Rk[(int64_t)k * Lg + t] = 0.0;
+        if (w == 0 && tid == 0) gs->r[k] = -1;
+    }
+    // columns the group changes: some R entry of the slot nonzero
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < kMaxFuse; ++k) nz |= k < kd && rslot[k] != 0.0;
+    const unsigned long long cnt = __popcll(__ballot(nz));
+    if ((tid & 63) == 0 && cnt) atomicAdd(cols_done, cnt);
 }
 
 static __global__ __launch_bounds__(256) void k_gdecide(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                 int32_t K, const ArgMin *__restrict__ parts,
-                                                 SPart *__restrict__ sparts, DevState *__restrict__ st,
+                                                 int32_t K, int32_t KF, SPart *__restrict__ sparts,
+                                                 unsigned long long *__restrict__ cols_done, DevState *__restrict__ st,
                                                  GroupState *__restrict__ gs, double *__restrict__ Fk,
                                                  double *__restrict__ Rk, int32_t *__restrict__ cols,
                                                  int32_t *__restrict__ pos, int32_t *__restrict__ basis,
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
                                                  uint32_t spin_limit) {
-    decide_body(T, ld, m, n, K, parts, sparts, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
-                    spin_limit);
+    decide_body(T, ld, m, n, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
+                spin_limit);
     // every workgroup leaves through here; the last one resets the barrier
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -938,6 +969,71 @@ __global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t l
     if (row0) {
         parts[g] = ArgMin{val, idx};
         if (changed) atomicAdd(cols_done, changed);
+    }
+}
+
+// The update pass used with the one-launch decision kernel: loads, the
+// chain, stores, and nothing else (any conditional work after the chain --
+// a row-0 reduction, a partial last tile -- made the compiler keep far more
+// live: 360 VGPRs instead of 125 at 8 slots x 16 pivots). The decision kernel
+// does that work instead: it reads row 0 after the update for the next
+// pricing, counts the changed columns, and stores exact identities for the
+// pivots a group did not reach (F = 0, R = 0, pivot row -1), so every pass
+// applies KF pivots without masking. A thread owns one row pair (two rows),
+// threads past the last pair load pair 0 and store nothing; slots past the
+// list (and the padding to a whole slot group) point at a zero column `dump`
+// whose R entries are 0, so every workgroup takes the same straight path.
+template <int B, int C, int KF>
+__global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                    int64_t Lg, int32_t rowchunks, const int32_t *__restrict__ cols,
+                                                    const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                                    const GroupState *__restrict__ gs, double *__restrict__ dump) {
+    __shared__ double sR[C][KF];
+    if (gs->kdone == 0) return;
+    const int32_t Lv = n + 1 + gs->napp;
+    const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
+    const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
+    const int32_t c0 = g * C;
+    if (c0 >= Lv) return;
+    const int32_t nvec = (m + 2) / 2;
+    const int32_t v = rc * B + (int32_t)threadIdx.x;
+    const bool live = v < nvec;
+    const int32_t vs = live ? v : 0;
+    const int32_t i0 = 2 * v;
+    const int64_t ldv = ld / 2;
+    const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
+    int32_t rk[KF];
+    double2 f[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+        rk[k] = gs->r[k];
+        f[k] = F2[k * ldv + vs];
+    }
+    double2 *p[C];
+    double2 x[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int32_t jc = cols[c0 + c];
+        p[c] = reinterpret_cast<double2 *>(jc >= 0 && c0 + c < Lv ? T + (int64_t)jc * ld : dump) + vs;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = *p[c];
+    for (int t = threadIdx.x; t < C * KF; t += B) {  // C * KF may exceed B
+        const int k = t % KF, c = t / KF;
+        sR[c][k] = c0 + c < Lv ? Rk[(int64_t)k * Lg + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KF; ++k)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const double R = sR[c][k];
+            x[c].x = (i0 == rk[k]) ? R : fma(-f[k].x, R, x[c].x);
+            x[c].y = (i0 + 1 == rk[k]) ? R : fma(-f[k].y, R, x[c].y);
+        }
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) *p[c] = x[c];
     }
 }
 

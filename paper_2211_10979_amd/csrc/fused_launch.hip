@@ -35,7 +35,46 @@ void update(const FusedArgs &a, unsigned grid, hipStream_t s, hipEvent_t e0, hip
                            (const GroupState *)a.gs, a.parts, a.cols_done);
 }
 
+template <int B, int C, int KF>
+void update_pure(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int32_t rowchunks = (int32_t)((((int64_t)a.m + 2) / 2 + B - 1) / B);  // row pairs
+    const unsigned grid = (unsigned)((int64_t)rowchunks * a.nparts);
+    if (e0)
+        hipExtLaunchKernelGGL((k_gupdate_pure<B, C, KF>), dim3(grid), dim3(B), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n,
+                              Lg, rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                              (const GroupState *)a.gs, a.dump);
+    else
+        hipLaunchKernelGGL((k_gupdate_pure<B, C, KF>), dim3(grid), dim3(B), 0, s, a.T, a.ld, a.m, a.n, Lg, rowchunks,
+                           (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, a.dump);
+}
+
 using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
+
+template <int B, int C>
+UpdateFn pick_pure(int K) {
+    switch (fused_update_kf(K)) {
+        case 2: return update_pure<B, C, 2>;
+        case 4: return update_pure<B, C, 4>;
+        case 8: return update_pure<B, C, 8>;
+        case 12: return update_pure<B, C, 12>;
+        case 16: return update_pure<B, C, 16>;
+        default: return nullptr;
+    }
+}
+
+// The pure update pass (with the one-launch decision kernel), same shapes.
+UpdateFn find_update_pure(int block, int cols, int rv, int K) {
+    if (rv != 1 || K < 2 || K > kMaxFuse) return nullptr;
+#define LP_PSHAPE(B, C) \
+    if (block == B && cols == C) return pick_pure<B, C>(K);
+    LP_PSHAPE(256, 1) LP_PSHAPE(256, 2) LP_PSHAPE(256, 4) LP_PSHAPE(256, 8)
+    LP_PSHAPE(128, 1) LP_PSHAPE(128, 2) LP_PSHAPE(128, 4) LP_PSHAPE(128, 8)
+    LP_PSHAPE(64, 1) LP_PSHAPE(64, 2) LP_PSHAPE(64, 4) LP_PSHAPE(64, 8)
+#undef LP_PSHAPE
+    return nullptr;
+}
 
 // Update instances exist for groups of up to 2, 4, 8, 12 and 16 pivots; a
 // group size in between takes the next larger instance (its surplus pivots
@@ -70,7 +109,7 @@ bool fused_update_supported(int block, int cols, int rv, int K) { return find_up
 
 void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_gdecide, dim3((unsigned)a.decide_wgs), dim3(256), 0, s, (const double *)a.T, a.ld, a.m, a.n,
-                       a.K, (const ArgMin *)a.parts, a.sparts, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
+                       a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
                        a.log_q, a.rparts, a.gsync, a.decide_spin);
 }
 
@@ -121,7 +160,11 @@ void launch_fused_stage(const FusedArgs &a, int j, hipStream_t s) {
 void launch_fused_update(const FusedArgs &a, int block, int cols, int rv, hipStream_t s, hipEvent_t e0,
                          hipEvent_t e1) {
     const unsigned grid = (unsigned)((int64_t)a.rowchunks * a.nparts);
-    if (UpdateFn f = find_update(block, cols, rv, a.K)) f(a, grid, s, e0, e1);
+    if (a.decide_wgs > 0) {
+        if (UpdateFn f = find_update_pure(block, cols, rv, a.K)) f(a, grid, s, e0, e1);
+    } else if (UpdateFn f = find_update(block, cols, rv, a.K)) {
+        f(a, grid, s, e0, e1);
+    }
 }
 
 }  // namespace lpgpu

@@ -13,6 +13,7 @@ struct FusedArgs {
     double *T;
     int64_t ld;
     int32_t m, n, K;
+    int32_t KF;         // pivots per update pass of the update instance (>= K; the surplus are identities)
     int32_t rowchunks;  // update tiles: row chunks of one row per thread
     int32_t nsparts;    // staging workgroups (= Step 1 partials of the staging kernel)
     int32_t nparts;     // update slot groups (= Step 1 partials of the update kernel)
@@ -31,7 +32,11 @@ struct FusedArgs {
     int32_t decide_wgs;  // > 0: workgroups of the one-launch decision kernel
     GridSync *gsync;     // its barrier counters, zero between launches
     uint32_t decide_spin;
+    double *dump;       // a zero column the pure update pass writes for slots past the list
 };
+
+// Update instances exist for groups of up to 2, 4, 8, 12 and 16 pivots.
+inline int32_t fused_update_kf(int32_t K) { return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : 16; }
 
 // The one-launch decision kernel: G workgroups of 256 threads, one row and
 // one list slot per thread; used when G <= kMaxDecideWgs.

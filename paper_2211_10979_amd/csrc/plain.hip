@@ -104,6 +104,7 @@ struct lp_ctx {
     int64_t Lg = 0;                           // list slots: n + 2 (K = 1) or n + 1 + K
     GroupState *gs = nullptr;                 // K > 1: decisions of the current group
     double *D = nullptr;                      // K > 1: row-0 entry of every slot during a group
+    double *dump = nullptr;                   // K > 1: zero column written for slots past the list
     SPart *sparts = nullptr;                  // K > 1: Step 1 partials of the staging kernel
     GRatio *grparts = nullptr;                // K > 1: Step 2 partials of the select workgroups
     GridSync *gsync = nullptr;                // K > 1: barrier counters of the decision kernel
@@ -159,6 +160,7 @@ void free_ctx(lp_ctx *h) {
     if (h->sparts) (void)hipFree(h->sparts);
     if (h->grparts) (void)hipFree(h->grparts);
     if (h->gsync) (void)hipFree(h->gsync);
+    if (h->dump) (void)hipFree(h->dump);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -299,7 +301,9 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->T, tbytes)) return fail(rc);
         h->own_T = true;
     }
-    if (int rc = dev_alloc((void **)&h->F, (size_t)h->fuse * h->ld * sizeof(double))) return fail(rc);
+    // F and R hold the pivots of the update instance (fused_update_kf(K) >= K)
+    const int kf = h->fuse > 1 ? fused_update_kf(h->fuse) : 1;
+    if (int rc = dev_alloc((void **)&h->F, (size_t)kf * h->ld * sizeof(double))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->parts, (size_t)h->nparts * sizeof(ArgMin))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->st, sizeof(DevState))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->basis, (size_t)m * sizeof(int32_t))) return fail(rc);
@@ -317,7 +321,9 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     // both are padded past the last slot
     if (int rc = dev_alloc((void **)&h->cols, ((size_t)h->Lg + 16) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)h->fuse * h->Lg + 16) * sizeof(double))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double))) return fail(rc);
+    if (hipMemset(h->Rl, 0, ((size_t)kf * h->Lg + 16) * sizeof(double)) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (h->fuse > 1) {
         if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
@@ -328,6 +334,9 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->sparts, nsp * sizeof(SPart))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->grparts, kMaxDecideWgs * sizeof(GRatio))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->gsync, sizeof(GridSync))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->dump, (size_t)h->ld * sizeof(double))) return fail(rc);
+        if (hipMemset(h->dump, 0, (size_t)h->ld * sizeof(double)) != hipSuccess)
+            return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
         if (hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess)
             return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     }
@@ -371,9 +380,10 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.fresh = 1;
     init.nparts = h->nparts;
     if (h->fuse > 1) {
-        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)h->fuse * ld), h->Lg);
+        const int32_t kf = fused_update_kf(h->fuse);
+        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)kf * ld), h->Lg + 16);
         hipLaunchKernelGGL(k_ginit, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
-                           h->gs, h->basis, m, n, (int32_t)h->fuse, h->F, ld, h->cols, h->pos, h->cols_done);
+                           h->gs, h->basis, m, n, (int32_t)h->fuse, kf, h->F, ld, h->cols, h->pos, h->cols_done);
     } else {
         const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
         hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
@@ -455,6 +465,8 @@ FusedArgs fused_args(lp_ctx *h) {
     a.m = h->m;
     a.n = h->n;
     a.K = h->fuse;
+    a.KF = fused_update_kf(h->fuse);
+    a.dump = h->dump;
     a.rowchunks = (int32_t)(((int64_t)h->m + h->ucfg.block) / h->ucfg.block);  // one row per thread
     a.nsparts = h->nsparts;
     a.nparts = h->nparts;
