@@ -110,11 +110,14 @@ typedef struct {
                                rows_per_thread 0 or 1, update_hints 0, update_grid_stride 0 and
                                select_workgroups <= 1. */
     int32_t decide_kernel;  /* K > 1: 0 = auto (one launch for all decisions of a group when
-                               G = max(m + 1, n + 1 + K) / 256 rounded up is at most 128
-                               workgroups, else two launches per pivot); 1 = two launches per
-                               pivot */
+                               G = max(m + 1, n + 1 + K) / decide_block rounded up is at most
+                               128 workgroups, else two launches per pivot); 1 = two launches
+                               per pivot */
     int32_t decide_spin;    /* polls before a grid-barrier wait of the decision kernel gives up
                                with LP_STALLED (0 = default, about 0.2 s) */
+    int32_t decide_block;   /* threads per workgroup of the decision kernel (256 or 512; 0 = auto:
+                               256) */
+    int32_t reserved;
 } lp_options;
 
 typedef struct {
@@ -136,7 +139,8 @@ typedef struct {
     int32_t update_rows;    /* row pairs per thread and column, */
     int32_t update_hints;   /* cache hints (bit 0 loads, bit 1 stores non-temporal) */
     int32_t update_fuse;    /* pivots per pass over the tableau (fuse_pivots in use) */
-    int32_t reserved;
+    int32_t decide_workgroups; /* K > 1: workgroups of the one-launch decision kernel (its update
+                               pass is k_gupdate_pure); 0 = two launches per pivot (k_gupdate) */
 } lp_info;
 
 /* Library version string. Never fails. */

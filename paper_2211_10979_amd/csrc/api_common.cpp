@@ -61,6 +61,8 @@ int lp_options_default(lp_options *o) {
     o->fuse_pivots = 0;
     o->decide_kernel = 0;
     o->decide_spin = 0;
+    o->decide_block = 0;
+    o->reserved = 0;
     return LP_OK;
 }
 

@@ -84,16 +84,27 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
     const int kd = gs->kdone;
     if (kd == 0) return;
     const int na = gs->napp;
+    // loads without per-entry conditions (every index is in bounds: the
+    // group record has kMaxFuse entries, the list kMaxFuse padding slots),
+    // then the entries past the group masked out, so that no load waits for
+    // another
     int32_t qk[kMaxFuse], lk[kMaxFuse], app[kMaxFuse], pq[kMaxFuse];
 #pragma unroll
     for (int k = 0; k < kMaxFuse; ++k) {
-        qk[k] = k < kd ? gs->q[k] : -1;
-        lk[k] = k < kd ? gs->l[k] : -1;
+        qk[k] = gs->q[k];
+        lk[k] = gs->l[k];
+        app[k] = cols[n + 1 + k];
     }
 #pragma unroll
     for (int k = 0; k < kMaxFuse; ++k) {
-        app[k] = k < na ? cols[n + 1 + k] : -1;
-        pq[k] = k < kd ? pos[qk[k]] : -1;
+        const bool in = k < kd && qk[k] >= 0;
+        pq[k] = pos[in ? qk[k] : 0];
+        if (!in) {
+            qk[k] = -1;
+            lk[k] = -1;
+            pq[k] = -1;
+        }
+        if (k >= na) app[k] = -1;
     }
     // the last event of the group decides: entered -> basic, left -> nonbasic
     bool qb[kMaxFuse], ab[kMaxFuse];  // entered column k / appended column s basic at the end
@@ -529,13 +540,13 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
 //
 // k_gdecide runs the group's Steps 1-2 and the Step 3 inputs (what k_gselect
 // and k_gstage compute, with the same arithmetic in the same order) for up
-// to K pivots in one launch of G workgroups of 256 threads, G*256 covering
-// both the rows 0..m and the list slots. It starts by closing the previous
+// to K pivots in one launch of G workgroups of BD threads (256 or 512),
+// G*BD covering both the rows 0..m and the list slots. It starts by closing the previous
 // group and by reducing the slots' row-0 entries (the update pass leaves row
 // 0 in the tableau) to the first pivot's Step 1 partials, and ends by storing
 // identities for the pivots the group did not reach and counting the changed
-// columns, which is all the pure update pass needs. Thread (w, x) owns row w*256+x and
-// slot w*256+x for the whole group, and keeps their chain state in
+// columns, which is all the pure update pass needs. Thread (w, x) owns row
+// w*BD+x and slot w*BD+x for the whole group, and keeps their chain state in
 // registers across pivots: the row's entries of the group's pivot columns
 // (F_k[i]), the slot's normalised pivot-row entries (R_k[t]), its row-0
 // entry, its column, and the row's basic column. Per pivot, two grid
@@ -578,6 +589,7 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
     return *s_ok != 0;
 }
 
+template <int BD>
 __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                             int32_t K, int32_t KF, SPart *__restrict__ sparts,
                                             unsigned long long *__restrict__ cols_done,
@@ -587,12 +599,12 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
                                             int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
                                             int32_t *__restrict__ log_q, GRatio *__restrict__ rparts,
                                             GridSync *__restrict__ gsync, uint32_t spin_limit) {
-    __shared__ double sv[4];
-    __shared__ int32_t si[4], sl[4];
+    __shared__ double sv[BD / 64];
+    __shared__ int32_t si[BD / 64], sl[BD / 64];
     __shared__ int32_t s_ok;
     __shared__ double s_p;
     __shared__ int32_t s_leave, s_inlist;
-    const int tid = threadIdx.x, nt = 256;
+    const int tid = threadIdx.x, nt = BD;
     const int G = gridDim.x, w = blockIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
     const int64_t W = (int64_t)n + m + 1;
@@ -605,13 +617,13 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
     if (s0.status != LP_RUNNING) return;
 
     // this thread's row and slot, and their state at the start of the group
-    const int32_t i = w * 256 + tid;
+    const int32_t i = w * BD + tid;
     const bool has_row = i <= m;
     const int32_t is = has_row ? i : 0;
     const double rhs0 = T[(W - 1) * ld + is];
     int32_t basis_i = (has_row && i >= 1) ? basis[i - 1] : -1;
     bool inlist_i = basis_i >= 0 && pos[basis_i] >= 0;
-    const int32_t t = w * 256 + tid;
+    const int32_t t = w * BD + tid;
     const bool has_slot = t < Lg;
     int32_t c_t = has_slot ? cols[t] : -1;
     double D_t = c_t >= 0 ? T[(int64_t)c_t * ld] : 0.0;
@@ -684,25 +696,22 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         for (int k = 0; k < kMaxFuse; ++k)
             if (k == j) frow[k] = a;
         if (has_row) Fk[(int64_t)j * ld + i] = a;
+        // a NaN (in the column, the RHS or a ratio) becomes a NaN candidate,
+        // which wins the argmin and so reaches the decision as "bad"
         double rv = __builtin_inf();
         int32_t r = kNoIndex;
-        int bad = 0;
         if (has_row && i >= 1) {
             if (a != a || bb != bb) {
-                bad = 1;
+                rv = __builtin_nan("");
+                r = i;
             } else if (a > s0.eps_p) {
-                const double ratio = bb / a;
-                if (ratio != ratio) {
-                    bad = 1;
-                } else {
-                    rv = ratio;
-                    r = i;
-                }
+                rv = bb / a;
+                r = i;
             }
         }
         const int32_t r_mine = r;
-        bad = __syncthreads_or(bad);
         block_argmin(rv, r, sv, si);
+        const int bad = rv != rv;
         if (r != kNoIndex && r_mine == r) {  // the one thread that owns row r
             s_p = a;
             s_leave = basis_i;
@@ -719,17 +728,17 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         rv = pr.v;
         r = pr.r;
         int32_t wk = tid;
-        bad = __syncthreads_or(pr.bad);
         block_argmin_t(rv, r, wk, sv, si, sl);
+        const int bad_all = rv != rv;
         if (r != kNoIndex && wk == tid) {
             s_p = pr.p;
             s_leave = pr.leave;
             s_inlist = pr.lpos;
         }
         __syncthreads();
-        if (bad || r == kNoIndex || s0.pivots + j >= s0.max_pivots) {
+        if (bad_all || r == kNoIndex || s0.pivots + j >= s0.max_pivots) {
             if (w == 0 && tid == 0)
-                st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+                st->status = bad_all ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
             break;
         }
         const double p = s_p;
@@ -816,7 +825,8 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
     if ((tid & 63) == 0 && cnt) atomicAdd(cols_done, cnt);
 }
 
-static __global__ __launch_bounds__(256) void k_gdecide(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+template <int BD>
+__global__ __launch_bounds__(BD) void k_gdecide(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                  int32_t K, int32_t KF, SPart *__restrict__ sparts,
                                                  unsigned long long *__restrict__ cols_done, DevState *__restrict__ st,
                                                  GroupState *__restrict__ gs, double *__restrict__ Fk,
@@ -825,7 +835,7 @@ static __global__ __launch_bounds__(256) void k_gdecide(const double *__restrict
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
                                                  uint32_t spin_limit) {
-    decide_body(T, ld, m, n, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
+    decide_body<BD>(T, ld, m, n, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
                 spin_limit);
     // every workgroup leaves through here; the last one resets the barrier
     __syncthreads();

@@ -107,10 +107,18 @@ UpdateFn find_update(int block, int cols, int rv, int K) {
 
 bool fused_update_supported(int block, int cols, int rv, int K) { return find_update(block, cols, rv, K) != nullptr; }
 
-void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_gdecide, dim3((unsigned)a.decide_wgs), dim3(256), 0, s, (const double *)a.T, a.ld, a.m, a.n,
-                       a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
+template <int BD>
+void decide_bd(const FusedArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_gdecide<BD>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, (const double *)a.T, a.ld, a.m,
+                       a.n, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
                        a.log_q, a.rparts, a.gsync, a.decide_spin);
+}
+
+void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
+    if (a.decide_block == 512)
+        decide_bd<512>(a, s);
+    else
+        decide_bd<256>(a, s);
 }
 
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s) {

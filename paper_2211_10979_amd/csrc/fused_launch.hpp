@@ -30,6 +30,7 @@ struct FusedArgs {
     GRatio *rparts;      // their Step 2 partials
     uint32_t *ticket;    // their arrival counter, zero between launches
     int32_t decide_wgs;  // > 0: workgroups of the one-launch decision kernel
+    int32_t decide_block;  // its threads per workgroup (256 or 512)
     GridSync *gsync;     // its barrier counters, zero between launches
     uint32_t decide_spin;
     double *dump;       // a zero column the pure update pass writes for slots past the list
@@ -38,13 +39,13 @@ struct FusedArgs {
 // Update instances exist for groups of up to 2, 4, 8, 12 and 16 pivots.
 inline int32_t fused_update_kf(int32_t K) { return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : 16; }
 
-// The one-launch decision kernel: G workgroups of 256 threads, one row and
-// one list slot per thread; used when G <= kMaxDecideWgs.
+// The one-launch decision kernel: G workgroups of `block` threads, one row
+// and one list slot per thread; used when G <= kMaxDecideWgs.
 constexpr int kMaxDecideWgs = 128;
-inline int32_t decide_workgroups_for(int32_t m, int64_t Lg) {
+inline int32_t decide_workgroups_for(int32_t m, int64_t Lg, int32_t block) {
     const int64_t rows = (int64_t)m + 1;
     const int64_t span = rows > Lg ? rows : Lg;
-    return (int32_t)((span + 255) / 256);
+    return (int32_t)((span + block - 1) / block);
 }
 constexpr uint32_t kDefaultDecideSpin = 1u << 22;
 

@@ -109,6 +109,7 @@ struct lp_ctx {
     GRatio *grparts = nullptr;                // K > 1: Step 2 partials of the select workgroups
     GridSync *gsync = nullptr;                // K > 1: barrier counters of the decision kernel
     int decide_wgs = 0;                       // K > 1: > 0 = one-launch decision kernel, its workgroups
+    int decide_block = 256;                   // K > 1: its threads per workgroup
     uint32_t decide_spin = kDefaultDecideSpin;
     int nsparts = 0;
     bool use_graph = true;
@@ -192,6 +193,8 @@ int validate_opts(const lp_options &o) {
     if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 16]");
     if (o.decide_kernel < 0 || o.decide_kernel > 1) return set_error(LP_E_INVAL, "decide_kernel must be 0 or 1");
     if (o.decide_spin < 0) return set_error(LP_E_INVAL, "decide_spin must be >= 0");
+    if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
+        return set_error(LP_E_INVAL, "decide_block must be 0 (auto), 256 or 512");
     return LP_OK;
 }
 
@@ -327,7 +330,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     if (h->fuse > 1) {
         if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
-        const int32_t g = decide_workgroups_for(m, h->Lg);
+        h->decide_block = o.decide_block > 0 ? o.decide_block : 256;
+        const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
         h->decide_wgs = (o.decide_kernel == 0 && g <= kMaxDecideWgs) ? g : 0;
         h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
         const size_t nsp = std::max<size_t>((size_t)h->nsparts, (size_t)kMaxDecideWgs);
@@ -487,6 +491,7 @@ FusedArgs fused_args(lp_ctx *h) {
     a.rparts = h->grparts;
     a.ticket = h->ticket;
     a.decide_wgs = h->decide_wgs;
+    a.decide_block = h->decide_block;
     a.gsync = h->gsync;
     a.decide_spin = h->decide_spin;
     return a;
@@ -795,7 +800,7 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
     info->update_rows = h->ucfg.rv;
     info->update_hints = h->ucfg.nt;
     info->update_fuse = h->fuse;
-    info->reserved = 0;
+    info->decide_workgroups = h->fuse > 1 ? h->decide_wgs : 0;
     return LP_OK;
 }
 

@@ -60,6 +60,8 @@ class lp_options(ctypes.Structure):
         ("fuse_pivots", ctypes.c_int32),
         ("decide_kernel", ctypes.c_int32),
         ("decide_spin", ctypes.c_int32),
+        ("decide_block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -86,7 +88,7 @@ class lp_info(ctypes.Structure):
         ("update_rows", ctypes.c_int32),
         ("update_hints", ctypes.c_int32),
         ("update_fuse", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("decide_workgroups", ctypes.c_int32),
     ]
 
 

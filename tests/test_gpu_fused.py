@@ -238,7 +238,7 @@ def test_options_are_checked():
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
                 dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1),
-                dict(decide_kernel=2), dict(decide_kernel=-1), dict(decide_spin=-5)):
+                dict(decide_kernel=2), dict(decide_kernel=-1), dict(decide_spin=-5), dict(decide_block=128)):
         with pytest.raises(lpgpu.LPError) as e:
             lpgpu.lp_create(A, b, c, **bad)
         assert e.value.code == lpgpu.LP_E_INVAL
@@ -265,3 +265,14 @@ def test_decision_kernel_gives_up_instead_of_hanging():
     assert g["status"] == lpgpu.LP_STALLED
     A, b, c = degenerate_lp(5, 1)
     solve_and_compare(A, b, c, fuse_pivots=12)
+
+
+@pytest.mark.parametrize("block", [256, 512])
+def test_decision_kernel_block_sizes(block):
+    """The decision kernel's workgroup size changes no result."""
+    say(f"fused: decision kernel with {block} threads per workgroup")
+    for seed in range(0, 120, 7):
+        A, b, c = degenerate_lp(seed, seed % 4)
+        solve_and_compare(A, b, c, fuse_pivots=16, decide_block=block)
+    lp = lpgen.workload("dense_2000x2000")
+    solve_and_compare(lp.A, lp.b, lp.c, fuse_pivots=16, decide_block=block)
