@@ -20,30 +20,49 @@ constexpr int kBuildTile = 64;
 
 // Initialization Step, structural part: column j < n of T gets -c_j in row 0
 // and column j of A in rows 1..m (Table I); padding rows are zero. A is
-// row-major, so each 64x64 tile is transposed through LDS.
+// row-major, so each 64x64 tile is transposed through LDS; both sides move
+// 16 bytes per thread access (two columns of a row of A, two rows of a
+// column of T).
 static __global__ __launch_bounds__(256) void k_build_struct(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                      const double *__restrict__ A, const double *__restrict__ c) {
+                                                             const double *__restrict__ A, const double *__restrict__ c) {
     __shared__ double tile[kBuildTile][kBuildTile + 1];
     const int64_t j0 = (int64_t)blockIdx.x * kBuildTile;
     const int64_t i0 = (int64_t)blockIdx.y * kBuildTile;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll 4
-    for (int k = 0; k < kBuildTile / 4; ++k) {
-        const int64_t i = i0 + ty + 4 * k, j = j0 + tx;
-        double v = 0.0;
-        if (j < n) {
-            if (i == 0)
-                v = -c[j];
-            else if (i <= m)
-                v = A[(i - 1) * n + j];
+    const int pr = threadIdx.x & 31, rw = threadIdx.x >> 5;  // pair within a tile row, row group
+    // 16-byte loads of A need an even n (every row starts 16-byte aligned)
+    // and an aligned A (a caller's device array may be any view)
+    const bool vec_a = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+#pragma unroll
+    for (int k = 0; k < kBuildTile / 8; ++k) {
+        const int r = rw + 8 * k;
+        const int64_t i = i0 + r, j = j0 + 2 * pr;
+        double2 v = {0.0, 0.0};
+        if (i == 0) {
+            if (j < n) v.x = -c[j];
+            if (j + 1 < n) v.y = -c[j + 1];
+        } else if (i <= m) {
+            const double *a = A + (i - 1) * n + j;
+            if (vec_a && j + 1 < n) {  // j is even
+                v = *reinterpret_cast<const double2 *>(a);
+            } else {
+                if (j < n) v.x = a[0];
+                if (j + 1 < n) v.y = a[1];
+            }
         }
-        tile[ty + 4 * k][tx] = v;
+        tile[r][2 * pr] = v.x;
+        tile[r][2 * pr + 1] = v.y;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kBuildTile / 4; ++k) {
-        const int64_t j = j0 + ty + 4 * k, i = i0 + tx;
-        if (j < n && i < ld) T[j * ld + i] = tile[tx][ty + 4 * k];
+#pragma unroll
+    for (int k = 0; k < kBuildTile / 8; ++k) {
+        const int cl = rw + 8 * k;
+        const int64_t j = j0 + cl, i = i0 + 2 * pr;
+        if (j < n && i + 1 < ld) {  // ld is even: rows i, i+1 both exist
+            double2 v;
+            v.x = tile[2 * pr][cl];
+            v.y = tile[2 * pr + 1][cl];
+            *reinterpret_cast<double2 *>(T + j * ld + i) = v;
+        }
     }
 }
 

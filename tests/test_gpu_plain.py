@@ -363,3 +363,31 @@ def test_timing_mode_keeps_results(opts):
     lp = lpgen.dense_lp(5, 900, 1100)
     g = lpgpu.solve(lp.A, lp.b, lp.c, **opts)
     assert_same_result(lp.A, lp.b, lp.c, g, oracle.solve(lp.A, lp.b, lp.c))
+
+
+def test_device_inputs_at_any_alignment():
+    """A caller's device A may be a view 8 bytes off a 16-byte boundary, with
+    an odd or even n: the build reads it either way."""
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cuda", 0)
+    for m, n in ((300, 400), (301, 401)):
+        lp = lpgen.dense_lp(40 + n, m, n)
+        flat = torch.empty(m * n + 1, dtype=torch.float64, device=dev)
+        flat[1:] = torch.from_numpy(lp.A.ravel()).to(dev)
+        dA = flat[1:].view(m, n)
+        assert dA.data_ptr() % 16 == 8
+        db = torch.from_numpy(lp.b).to(dev)
+        dc = torch.from_numpy(lp.c).to(dev)
+        h = lpgpu.lp_create_device(m, n, dA, db, dc)
+        o = oracle.OracleLP(lp.A, lp.b, lp.c)
+        try:
+            assert np.array_equal(lpgpu.lp_get_tableau(h), o.tableau()), "initial tableau"
+            lpgpu.lp_solve(h)
+            o.step(-1)
+            rows, cols = lpgpu.lp_get_pivots(h)
+            orow, ocol = o.log()
+            assert rows.tolist() == orow.tolist() and cols.tolist() == ocol.tolist()
+            assert np.array_equal(lpgpu.lp_get_tableau(h), o.tableau())
+        finally:
+            lpgpu.lp_destroy(h)
+            o.close()
