@@ -117,7 +117,11 @@ typedef struct {
                                with LP_STALLED (0 = default, about 0.2 s) */
     int32_t decide_block;   /* threads per workgroup of the decision kernel (256 or 512; 0 = auto:
                                256) */
-    int32_t reserved;
+    int32_t eager_build;    /* 0 = auto: with the one-launch decision kernel, lp_reload_device
+                               defers the build of the structural columns to the first update
+                               pass (which reads A and c instead of the tableau) and leaves the
+                               slack columns unwritten until they leave the basis; 1 = build
+                               the whole tableau at once (default 0) */
 } lp_options;
 
 typedef struct {
@@ -133,7 +137,9 @@ typedef struct {
     int64_t width;          /* W = n+m+1 */
     int64_t ld;             /* column stride of the column-major device tableau, in doubles */
     size_t tableau_bytes;   /* ld * W * 8 */
-    const double *tableau;  /* device pointer: T[i][j] at tableau[j*ld + i] */
+    const double *tableau;  /* device pointer: T[i][j] at tableau[j*ld + i]; after a deferred
+                               build, basic columns that have never left the basis are not
+                               stored there until lp_get_tableau */
     int32_t update_block;   /* update kernel in use: threads per workgroup, */
     int32_t update_cols;    /* listed columns per workgroup, */
     int32_t update_rows;    /* row pairs per thread and column, */
@@ -182,7 +188,12 @@ int lp_create_device(lp_ctx **out, int32_t m, int32_t n, const double *dA, const
 /*
  * Rebuilds the tableau of an existing context from device-resident A, b, c of
  * the same m and n (the Initialization Step again), resetting the pivot count
- * and log. Asynchronous on the context stream.
+ * and log. Asynchronous on the context stream. When the build is deferred
+ * (eager_build 0 with the one-launch decision kernel: lp_get_info's
+ * decide_workgroups > 0), A and c are read by the first update pass of the
+ * next lp_solve / lp_step, or by lp_get_tableau if that comes first: they
+ * must stay valid and unchanged until that call returns. b is read at once
+ * (on the stream).
  */
 int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double *dc);
 
@@ -214,7 +225,10 @@ int lp_get_pivots(const lp_ctx *h, int32_t *rows, int32_t *cols, int64_t cap, in
 
 /*
  * Copies the tableau to host memory, column by column: out[j*(m+1) + i] =
- * T[i][j] for j in [0, W), i in [0, m]. out holds (m+1)*W doubles.
+ * T[i][j] for j in [0, W), i in [0, m]. out holds (m+1)*W doubles. Basic
+ * columns not stored on the device (a deferred build writes a slack column
+ * only when it leaves the basis) are stored first, as the unit vectors they
+ * are; a pending deferred build runs first.
  */
 int lp_get_tableau(const lp_ctx *h, double *out);
 
@@ -236,6 +250,13 @@ typedef struct {
                                  some pivot of the pass; one pass per pivot when K = 1) */
     double update_ms_applied; /* the part of update_ms spent in launches that applied pivots */
     int64_t applied_launches; /* those launches (the others were queued after the solve ended) */
+    double first_pass_ms;     /* time_kernels = 1 and a deferred build: the first update pass
+                                 (k_gfirst: the structural build fused with the first group's
+                                 Step 3), not part of update_ms */
+    int64_t first_pass_pivots;  /* pivots applied by that pass (part of pivots) */
+    int64_t first_pass_changed; /* columns it changed (part of updated_columns) */
+    int64_t first_pass_columns; /* columns it wrote: the n structural ones, the RHS and those
+                                   appended during the group (0 without a deferred build) */
 } lp_timing;
 
 /* Timing and work counters of the context (see lp_timing). */

@@ -62,7 +62,7 @@ int lp_options_default(lp_options *o) {
     o->decide_kernel = 0;
     o->decide_spin = 0;
     o->decide_block = 0;
-    o->reserved = 0;
+    o->eager_build = 0;
     return LP_OK;
 }
 

@@ -22,7 +22,9 @@
 // columns that leave the basis during the group (appended when they leave,
 // -1 when unused). pos[c] is the slot of column c, or -1. Columns that are
 // basic during the whole group are exact unit vectors that no pivot of the
-// group changes (their pivot-row entry is 0), so they are left out. A
+// group changes (their pivot-row entry is 0), so they are left out; a basic
+// column is stored only once it has left the basis (after a deferred build
+// the slack columns are not written until then). A
 // column's slot t indexes R_k[t] (the normalised pivot-row entry of pivot k)
 // and D[t] (its row-0 entry after the pivots staged so far).
 //
@@ -55,15 +57,21 @@ struct GroupState {
 static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int32_t *__restrict__ basis, int32_t m,
                                int32_t n, int32_t K, int32_t KF, double *__restrict__ Fk, int64_t ld,
                                int32_t *__restrict__ cols, int32_t *__restrict__ pos,
-                               unsigned long long *__restrict__ cols_done) {
+                               unsigned long long *__restrict__ cols_done, double *__restrict__ T,
+                               const double *__restrict__ b) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
     if (idx == 0) {
         *st = init;
         gs->kdone = 0;
         gs->napp = 0;
-        *cols_done = 0;
+        cols_done[0] = 0;
+        cols_done[1] = 0;
+        cols_done[2] = 0;
+        cols_done[3] = 0;
     }
+    // with a deferred build, the right-hand side column (b in rows 1..m)
+    if (b && idx < ld) T[(int64_t)(n + m) * ld + idx] = (idx >= 1 && idx <= m) ? b[idx - 1] : 0.0;
     if (idx < m) basis[idx] = n + (int32_t)idx;
     if (idx < (int64_t)KF * ld) Fk[idx] = 0.0;
     if (idx < Lg + 16) cols[idx] = idx < n ? (int32_t)idx : (idx == n ? n + m : -1);  // list + padding
@@ -589,8 +597,21 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
     return *s_ok != 0;
 }
 
-template <int BD>
-__device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+// Entry (row, col) of the tableau at the start of the group. The first group
+// after a deferred build reads the structural columns from A and c (the
+// tableau holds them only after that group's update pass); everything else
+// is read from the tableau.
+template <bool First>
+__device__ __forceinline__ double start_entry(const double *__restrict__ T, int64_t ld, int32_t n,
+                                              const double *__restrict__ A, const double *__restrict__ cv,
+                                              int32_t col, int32_t row) {
+    if (First && col < n) return row == 0 ? -cv[col] : A[(int64_t)(row - 1) * n + col];
+    return T[(int64_t)col * ld + row];
+}
+
+template <int BD, bool First>
+__device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                            const double *__restrict__ A, const double *__restrict__ cv,
                                             int32_t K, int32_t KF, SPart *__restrict__ sparts,
                                             unsigned long long *__restrict__ cols_done,
                                             DevState *__restrict__ st, GroupState *__restrict__ gs,
@@ -626,7 +647,7 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
     const int32_t t = w * BD + tid;
     const bool has_slot = t < Lg;
     int32_t c_t = has_slot ? cols[t] : -1;
-    double D_t = c_t >= 0 ? T[(int64_t)c_t * ld] : 0.0;
+    double D_t = c_t >= 0 ? start_entry<First>(T, ld, n, A, cv, c_t, 0) : 0.0;
     {
         // Step 1 partials of the group's first pivot: the slots' row-0
         // entries after the previous update
@@ -674,7 +695,6 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         // coefficients of all kMaxFuse steps are loaded in one batch (index
         // clamped into the buffer) and the steps k >= j are masked out by
         // selects, so that no load waits behind another.
-        const double *colq = T + (int64_t)q * ld;
         const int32_t tqs = tq < 0 ? 0 : tq;
         double Rq[kMaxFuse], Rb[kMaxFuse];
 #pragma unroll
@@ -683,7 +703,7 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
             Rq[k] = Rk[kk * Lg + tqs];
             Rb[k] = Rk[kk * Lg + n];
         }
-        double a = colq[is], bb = rhs0;
+        double a = start_entry<First>(T, ld, n, A, cv, q, is), bb = rhs0;
 #pragma unroll
         for (int k = 0; k < kMaxFuse; ++k) {
             const bool on = k < j, piv = i == rk[k];
@@ -774,6 +794,13 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
             inlist_i = true;
         }
         if (t == aslot) c_t = leave;
+        // a column that leaves the basis for the first time in this group is
+        // stored now as the unit vector it is (e_r: its basic row is the
+        // pivot row), which makes it readable by the later pivots of the
+        // group (after the barrier) and by the update pass; a column stored
+        // before is that unit vector already. After a deferred build the
+        // slack columns are not stored until they leave.
+        if (aslot >= 0 && i < ld) T[(int64_t)leave * ld + i] = (i == r) ? 1.0 : 0.0;
 
         // Step 3 inputs of this thread's slot: the pivot-row entry after the
         // j earlier pivots, R_j[t] = that / p, and the row-0 entry after
@@ -785,7 +812,9 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
         const double F0 = Fk[(int64_t)j * ld];
         double R = 0.0;
         if (c_t >= 0) {
-            double y = T[(int64_t)c_t * ld + r];
+            // (the slot just appended holds e_r, whose entry in row r is 1:
+            // taken as is, since the store above may not be visible yet)
+            double y = t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r);
 #pragma unroll
             for (int k = 0; k < kMaxFuse; ++k) {
                 const double ny = (r == rk[k]) ? rslot[k] : fma(-Fr[k], rslot[k], y);
@@ -822,11 +851,19 @@ __device__ __forceinline__ void decide_body(const double *__restrict__ T, int64_
 #pragma unroll
     for (int k = 0; k < kMaxFuse; ++k) nz |= k < kd && rslot[k] != 0.0;
     const unsigned long long cnt = __popcll(__ballot(nz));
-    if ((tid & 63) == 0 && cnt) atomicAdd(cols_done, cnt);
+    if ((tid & 63) == 0 && cnt) {
+        atomicAdd(cols_done, cnt);
+        if (First) atomicAdd(cols_done + 1, cnt);
+    }
+    if (First && w == 0 && tid == 0) {
+        cols_done[2] = (unsigned long long)kd;
+        cols_done[3] = (unsigned long long)napp;
+    }
 }
 
-template <int BD>
-__global__ __launch_bounds__(BD) void k_gdecide(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+template <int BD, bool First>
+__global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                 const double *__restrict__ A, const double *__restrict__ cv,
                                                  int32_t K, int32_t KF, SPart *__restrict__ sparts,
                                                  unsigned long long *__restrict__ cols_done, DevState *__restrict__ st,
                                                  GroupState *__restrict__ gs, double *__restrict__ Fk,
@@ -835,7 +872,7 @@ __global__ __launch_bounds__(BD) void k_gdecide(const double *__restrict__ T, in
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
                                                  uint32_t spin_limit) {
-    decide_body<BD>(T, ld, m, n, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
+    decide_body<BD, First>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
                 spin_limit);
     // every workgroup leaves through here; the last one resets the barrier
     __syncthreads();
@@ -994,17 +1031,11 @@ __global__ __launch_bounds__(B) void k_gupdate(double *__restrict__ T, int64_t l
 // list (and the padding to a whole slot group) point at a zero column `dump`
 // whose R entries are 0, so every workgroup takes the same straight path.
 template <int B, int C, int KF>
-__global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                    int64_t Lg, int32_t rowchunks, const int32_t *__restrict__ cols,
-                                                    const double *__restrict__ Rk, const double *__restrict__ Fk,
-                                                    const GroupState *__restrict__ gs, double *__restrict__ dump) {
+__device__ __forceinline__ void pure_tile(double *__restrict__ T, int64_t ld, int32_t m, int64_t Lg, int32_t Lv,
+                                          int32_t rc, int32_t c0, const int32_t *__restrict__ cols,
+                                          const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                          const GroupState *__restrict__ gs, double *__restrict__ dump) {
     __shared__ double sR[C][KF];
-    if (gs->kdone == 0) return;
-    const int32_t Lv = n + 1 + gs->napp;
-    const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
-    const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
-    const int32_t c0 = g * C;
-    if (c0 >= Lv) return;
     const int32_t nvec = (m + 2) / 2;
     const int32_t v = rc * B + (int32_t)threadIdx.x;
     const bool live = v < nvec;
@@ -1044,6 +1075,180 @@ __global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int6
     if (live) {
 #pragma unroll
         for (int c = 0; c < C; ++c) *p[c] = x[c];
+    }
+}
+
+template <int B, int C, int KF>
+__global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                    int64_t Lg, int32_t rowchunks, const int32_t *__restrict__ cols,
+                                                    const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                                    const GroupState *__restrict__ gs, double *__restrict__ dump) {
+    if (gs->kdone == 0) return;
+    const int32_t Lv = n + 1 + gs->napp;
+    const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
+    const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
+    const int32_t c0 = g * C;
+    if (c0 >= Lv) return;
+    pure_tile<B, C, KF>(T, ld, m, Lg, Lv, rc, c0, cols, Rk, Fk, gs, dump);
+}
+
+// The first update pass after a deferred build: the Initialization Step of
+// the structural columns and the first group's Step 3 in one pass. Column
+// j < n sits in list slot j during the first group, so a tile of A (row 0:
+// -c) is read row-major, transposed through LDS and written to the tableau
+// after the group's KF pivots are applied to it, with the same chain as the
+// pure pass applies to a built column (the same operations in the same order
+// on the same start value, hence the same bits; a tile that holds no pivot
+// row skips the pivot-row select, which would pick the fma result in every
+// row). A group of no pivots writes the tile as the plain build does.
+// Workgroups past the tiles run the pure pass over slots n.. (the right-hand
+// side, built by k_ginit, and the columns appended during the group, which
+// the decision kernel stored as unit vectors when they left the basis).
+constexpr int kFirstRows = 32;  // tile rows (tableau rows)
+constexpr int kFirstTile = 64;  // tile columns
+constexpr int kFirstCols = 8;   // list slots per workgroup of the pure part
+
+template <int KF>
+__global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t ld, int32_t m, int32_t n, int64_t Lg,
+                                                int32_t ntx, int32_t ntiles, int32_t rowchunks,
+                                                const double *__restrict__ A, const double *__restrict__ cv,
+                                                const int32_t *__restrict__ cols, const double *__restrict__ Rk,
+                                                const double *__restrict__ Fk, const GroupState *__restrict__ gs,
+                                                double *__restrict__ dump) {
+    constexpr int TR = kFirstRows, TC = kFirstTile;
+    constexpr int NP = TR / 2;          // row pairs of a tile
+    constexpr int CG = 256 / NP;        // column groups of the write phase
+    constexpr int NR = (KF * TC + 255) / 256;  // R entries per thread to stage
+    constexpr int NF = (KF * NP + 255) / 256;  // F pairs per thread to stage
+    const int32_t kd = gs->kdone;
+    if ((int32_t)blockIdx.x >= ntiles) {
+        if (kd == 0) return;
+        const int32_t b = (int32_t)blockIdx.x - ntiles;
+        const int32_t rc = b % rowchunks;
+        const int32_t c0 = n + (b / rowchunks) * kFirstCols;
+        const int32_t Lv = n + 1 + gs->napp;
+        if (c0 >= Lv) return;
+        pure_tile<256, kFirstCols, KF>(T, ld, m, Lg, Lv, rc, c0, cols, Rk, Fk, gs, dump);
+        return;
+    }
+    __shared__ double tile[TR][TC + 1];
+    __shared__ double sR[KF][TC];
+    __shared__ double2 sF[KF][NP];
+    const int64_t j0 = (int64_t)(blockIdx.x % (uint32_t)ntx) * TC;
+    const int64_t i0 = (int64_t)(blockIdx.x / (uint32_t)ntx) * TR;
+    const int tid = threadIdx.x;
+    // the group's R entries of the tile's columns and F entries of its rows,
+    // loaded first so that they arrive with the tile
+    double rv[NR];
+    double2 fv[NF];
+    if (kd > 0) {
+        const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
+        const int64_t ldv = ld / 2;
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int t = tid + 256 * u, k = t / TC, cl = t % TC;
+            rv[u] = t < KF * TC && j0 + cl < n ? Rk[(int64_t)k * Lg + j0 + cl] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NF; ++u) {
+            const int t = tid + 256 * u, k = t / NP, v = t % NP;
+            fv[u] = t < KF * NP && i0 + 2 * v < ld ? F2[k * ldv + i0 / 2 + v] : double2{0.0, 0.0};
+        }
+    }
+    // the tile of A: 16-byte loads need an even n and a 16-byte aligned A
+    {
+        const int pr = tid & 31, rw = tid >> 5;  // column pair, row group
+        const bool vec_a = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+        double2 va[TR / 8];
+#pragma unroll
+        for (int k = 0; k < TR / 8; ++k) {
+            const int64_t i = i0 + rw + 8 * k, j = j0 + 2 * pr;
+            double2 v = {0.0, 0.0};
+            if (i == 0) {
+                if (j < n) v.x = -cv[j];
+                if (j + 1 < n) v.y = -cv[j + 1];
+            } else if (i <= m) {
+                const double *a = A + (i - 1) * n + j;
+                if (vec_a && j + 1 < n) {  // j is even
+                    v = *reinterpret_cast<const double2 *>(a);
+                } else {
+                    if (j < n) v.x = a[0];
+                    if (j + 1 < n) v.y = a[1];
+                }
+            }
+            va[k] = v;
+        }
+        if (kd > 0) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u) {
+                const int t = tid + 256 * u;
+                if (t < KF * TC) sR[t / TC][t % TC] = rv[u];
+            }
+#pragma unroll
+            for (int u = 0; u < NF; ++u) {
+                const int t = tid + 256 * u;
+                if (t < KF * NP) sF[t / NP][t % NP] = fv[u];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TR / 8; ++k) {
+            tile[rw + 8 * k][2 * pr] = va[k].x;
+            tile[rw + 8 * k][2 * pr + 1] = va[k].y;
+        }
+    }
+    __syncthreads();
+    // write phase: row pair p of the tile (rows iw, iw + 1; ld is even, so
+    // both exist when the first does), columns cg + CG u
+    const int p = tid % NP, cg = tid / NP;
+    const int64_t iw = i0 + 2 * p;
+    if (iw >= ld) return;
+    if (kd == 0) {
+#pragma unroll
+        for (int u = 0; u < TC / CG; ++u) {
+            const int cl = cg + CG * u;
+            const int64_t j = j0 + cl;
+            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = double2{tile[2 * p][cl], tile[2 * p + 1][cl]};
+        }
+        return;
+    }
+    int32_t rk[KF];
+    bool sel = false;  // the tile holds a pivot row (uniform)
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+        rk[k] = gs->r[k];
+        sel |= rk[k] >= i0 && rk[k] < i0 + TR;
+    }
+    double2 f[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) f[k] = sF[k][p];
+    if (sel) {
+#pragma unroll
+        for (int u = 0; u < TC / CG; ++u) {
+            const int cl = cg + CG * u;
+            const int64_t j = j0 + cl;
+            double2 x{tile[2 * p][cl], tile[2 * p + 1][cl]};
+#pragma unroll
+            for (int k = 0; k < KF; ++k) {
+                const double R = sR[k][cl];
+                x.x = (iw == rk[k]) ? R : fma(-f[k].x, R, x.x);
+                x.y = (iw + 1 == rk[k]) ? R : fma(-f[k].y, R, x.y);
+            }
+            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
+        }
+    } else {  // the same chain: no row of the tile is a pivot row
+#pragma unroll
+        for (int u = 0; u < TC / CG; ++u) {
+            const int cl = cg + CG * u;
+            const int64_t j = j0 + cl;
+            double2 x{tile[2 * p][cl], tile[2 * p + 1][cl]};
+#pragma unroll
+            for (int k = 0; k < KF; ++k) {
+                const double R = sR[k][cl];
+                x.x = fma(-f[k].x, R, x.x);
+                x.y = fma(-f[k].y, R, x.y);
+            }
+            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
+        }
     }
 }
 

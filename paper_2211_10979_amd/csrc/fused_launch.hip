@@ -107,18 +107,60 @@ UpdateFn find_update(int block, int cols, int rv, int K) {
 
 bool fused_update_supported(int block, int cols, int rv, int K) { return find_update(block, cols, rv, K) != nullptr; }
 
-template <int BD>
-void decide_bd(const FusedArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_gdecide<BD>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, (const double *)a.T, a.ld, a.m,
-                       a.n, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
+template <int BD, bool First>
+void decide_bd(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
+    hipLaunchKernelGGL((k_gdecide<BD, First>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n, A, c,
+                       a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
                        a.log_q, a.rparts, a.gsync, a.decide_spin);
 }
 
 void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
     if (a.decide_block == 512)
-        decide_bd<512>(a, s);
+        decide_bd<512, false>(a, nullptr, nullptr, s);
     else
-        decide_bd<256>(a, s);
+        decide_bd<256, false>(a, nullptr, nullptr, s);
+}
+
+void launch_first_decide(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
+    if (a.decide_block == 512)
+        decide_bd<512, true>(a, A, c, s);
+    else
+        decide_bd<256, true>(a, A, c, s);
+}
+
+namespace {
+
+template <int KF>
+void first_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int32_t ntx = (a.n + kFirstTile - 1) / kFirstTile;
+    const int32_t nty = (int32_t)((a.ld + kFirstRows - 1) / kFirstRows);
+    const int32_t ntiles = ntx * nty;
+    const int32_t rowchunks = (int32_t)((((int64_t)a.m + 2) / 2 + 255) / 256);  // row pairs
+    const int32_t slot_groups = (1 + a.K + kFirstCols - 1) / kFirstCols;      // slots n .. n+K
+    const unsigned grid = (unsigned)((int64_t)ntiles + (int64_t)rowchunks * slot_groups);
+    if (e0)
+        hipExtLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg, ntx,
+                              ntiles, rowchunks, A, c, (const int32_t *)a.cols, (const double *)a.Rk,
+                              (const double *)a.Fk, (const GroupState *)a.gs, a.dump);
+    else
+        hipLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, ntx, ntiles, rowchunks,
+                           A, c, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, a.dump);
+}
+
+}  // namespace
+
+void launch_first_update(const FusedArgs &a, const double *A, const double *c, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+    switch (a.KF) {
+        case 2: first_kf<2>(a, A, c, s, e0, e1); break;
+        case 4: first_kf<4>(a, A, c, s, e0, e1); break;
+        case 8: first_kf<8>(a, A, c, s, e0, e1); break;
+        case 12: first_kf<12>(a, A, c, s, e0, e1); break;
+        case 16: first_kf<16>(a, A, c, s, e0, e1); break;
+        default: break;
+    }
 }
 
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s) {

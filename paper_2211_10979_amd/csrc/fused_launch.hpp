@@ -25,7 +25,9 @@ struct FusedArgs {
     int32_t *cols, *pos, *basis, *log_r, *log_q;
     ArgMin *parts;
     SPart *sparts;
-    unsigned long long *cols_done;
+    unsigned long long *cols_done;  // [0] columns changed by all passes; the first pass after a deferred
+                                    // build: [1] its changed columns, [2] its pivots, [3] its appended
+                                    // columns
     int32_t select_wgs;  // workgroups of the select kernel (at most kMaxSelectWgs)
     GRatio *rparts;      // their Step 2 partials
     uint32_t *ticket;    // their arrival counter, zero between launches
@@ -61,6 +63,13 @@ bool fused_update_supported(int block, int cols, int rv, int K);
 
 // All decisions of a group in one launch (a.decide_wgs > 0).
 void launch_fused_decide(const FusedArgs &a, hipStream_t s);
+
+// The first group after a deferred build: its decisions read the structural
+// columns from A (row-major m x n) and c, and its update pass writes them
+// (the Initialization Step of those columns fused with the group's Step 3).
+void launch_first_decide(const FusedArgs &a, const double *A, const double *c, hipStream_t s);
+void launch_first_update(const FusedArgs &a, const double *A, const double *c, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1);
 
 // Steps 1-2 (select) and the Step 3 inputs (stage) of pivot j of a group.
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s);

@@ -114,6 +114,18 @@ struct lp_ctx {
     int nsparts = 0;
     bool use_graph = true;
     bool timing = false;
+    // Deferred build (lp_reload_device with the one-launch decision kernel):
+    // the inputs the first update pass reads, whether that pass is still to
+    // come, and whether basic columns may be unstored (slack columns are
+    // written only when they leave the basis).
+    bool eager_build = false;
+    const double *pend_A = nullptr, *pend_b = nullptr, *pend_c = nullptr;
+    bool pending = false;
+    bool first_ran = false;  // the first group of the current build was such a group
+    bool lazy = false;
+    bool first_slot[2] = {false, false};  // the chunk in this slot is the first group of a deferred build
+    hipEvent_t ev_first[2] = {nullptr, nullptr};
+    double first_ms = 0.0;
     // Two captured chunk graphs used alternately, so that the events of one
     // can be read while the other runs.
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -142,6 +154,8 @@ void free_ctx(lp_ctx *h) {
         for (auto e : h->ev_upd[k])
             if (e) (void)hipEventDestroy(e);
     }
+    for (auto e : h->ev_first)
+        if (e) (void)hipEventDestroy(e);
     if (h->cols_done) (void)hipFree(h->cols_done);
     if (h->rparts) (void)hipFree(h->rparts);
     if (h->ticket) (void)hipFree(h->ticket);
@@ -195,6 +209,7 @@ int validate_opts(const lp_options &o) {
     if (o.decide_spin < 0) return set_error(LP_E_INVAL, "decide_spin must be >= 0");
     if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
         return set_error(LP_E_INVAL, "decide_block must be 0 (auto), 256 or 512");
+    if (o.eager_build < 0 || o.eager_build > 1) return set_error(LP_E_INVAL, "eager_build must be 0 or 1");
     return LP_OK;
 }
 
@@ -273,6 +288,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->select_wgs = o.select_workgroups > 0 ? o.select_workgroups : 1;
     h->use_graph = o.use_graph != 0;
     h->timing = o.time_kernels != 0;
+    h->eager_build = o.eager_build != 0;
 
     auto fail = [&](int rc) {
         free_ctx(h);
@@ -315,7 +331,9 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->log_q, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
     }
     if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->cols_done, sizeof(unsigned long long))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->cols_done, 4 * sizeof(unsigned long long))) return fail(rc);
+    if (hipMemset(h->cols_done, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (int rc = dev_alloc((void **)&h->rparts, 64 * sizeof(RatioPart))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->ticket, sizeof(uint32_t))) return fail(rc);
     if (hipMemset(h->ticket, 0, sizeof(uint32_t)) != hipSuccess)
@@ -357,21 +375,42 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
             h->ev_upd[k].assign(2 * (size_t)h->chunk, nullptr);
             for (auto &e : h->ev_upd[k])
                 if (hipEventCreate(&e) != hipSuccess) return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
+            if (hipEventCreate(&h->ev_first[k]) != hipSuccess)
+                return fail(set_error(LP_E_DEVICE, "hipEventCreate failed"));
         }
     }
     *out = h;
     return LP_OK;
 }
 
-// Initialization Step from device-resident inputs, on the context stream.
-int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *dc) {
+// The whole tableau of Table I: structural columns, slack identity and (with
+// `rhs`) the RHS column.
+void enqueue_full_build(lp_ctx *h, const double *dA, const double *db, const double *dc, bool rhs = true) {
     const int32_t m = h->m, n = h->n;
     const int64_t ld = h->ld;
     dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
     hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, h->stream, h->T, ld, m, n, dA, dc);
-    const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
+    const int32_t ncols = rhs ? m + 1 : m;  // without the RHS, b is not read (and may be NULL)
+    const int64_t nslack = (int64_t)ncols * (ld / 2);
     hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, h->stream, h->T, ld, m,
-                       n, db);
+                       n, db, ncols);
+}
+
+// Initialization Step from device-resident inputs, on the context stream.
+// Deferred (`defer`, with the one-launch decision kernel): only the RHS
+// column and the solver state here; the first group reads the structural
+// columns from A and c, and its update pass writes them.
+int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *dc, bool defer) {
+    const int32_t m = h->m, n = h->n;
+    const int64_t ld = h->ld;
+    defer = defer && !h->eager_build && h->fuse > 1 && h->decide_wgs > 0;
+    if (!defer) enqueue_full_build(h, dA, db, dc);
+    h->pending = defer;
+    h->first_ran = false;
+    h->lazy = defer;
+    h->pend_A = defer ? dA : nullptr;
+    h->pend_b = defer ? db : nullptr;
+    h->pend_c = defer ? dc : nullptr;
     DevState init{};
     init.status = LP_RUNNING;
     init.go = 0;
@@ -387,7 +426,8 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
         const int32_t kf = fused_update_kf(h->fuse);
         const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)kf * ld), h->Lg + 16);
         hipLaunchKernelGGL(k_ginit, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
-                           h->gs, h->basis, m, n, (int32_t)h->fuse, kf, h->F, ld, h->cols, h->pos, h->cols_done);
+                           h->gs, h->basis, m, n, (int32_t)h->fuse, kf, h->F, ld, h->cols, h->pos, h->cols_done,
+                           h->T, defer ? db : nullptr);
     } else {
         const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
         hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
@@ -513,6 +553,20 @@ void enqueue_group(lp_ctx *h, hipEvent_t e0, hipEvent_t e1) {
     launch_fused_update(a, u.block, u.cols, u.rv, h->stream, e0, e1);
 }
 
+// The first group after a deferred build, launched directly (its kernels
+// take the caller's A and c): the decisions, then the pass that writes the
+// structural columns with the group's pivots applied.
+int launch_first_group(lp_ctx *h) {
+    const FusedArgs a = fused_args(h);
+    launch_first_decide(a, h->pend_A, h->pend_c, h->stream);
+    if (h->timing)
+        launch_first_update(a, h->pend_A, h->pend_c, h->stream, h->ev_first[0], h->ev_first[1]);
+    else
+        launch_first_update(a, h->pend_A, h->pend_c, h->stream, nullptr, nullptr);
+    LP_HIP_CHECK(hipGetLastError());
+    return LP_OK;
+}
+
 // One chunk: `chunk` pivots of (select, stage, update), or `chunk` groups of
 // pivot fusion, with event records around each update kernel in timing mode.
 int enqueue_chunk(lp_ctx *h, int slot) {
@@ -577,6 +631,12 @@ int launch_chunk(lp_ctx *h, int slot) {
 // applied a pivot and the no-op ones queued after the solve ended.
 int harvest_timing(lp_ctx *h, int slot, int64_t advanced) {
     if (!h->timing) return LP_OK;
+    if (h->first_slot[slot]) {  // the first group of a deferred build: its own kernel, timed apart
+        float ms = 0.f;
+        LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_first[0], h->ev_first[1]));
+        h->first_ms += ms;
+        return LP_OK;
+    }
     for (int64_t k = 0; k < h->chunk; ++k) {
         float ms = 0.f;
         LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_upd[slot][2 * k], h->ev_upd[slot][2 * k + 1]));
@@ -601,16 +661,27 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     h->update_launches = 0;
     h->update_ms_applied = 0.0;
     h->applied_launches = 0;
+    h->first_ms = 0.0;
+    // the first chunk is the first group of a deferred build when one is pending
+    auto launch = [h](int sl) -> int {
+        h->first_slot[sl] = h->pending;
+        if (h->pending) {
+            h->pending = false;
+            h->first_ran = true;
+            return launch_first_group(h);
+        }
+        return launch_chunk(h, sl);
+    };
     int64_t last = h->pivots_host;  // pivots before the chunk being harvested
     hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
-    if (int rc = launch_chunk(h, 0)) return rc;
+    if (int rc = launch(0)) return rc;
     LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipEventRecord(h->ev_slot[0], h->stream));
     for (;;) {
         const int next = slot ^ 1;
-        if (int rc = launch_chunk(h, next)) return rc;
+        if (int rc = launch(next)) return rc;
         LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[next], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
         LP_HIP_CHECK(hipEventRecord(h->ev_slot[next], h->stream));
         LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
@@ -652,7 +723,7 @@ int lp_create_device(lp_ctx **out, int32_t m, int32_t n, const double *dA, const
     lp_ctx *h = nullptr;
     if (int rc = alloc_ctx(&h, m, n, opt)) return rc;
     DeviceGuard g(h->device);
-    if (int rc = enqueue_build(h, dA, db, dc)) {
+    if (int rc = enqueue_build(h, dA, db, dc, false)) {
         free_ctx(h);
         return rc;
     }
@@ -694,7 +765,7 @@ int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double 
         hipMemcpyAsync(stage + na, b, (size_t)m * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(stage + na + m, c, (size_t)n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess)
         rc = set_error(LP_E_DEVICE, "input copy failed");
-    if (!rc) rc = enqueue_build(h, stage, stage + na, stage + na + m);
+    if (!rc) rc = enqueue_build(h, stage, stage + na, stage + na + m, false);
     if (!rc && hipStreamSynchronize(h->stream) != hipSuccess) rc = set_error(LP_E_DEVICE, "build failed");
     (void)hipFree(stage);
     if (!rc) rc = capture_graphs(h);
@@ -709,7 +780,7 @@ int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double 
 int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double *dc) {
     if (!h || !dA || !db || !dc) return set_error(LP_E_INVAL, "NULL argument");
     DeviceGuard g(h->device);
-    return enqueue_build(h, dA, db, dc);
+    return enqueue_build(h, dA, db, dc, true);
 }
 
 int lp_solve(lp_ctx *h) {
@@ -770,9 +841,21 @@ int lp_get_pivots(const lp_ctx *h, int32_t *rows, int32_t *cols, int64_t cap, in
     return LP_OK;
 }
 
-int lp_get_tableau(const lp_ctx *h, double *out) {
-    if (!h || !out) return set_error(LP_E_INVAL, "NULL argument");
+int lp_get_tableau(const lp_ctx *hc, double *out) {
+    if (!hc || !out) return set_error(LP_E_INVAL, "NULL argument");
+    lp_ctx *h = const_cast<lp_ctx *>(hc);
     DeviceGuard g(h->device);
+    if (h->pending) {  // a deferred build nothing has run yet: build it now (b is already in the RHS)
+        enqueue_full_build(h, h->pend_A, nullptr, h->pend_c, false);
+        h->pending = false;
+        h->lazy = false;
+    } else if (h->lazy) {  // store the basic columns that were never stored
+        const int64_t nb = (int64_t)h->m * (h->ld / 2);
+        hipLaunchKernelGGL(k_store_basic, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
+                           h->m, (const int32_t *)h->basis);
+        h->lazy = false;
+    }
+    LP_HIP_CHECK(hipGetLastError());
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
     LP_HIP_CHECK(hipMemcpy2D(out, (size_t)(h->m + 1) * sizeof(double), h->T, (size_t)h->ld * sizeof(double),
                              (size_t)(h->m + 1) * sizeof(double), (size_t)h->W, hipMemcpyDeviceToHost));
@@ -807,10 +890,10 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
 int lp_get_timing(const lp_ctx *h, lp_timing *t) {
     if (!h || !t) return set_error(LP_E_INVAL, "NULL argument");
     DeviceGuard g(h->device);
-    unsigned long long cols = 0;
+    unsigned long long cols[4] = {0, 0, 0, 0};
     DevState s;
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    LP_HIP_CHECK(hipMemcpy(&cols, h->cols_done, sizeof(cols), hipMemcpyDeviceToHost));
+    LP_HIP_CHECK(hipMemcpy(cols, h->cols_done, sizeof(cols), hipMemcpyDeviceToHost));
     LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
     t->solve_ms = h->last_ms;
     t->update_ms = h->update_ms;
@@ -818,7 +901,11 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t) {
     t->update_ms_applied = h->update_ms_applied;
     t->applied_launches = h->applied_launches;
     t->pivots = s.pivots;
-    t->updated_columns = (int64_t)cols;
+    t->updated_columns = (int64_t)cols[0];
+    t->first_pass_ms = h->first_ms;
+    t->first_pass_pivots = (int64_t)cols[2];
+    t->first_pass_changed = (int64_t)cols[1];
+    t->first_pass_columns = h->first_ran ? (int64_t)h->n + 1 + (int64_t)cols[3] : 0;
     return LP_OK;
 }
 

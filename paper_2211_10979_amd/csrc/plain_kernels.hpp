@@ -66,12 +66,14 @@ static __global__ __launch_bounds__(256) void k_build_struct(double *__restrict_
     }
 }
 
-// Initialization Step, slack identity and right-hand side (columns n..W-1).
+// Initialization Step, slack identity and right-hand side: columns
+// n .. n+ncols-1, where ncols is m (the slack columns only; b is not read) or
+// m + 1 (and the RHS column from b).
 static __global__ __launch_bounds__(256) void k_build_slack(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                     const double *__restrict__ b) {
+                                                     const double *__restrict__ b, int32_t ncols) {
     const int64_t half = ld / 2;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)(m + 1) * half) return;
+    if (idx >= (int64_t)ncols * half) return;
     const int64_t s = idx / half, v = idx % half;
     const int64_t i0 = 2 * v, i1 = 2 * v + 1;
     double2 y;
@@ -546,19 +548,43 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
     }
 }
 
-// Finalization: x (n), y (m) and the objective into out[0 .. n+m].
+// Finalization: x (n), y (m) and the objective into out[0 .. n+m]. y_i is
+// the row-0 entry of slack column n+i-1: read from the tableau when that
+// column is nonbasic, 0 when it is basic (a basic column is a unit vector
+// with 0 in row 0, and may not be stored: see k_store_basic). The y slots
+// first mark "nonbasic" (1), the basic slacks then clear theirs (0).
 static __global__ __launch_bounds__(1024) void k_extract(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                  const int32_t *__restrict__ basis, double *__restrict__ out) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int64_t W = (int64_t)n + m + 1;
     for (int32_t j = tid; j < n; j += nt) out[j] = 0.0;
+    for (int32_t i = tid; i < m; i += nt) out[n + i] = 1.0;
     __syncthreads();
     for (int32_t i = 1 + tid; i <= m; i += nt) {
         const int32_t bv = basis[i - 1];
-        if (bv < n) out[bv] = T[(W - 1) * ld + i];
-        out[n + i - 1] = T[((int64_t)n + i - 1) * ld];
+        out[bv] = bv < n ? T[(W - 1) * ld + i] : 0.0;
     }
+    __syncthreads();
+    for (int32_t i = tid; i < m; i += nt)
+        if (out[n + i] != 0.0) out[n + i] = T[((int64_t)n + i) * ld];
     if (tid == 0) out[n + m] = T[(W - 1) * ld];
+}
+
+// Stores every basic column as the unit vector it is: the basic column of
+// row i is e_i (rows 0 .. ld-1, padding zero). A column stored before holds
+// exactly that already; one never stored (a slack column after a deferred
+// build) gets its value.
+static __global__ __launch_bounds__(256) void k_store_basic(double *__restrict__ T, int64_t ld, int32_t m,
+                                                            const int32_t *__restrict__ basis) {
+    const int64_t half = ld / 2;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)m * half) return;
+    const int64_t r = idx / half + 1, v = idx % half;  // tableau row r, row pair v
+    const int64_t col = basis[r - 1];
+    double2 y;
+    y.x = (2 * v == r) ? 1.0 : 0.0;
+    y.y = (2 * v + 1 == r) ? 1.0 : 0.0;
+    reinterpret_cast<double2 *>(T + col * ld)[v] = y;
 }
 
 }  // namespace lpgpu

@@ -320,7 +320,7 @@ void admission_loop(lp_server *s, int w) {
         hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, copy, d.T, d.ld, m, n, A, c);
         const int64_t nslack = (int64_t)(m + 1) * (d.ld / 2);
         hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, copy, d.T, d.ld, m,
-                           n, bb);
+                           n, bb, m + 1);
         hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, copy, d, s->state + r->slot, init);
         ok = ok && hipMemcpyAsync(s->desc + r->slot, &d, sizeof(BatchDesc), hipMemcpyHostToDevice, copy) ==
                        hipSuccess;
@@ -502,7 +502,8 @@ bool run_large(lp_server *s, int w, Request *r, const LargeLayout &L, char *bloc
     dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
     hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, st, d.T, ld, m, n, A, c);
     const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
-    hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n, bb);
+    hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n, bb,
+                       m + 1);
     DevState init{};
     init.status = LP_RUNNING;
     init.stop_at = INT64_MAX;

@@ -61,7 +61,7 @@ class lp_options(ctypes.Structure):
         ("decide_kernel", ctypes.c_int32),
         ("decide_spin", ctypes.c_int32),
         ("decide_block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("eager_build", ctypes.c_int32),
     ]
 
 
@@ -101,6 +101,10 @@ class lp_timing(ctypes.Structure):
         ("updated_columns", ctypes.c_int64),
         ("update_ms_applied", ctypes.c_double),
         ("applied_launches", ctypes.c_int64),
+        ("first_pass_ms", ctypes.c_double),
+        ("first_pass_pivots", ctypes.c_int64),
+        ("first_pass_changed", ctypes.c_int64),
+        ("first_pass_columns", ctypes.c_int64),
     ]
 
 

@@ -1,0 +1,209 @@
+"""GPU parity of the deferred build against the CPU oracle, through the C ABI.
+
+lp_reload_device with the one-launch decision kernel does not build the
+tableau at once: the first group's decisions read the structural columns from
+A and c, its update pass writes them with the group's pivots applied, and a
+slack column is stored only when it leaves the basis. The bar is the same as
+for the built tableau: identical pivot log, basis, status, x, y and objective,
+and the tableau equal element by element (lp_get_tableau stores the basic
+columns first). Before every reload the tableau memory is filled with NaN, so
+that any entry read before it is written shows in the results.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_10979_amd import lpgen
+
+pytestmark = pytest.mark.gpu
+
+lpgpu = pytest.importorskip("paper_2211_10979_amd.lpgpu")
+torch = pytest.importorskip("torch")
+
+from test_gpu_fused import degenerate_lp, group_events  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", 0))
+
+
+class Deferred:
+    """A context whose tableau lives in a caller-owned buffer, so that the
+    test can poison it before each reload."""
+
+    def __init__(self, m, n, **opts):
+        self.m, self.n = m, n
+        nbytes = lpgpu.lp_tableau_bytes(m, n)
+        self.buf = torch.empty(nbytes // 8, dtype=torch.float64, device=torch.device("cuda", 0))
+        one = dev(np.ones((m, n))), dev(np.ones(m)), dev(np.ones(n))
+        self.h = lpgpu.lp_create_device(m, n, *one, device_buffer=self.buf, **opts)
+
+    def reload(self, A, b, c):
+        self.inputs = dev(A), dev(b), dev(c)  # kept alive until the next reload
+        torch.cuda.synchronize()
+        self.buf.fill_(float("nan"))
+        torch.cuda.synchronize()
+        lpgpu.lp_reload_device(self.h, *self.inputs)
+
+    def close(self):
+        lpgpu.lp_destroy(self.h)
+
+
+def compare_final(h, o):
+    res, x, y = lpgpu.lp_get_solution(h)
+    rows, cols = lpgpu.lp_get_pivots(h)
+    orow, ocol = o.log()
+    assert res["status"] == o.status
+    assert res["pivots"] == o.pivots
+    assert rows.tolist() == orow.tolist() and cols.tolist() == ocol.tolist()
+    ox, oy, oobj = o.extract()
+    assert np.array_equal(x, ox) and np.array_equal(y, oy)
+    assert res["objective"] == oobj or (np.isnan(res["objective"]) and np.isnan(oobj))
+    assert lpgpu.lp_get_basis(h).tolist() == o.basis().tolist()
+    # after the solution: lp_get_tableau stores the basic columns
+    assert np.array_equal(lpgpu.lp_get_tableau(h), o.tableau())
+    return orow.tolist(), ocol.tolist()
+
+
+@pytest.mark.parametrize("K", [2, 4, 11, 16])
+def test_degenerate_battery_deferred(K):
+    """120 small LPs of several shapes through one context each, reloaded;
+    the battery has in-group re-entries, so slack columns are stored on
+    leaving and read again within the group."""
+    say(f"deferred build K={K}: degenerate battery")
+    events = np.zeros(2, dtype=int)
+    for seed in range(120):
+        A, b, c = degenerate_lp(seed, seed % 4)
+        m, n = A.shape
+        d = Deferred(m, n, fuse_pivots=K)
+        o = oracle.OracleLP(A, b, c)
+        try:
+            assert lpgpu.lp_get_info(d.h).decide_workgroups > 0
+            d.reload(A, b, c)
+            lpgpu.lp_solve(d.h)
+            o.step(-1)
+            rows, cols = compare_final(d.h, o)
+            events += group_events(m, n, rows, cols, K)
+        finally:
+            d.close()
+            o.close()
+    assert events[1] > 0 and (K == 2 or events[0] > 0), events
+
+
+@pytest.mark.parametrize("K", [7, 16])
+def test_stepping_after_reload(K):
+    """A first lp_step of 0 pivots (the first pass only builds), then
+    budgets that cut groups short; the tableau after every step."""
+    lp = lpgen.workload("dense_200x200")
+    say(f"deferred build K={K}: dense_200x200 stepping")
+    d = Deferred(lp.m, lp.n, fuse_pivots=K)
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    try:
+        d.reload(lp.A, lp.b, lp.c)
+        lpgpu.lp_step(d.h, 0)
+        assert np.array_equal(lpgpu.lp_get_tableau(d.h), o.tableau()), "built by a pass of no pivots"
+        budgets = [1, K, K + 1, 2 * K - 1, 3]
+        k = 0
+        while True:
+            every = budgets[k % len(budgets)]
+            k += 1
+            lpgpu.lp_step(d.h, every)
+            st = o.step(every)
+            res, _, _ = lpgpu.lp_get_solution(d.h)
+            assert res["pivots"] == o.pivots
+            assert np.array_equal(lpgpu.lp_get_tableau(d.h), o.tableau()), f"after pivot {o.pivots}"
+            if st != oracle.RUNNING:
+                break
+        compare_final(d.h, o)
+    finally:
+        d.close()
+        o.close()
+
+
+def test_tableau_before_any_solve():
+    """lp_get_tableau while the deferred build is pending builds it there;
+    the solve then continues from the built tableau."""
+    lp = lpgen.workload("dense_200x200")
+    say("deferred build: tableau before the solve")
+    d = Deferred(lp.m, lp.n)
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    try:
+        d.reload(lp.A, lp.b, lp.c)
+        assert np.array_equal(lpgpu.lp_get_tableau(d.h), o.tableau()), "initial tableau"
+        lpgpu.lp_solve(d.h)
+        o.step(-1)
+        compare_final(d.h, o)
+    finally:
+        d.close()
+        o.close()
+
+
+@pytest.mark.parametrize("shape", [(301, 401), (300, 400), (2000, 2000)])
+def test_full_solve_and_alignment(shape):
+    """Odd and even n, A at an 8-byte offset (no 16-byte loads of A), and the
+    dense 2000 x 2000 LP."""
+    m, n = shape
+    lp = lpgen.workload("dense_2000x2000") if shape == (2000, 2000) else lpgen.dense_lp(40 + n, m, n)
+    say(f"deferred build: {m}x{n}")
+    d = Deferred(m, n)
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    try:
+        flat = torch.empty(m * n + 1, dtype=torch.float64, device=torch.device("cuda", 0))
+        flat[1:] = dev(lp.A.ravel())
+        dA = flat[1:].view(m, n)
+        assert dA.data_ptr() % 16 == 8
+        db, dc = dev(lp.b), dev(lp.c)
+        torch.cuda.synchronize()
+        d.buf.fill_(float("nan"))
+        torch.cuda.synchronize()
+        lpgpu.lp_reload_device(d.h, dA, db, dc)
+        lpgpu.lp_solve(d.h)
+        o.step(-1)
+        compare_final(d.h, o)
+        # and again from 16-byte aligned inputs, same context
+        d.reload(lp.A, lp.b, lp.c)
+        lpgpu.lp_solve(d.h)
+        compare_final(d.h, o)
+    finally:
+        d.close()
+        o.close()
+
+
+def test_timing_counters_and_eager_option():
+    """time_kernels: the first pass is timed apart and counted; eager_build = 1
+    builds at once (no first pass) with the same results."""
+    lp = lpgen.workload("dense_2000x2000")
+    say("deferred build: counters, eager_build")
+    out = {}
+    for eager in (0, 1):
+        d = Deferred(lp.m, lp.n, time_kernels=1, eager_build=eager)
+        try:
+            d.reload(lp.A, lp.b, lp.c)
+            lpgpu.lp_solve(d.h)
+            res, x, y = lpgpu.lp_get_solution(d.h)
+            t = lpgpu.lp_get_timing(d.h)
+            out[eager] = (res, x, y, lpgpu.lp_get_tableau(d.h))
+            if eager:
+                assert t["first_pass_ms"] == 0 and t["first_pass_pivots"] == 0 and t["first_pass_columns"] == 0
+            else:
+                assert t["first_pass_ms"] > 0
+                assert t["first_pass_pivots"] == min(16, res["pivots"])
+                assert 0 < t["first_pass_changed"] <= t["updated_columns"]
+                assert lp.n + 1 < t["first_pass_columns"] <= lp.n + 1 + 16
+            # the update launches timed are those after the first group
+            assert t["applied_launches"] == -(-(res["pivots"] - t["first_pass_pivots"]) // 16)
+        finally:
+            d.close()
+    (r0, x0, y0, T0), (r1, x1, y1, T1) = out[0], out[1]
+    assert r0["pivots"] == r1["pivots"] and r0["objective"] == r1["objective"]
+    assert np.array_equal(x0, x1) and np.array_equal(y0, y1) and np.array_equal(T0, T1)
+    with pytest.raises(Exception):
+        lpgpu.lp_create(lp.A[:10, :10], lp.b[:10], lp.c[:10], eager_build=2)
