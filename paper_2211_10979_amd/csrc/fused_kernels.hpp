@@ -574,15 +574,21 @@ struct GridSync {
     uint32_t exits;  // workgroups that have left
 };
 
+// Thread 0 arrives with a release increment (the workgroup's writes, which
+// the workgroup barrier orders before it, become visible with the arrival),
+// polls the counter with relaxed loads, and after the wait issues one acquire
+// fence: the relaxed load that sees the target reads from the release
+// sequence of every arrival, so the fence makes all their writes visible
+// (fence synchronisation). An acquire on every poll would invalidate the
+// cache on every poll.
 __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, uint32_t spin_limit,
                                              DevState *st, int32_t *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();  // this workgroup's writes before its arrival
-        atomicAdd(&gsync->count, 1u);
+        __hip_atomic_fetch_add(&gsync->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t it = 0;
         bool ok = true;
-        while (__hip_atomic_load(&gsync->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&gsync->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (++it > spin_limit) {
                 ok = false;
                 break;
@@ -590,7 +596,7 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
             __builtin_amdgcn_s_sleep(2);
         }
         if (!ok) atomicExch(&st->status, (int32_t)LP_STALLED);
-        __threadfence();  // the others' writes before this workgroup reads
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_ok = ok;
     }
     __syncthreads();
