@@ -546,6 +546,79 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
 // ---------------------------------------------------------------------------
 // All decisions of a group in one launch.
 //
+// Reductions of the decision kernel. Within a row of 16 lanes the wave
+// argmin exchanges values by DPP (quad permutations, then the half-row and
+// row mirrors: after these four steps every lane holds its row's winner);
+// the last two steps cross rows with shuffles. The argmin is unique under
+// the (value, index) order of lex_less, so the result does not depend on the
+// order of the reduction: every wave that reduces the same candidates gets
+// the same winner.
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    return __hiloint2double(dpp_i32<CTRL>(__double2hiint(x)), dpp_i32<CTRL>(__double2loint(x)));
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int32_t lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp_step(double &v, int32_t &i, int32_t &t) {
+    const double ov = dpp_f64<CTRL>(v);
+    const int32_t oi = dpp_i32<CTRL>(i), ot = dpp_i32<CTRL>(t);
+    if (lex_less(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+        t = ot;
+    }
+}
+
+__device__ __forceinline__ void xor_step(double &v, int32_t &i, int32_t &t, int off) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int32_t oi = __shfl_xor(i, off, 64), ot = __shfl_xor(t, off, 64);
+    if (lex_less(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+        t = ot;
+    }
+}
+
+// wave argmin of (v, i) carrying t; every lane gets the winner
+__device__ __forceinline__ void wave_argmin_dpp(double &v, int32_t &i, int32_t &t) {
+    dpp_step<0xB1>(v, i, t);   // quad_perm [1,0,3,2]
+    dpp_step<0x4E>(v, i, t);   // quad_perm [2,3,0,1]
+    dpp_step<0x141>(v, i, t);  // row_half_mirror
+    dpp_step<0x140>(v, i, t);  // row_mirror
+    xor_step(v, i, t, 16);
+    xor_step(v, i, t, 32);
+}
+
+// Block argmin with one barrier: `sv`, `si`, `sl` (one entry per wave) must
+// belong to this call site alone, and a block-wide barrier must separate two
+// of its calls (the next call's writes then cannot meet this call's reads).
+template <int BD>
+__device__ __forceinline__ void block_argmin_dpp(double &v, int32_t &i, int32_t &t, double *sv, int32_t *si,
+                                                 int32_t *sl) {
+    wave_argmin_dpp(v, i, t);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sv[wave] = v;
+        si[wave] = i;
+        sl[wave] = t;
+    }
+    __syncthreads();
+    v = lane < BD / 64 ? sv[lane] : __builtin_inf();
+    i = lane < BD / 64 ? si[lane] : kNoIndex;
+    t = lane < BD / 64 ? sl[lane] : -1;
+    wave_argmin_dpp(v, i, t);
+}
+
 // k_gdecide runs the group's Steps 1-2 and the Step 3 inputs (what k_gselect
 // and k_gstage compute, with the same arithmetic in the same order) for up
 // to K pivots in one launch of G workgroups of BD threads (256 or 512),
@@ -626,12 +699,12 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
                                             int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
                                             int32_t *__restrict__ log_q, GRatio *__restrict__ rparts,
                                             GridSync *__restrict__ gsync, uint32_t spin_limit) {
-    __shared__ double sv[BD / 64];
-    __shared__ int32_t si[BD / 64], sl[BD / 64];
+    // one set of reduction slots per call site (ratio test, staging, start)
+    __shared__ double sv_r[BD / 64], sv_s[BD / 64], sv_0[BD / 64];
+    __shared__ int32_t si_r[BD / 64], si_s[BD / 64], si_0[BD / 64];
+    __shared__ int32_t sl_r[BD / 64], sl_s[BD / 64], sl_0[BD / 64];
     __shared__ int32_t s_ok;
-    __shared__ double s_p;
-    __shared__ int32_t s_leave, s_inlist;
-    const int tid = threadIdx.x, nt = BD;
+    const int tid = threadIdx.x;
     const int G = gridDim.x, w = blockIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
     const int64_t W = (int64_t)n + m + 1;
@@ -664,7 +737,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             di = c_t;
             ds = t;
         }
-        block_argmin_t(dv, di, ds, sv, si, sl);
+        block_argmin_dpp<BD>(dv, di, ds, sv_0, si_0, sl_0);
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
     }
     if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
@@ -683,10 +756,19 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         if (s0.pivots + j >= s0.stop_at) break;
 
         // Step 1
+        // (every wave reduces all G partials itself: no LDS, no barrier)
         double v = __builtin_inf();
         int32_t q = kNoIndex, tq = -1;
-        reduce_parts(sparts, G, tid, nt, v, q, tq);
-        block_argmin_t(v, q, tq, sv, si, sl);
+        {
+            const int lane = tid & 63;
+            SPart a = lane < G ? sparts[lane] : SPart{__builtin_inf(), kNoIndex, -1};
+            const SPart b = lane + 64 < G ? sparts[lane + 64] : SPart{__builtin_inf(), kNoIndex, -1};
+            if (lex_less(b.v, b.i, a.v, a.i)) a = b;
+            v = a.v;
+            q = a.i;
+            tq = a.t;
+            wave_argmin_dpp(v, q, tq);
+        }
         if (v != v || v >= -s0.eps_d) {
             if (w == 0 && tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
             break;
@@ -736,40 +818,45 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             }
         }
         const int32_t r_mine = r;
-        block_argmin(rv, r, sv, si);
-        const int bad = rv != rv;
-        if (r != kNoIndex && r_mine == r) {  // the one thread that owns row r
-            s_p = a;
-            s_leave = basis_i;
-            s_inlist = inlist_i;
+        {
+            int32_t unused = 0;
+            block_argmin_dpp<BD>(rv, r, unused, sv_r, si_r, sl_r);
         }
-        __syncthreads();
-        if (tid == 0)  // (lpos carries "the leaving column has a slot" here)
-            rparts[w] = r == kNoIndex ? GRatio{rv, r, bad, 0.0, -1, 0} : GRatio{rv, r, bad, s_p, s_leave, s_inlist};
+        // the workgroup's Step 2 partial, written by the thread that owns
+        // row r (by thread 0 when no row qualifies); lpos carries "the
+        // leaving column has a slot" here
+        if (r != kNoIndex && r_mine == r)
+            rparts[w] = GRatio{rv, r, rv != rv, a, basis_i, (int32_t)inlist_i};
+        else if (r == kNoIndex && tid == 0)
+            rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0};
         if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
 
         // the decision, reduced by every workgroup from all Step 2 partials
-        GRatio pr{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0};
-        if (tid < G) pr = rparts[tid];
-        rv = pr.v;
-        r = pr.r;
-        int32_t wk = tid;
-        block_argmin_t(rv, r, wk, sv, si, sl);
-        const int bad_all = rv != rv;
-        if (r != kNoIndex && wk == tid) {
-            s_p = pr.p;
-            s_leave = pr.leave;
-            s_inlist = pr.lpos;
+        // (every wave reduces all G partials itself; the winner's payload
+        // is read from the lane that holds it)
+        double p;
+        int32_t leave, inl;
+        {
+            const int lane = tid & 63;
+            const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0};
+            GRatio pa = lane < G ? rparts[lane] : none;
+            const GRatio pb = lane + 64 < G ? rparts[lane + 64] : none;
+            if (lex_less(pb.v, pb.r, pa.v, pa.r)) pa = pb;
+            rv = pa.v;
+            r = pa.r;
+            int32_t wl = lane;
+            wave_argmin_dpp(rv, r, wl);
+            p = readlane_f64(pa.p, wl);
+            leave = __builtin_amdgcn_readlane(pa.leave, wl);
+            inl = __builtin_amdgcn_readlane(pa.lpos, wl);
         }
-        __syncthreads();
+        const int bad_all = rv != rv;
         if (bad_all || r == kNoIndex || s0.pivots + j >= s0.max_pivots) {
             if (w == 0 && tid == 0)
                 st->status = bad_all ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
             break;
         }
-        const double p = s_p;
-        const int32_t leave = s_leave;
-        const int32_t aslot = s_inlist ? -1 : n + 1 + napp;  // appended slot of the leaving column
+        const int32_t aslot = inl ? -1 : n + 1 + napp;  // appended slot of the leaving column
         if (aslot >= 0) ++napp;
         if (w == 0 && tid == 0) {
             gs->r[j] = r;
@@ -840,7 +927,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             di = c_t;
             ds = t;
         }
-        block_argmin_t(dv, di, ds, sv, si, sl);
+        block_argmin_dpp<BD>(dv, di, ds, sv_s, si_s, sl_s);
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
         if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     }
