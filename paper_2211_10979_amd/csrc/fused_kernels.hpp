@@ -710,26 +710,101 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     const int64_t W = (int64_t)n + m + 1;
     uint32_t nbar = 0;
 
-    if (w == 0 && tid == 0) close_group(gs, cols, pos, n);
-    if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
-
     const DevState s0 = *st;
-    if (s0.status != LP_RUNNING) return;
+    const int32_t t = w * BD + tid;
+    const bool has_slot = t < Lg;
+    int32_t c_t = has_slot ? cols[t] : -1;
 
-    // this thread's row and slot, and their state at the start of the group
+    // The close of the previous group (see close_group), computed by every
+    // wave from the group record: lane k holds pivot k's entering column, its
+    // slot, its leaving column and the column appended in slot n+1+k. Every
+    // thread applies the result to its own slot; workgroup 0 stores it once
+    // every workgroup has read the list (after the first barrier, or on the
+    // way out).
+    const int lane = tid & 63;
+    const int32_t kd0 = gs->kdone, na0 = gs->napp;
+    int32_t cq = -1, cl = -1, ca = -1, cp = -1;
+    if (lane < kMaxFuse) {
+        cq = gs->q[lane];
+        cl = gs->l[lane];
+        ca = cols[n + 1 + lane];
+    }
+    if (lane >= kd0) {
+        cq = -1;
+        cl = -1;
+    }
+    if (lane >= na0) ca = -1;
+    if (cq >= 0) cp = pos[cq];
+    bool qb = false, ab = false, first = true;  // basic at the end (the last event decides)
+#pragma unroll
+    for (int e = 0; e < kMaxFuse; ++e) {
+        const int32_t qe = __builtin_amdgcn_readlane(cq, e), le = __builtin_amdgcn_readlane(cl, e);
+        if (qe >= 0 && qe == cq) qb = true;
+        if (le >= 0 && le == cq) qb = false;
+        if (qe >= 0 && qe == ca) ab = true;
+        if (le >= 0 && le == ca) ab = false;
+        if (e < lane && qe >= 0 && qe == cq) first = false;  // a column entered twice holds one slot
+    }
+    // slots freed (entered, still basic, slot below n) and appended columns
+    // that stay nonbasic, paired in order
+    const uint64_t free_mask = __ballot(cq >= 0 && first && cp >= 0 && cp < n && qb);
+    const uint64_t move_mask = __ballot(ca >= 0 && !ab);
+    // what workgroup 0 stores: bit 0 pos[cq] = -1, bit 1 pos[ca] = -1, bit 2
+    // slot n+1+lane cleared
+    const int32_t cflags = (cq >= 0 && qb && cp >= 0 ? 1 : 0) | (ca >= 0 && ab ? 2 : 0) | (ca >= 0 ? 4 : 0);
+    {
+        uint64_t fm = free_mask, mm = move_mask;
+#pragma unroll
+        for (int u = 0; u < kMaxFuse; ++u) {
+            if (fm == 0 || mm == 0) break;
+            const int32_t k = __builtin_ctzll(fm), a = __builtin_ctzll(mm);
+            fm &= fm - 1;
+            mm &= mm - 1;
+            if (t == __builtin_amdgcn_readlane(cp, k)) c_t = __builtin_amdgcn_readlane(ca, a);
+        }
+        if (t > n) c_t = -1;  // appended slots are empty after the close
+    }
+    // stores the close (one thread of workgroup 0)
+    auto store_close = [&]() {
+#pragma unroll
+        for (int e = 0; e < kMaxFuse; ++e) {
+            const int32_t f = __builtin_amdgcn_readlane(cflags, e);
+            if (f & 1) pos[__builtin_amdgcn_readlane(cq, e)] = -1;
+            if (f & 2) pos[__builtin_amdgcn_readlane(ca, e)] = -1;
+            if (f & 4) cols[n + 1 + e] = -1;
+        }
+        uint64_t fm = free_mask, mm = move_mask;
+#pragma unroll
+        for (int u = 0; u < kMaxFuse; ++u) {
+            if (fm == 0 || mm == 0) break;
+            const int32_t k = __builtin_ctzll(fm), a = __builtin_ctzll(mm);
+            fm &= fm - 1;
+            mm &= mm - 1;
+            const int32_t ts = __builtin_amdgcn_readlane(cp, k), cm = __builtin_amdgcn_readlane(ca, a);
+            cols[ts] = cm;
+            pos[cm] = ts;
+        }
+        gs->kdone = 0;
+        gs->napp = 0;
+    };
+    if (s0.status != LP_RUNNING) {
+        if (w == 0 && tid == 0) store_close();
+        return;
+    }
+
+    // this thread's row and slot, and their state at the start of the group;
+    // after the close no basic column is in the list
     const int32_t i = w * BD + tid;
     const bool has_row = i <= m;
     const int32_t is = has_row ? i : 0;
     const double rhs0 = T[(W - 1) * ld + is];
     int32_t basis_i = (has_row && i >= 1) ? basis[i - 1] : -1;
-    bool inlist_i = basis_i >= 0 && pos[basis_i] >= 0;
-    const int32_t t = w * BD + tid;
-    const bool has_slot = t < Lg;
-    int32_t c_t = has_slot ? cols[t] : -1;
+    bool inlist_i = false;
     double D_t = c_t >= 0 ? start_entry<First>(T, ld, n, A, cv, c_t, 0) : 0.0;
-    {
-        // Step 1 partials of the group's first pivot: the slots' row-0
-        // entries after the previous update
+    if (s0.fresh) {
+        // Step 1 partials of the first pivot after the build (later groups
+        // find them where the previous group's last staging left them: its
+        // row-0 entries after its last pivot, the values the update wrote)
         double dv = __builtin_inf();
         int32_t di = kNoIndex, ds = -1;
         if (c_t >= 0 && c_t != n + m) {
@@ -739,8 +814,8 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         block_argmin_dpp<BD>(dv, di, ds, sv_0, si_0, sl_0);
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
+        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     }
-    if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     double frow[kMaxFuse], rslot[kMaxFuse];
     int32_t rk[kMaxFuse];
 #pragma unroll
@@ -753,14 +828,13 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     int kd = 0;  // pivots decided in this group
 
     for (int j = 0; j < K; ++j) {
-        if (s0.pivots + j >= s0.stop_at) break;
+        const bool budget = s0.pivots + j >= s0.stop_at;
 
         // Step 1
         // (every wave reduces all G partials itself: no LDS, no barrier)
         double v = __builtin_inf();
         int32_t q = kNoIndex, tq = -1;
-        {
-            const int lane = tid & 63;
+        if (!budget) {
             SPart a = lane < G ? sparts[lane] : SPart{__builtin_inf(), kNoIndex, -1};
             const SPart b = lane + 64 < G ? sparts[lane + 64] : SPart{__builtin_inf(), kNoIndex, -1};
             if (lex_less(b.v, b.i, a.v, a.i)) a = b;
@@ -769,12 +843,21 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             tq = a.t;
             wave_argmin_dpp(v, q, tq);
         }
-        if (v != v || v >= -s0.eps_d) {
+        // (the same decisions in every workgroup: the same partials)
+        bool stop = budget;
+        if (!stop && (v != v || v >= -s0.eps_d)) {
             if (w == 0 && tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
-            break;
+            stop = true;
         }
-        if (tq < 0) {  // a broken list ends the solve instead of reading outside R
+        if (!stop && tq < 0) {  // a broken list ends the solve instead of reading outside R
             if (w == 0 && tid == 0) st->status = LP_NUMERICAL;
+            stop = true;
+        }
+        if (stop) {
+            if (j == 0) {  // the close is stored once every workgroup has read the list
+                if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+                if (w == 0 && tid == 0) store_close();
+            }
             break;
         }
 
@@ -830,6 +913,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         else if (r == kNoIndex && tid == 0)
             rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0};
         if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+        if (j == 0 && w == 0 && tid == 0) store_close();  // every workgroup has read the list
 
         // the decision, reduced by every workgroup from all Step 2 partials
         // (every wave reduces all G partials itself; the winner's payload
@@ -837,7 +921,6 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         double p;
         int32_t leave, inl;
         {
-            const int lane = tid & 63;
             const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0};
             GRatio pa = lane < G ? rparts[lane] : none;
             const GRatio pb = lane + 64 < G ? rparts[lane + 64] : none;
