@@ -149,8 +149,8 @@ def bench_plain(args, lpgpu, lpgen, torch):
         rows, cols = lpgpu.lp_get_pivots(h)
         info = lpgpu.lp_get_info(h)
         fuse = info.update_fuse
-        if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12 or 16 pivots
-            kf = next(k for k in (2, 4, 8, 12, 16) if k >= fuse)
+        if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24 or 32 pivots
+            kf = next(k for k in (2, 4, 8, 12, 16, 24, 32) if k >= fuse)
             name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"
             kernel = f"{name}<{info.update_block}, {info.update_cols}, {kf}>"
         else:

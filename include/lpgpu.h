@@ -98,7 +98,7 @@ typedef struct {
                                compute unit (block 64..512), one column per tile (default 0) */
     int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
     int32_t select_workgroups; /* Steps 1-2 kernel: workgroups (1..64; 0 = 1) */
-    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..16; 0 = auto: 16 unless
+    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..32; 0 = auto: 16 unless
                                an option above asks for a form only K = 1 has). With K > 1 the
                                solver decides K pivots one after the other, each from row 0,
                                its pivot column and the RHS rebuilt by replaying the earlier
@@ -108,7 +108,8 @@ typedef struct {
                                K = 1, with 1/K of the update traffic. K > 1 needs
                                update_block 0 or <= 256, cols_per_block <= 8,
                                rows_per_thread 0 or 1, update_hints 0, update_grid_stride 0 and
-                               select_workgroups <= 1. */
+                               select_workgroups <= 1; K > 16 also needs the one-launch
+                               decision kernel and cols_per_block 0, 4 or 8. */
     int32_t decide_kernel;  /* K > 1: 0 = auto (one launch for all decisions of a group when
                                G = max(m + 1, n + 1 + K) / decide_block rounded up is at most
                                128 workgroups, else two launches per pivot); 1 = two launches

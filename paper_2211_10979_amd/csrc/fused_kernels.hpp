@@ -41,7 +41,8 @@
 
 namespace lpgpu {
 
-constexpr int kMaxFuse = 16;
+constexpr int kMaxFuse = 32;       // pivots per group with the one-launch decision kernel
+constexpr int kMaxFuseSplit = 16;  // with the two launches per pivot (k_gselect, k_gstage)
 
 // Decisions of the current group, resident in device memory.
 struct GroupState {
@@ -70,11 +71,13 @@ static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int3
         cols_done[2] = 0;
         cols_done[3] = 0;
     }
-    // with a deferred build, the right-hand side column (b in rows 1..m)
+    // with a deferred build, the right-hand side column (b in rows 1..m) and
+    // row 0 of the slack columns (0: they are basic)
     if (b && idx < ld) T[(int64_t)(n + m) * ld + idx] = (idx >= 1 && idx <= m) ? b[idx - 1] : 0.0;
+    if (b && idx < m) T[(int64_t)(n + idx) * ld] = 0.0;
     if (idx < m) basis[idx] = n + (int32_t)idx;
     if (idx < (int64_t)KF * ld) Fk[idx] = 0.0;
-    if (idx < Lg + 16) cols[idx] = idx < n ? (int32_t)idx : (idx == n ? n + m : -1);  // list + padding
+    if (idx < Lg + kMaxFuse) cols[idx] = idx < n ? (int32_t)idx : (idx == n ? n + m : -1);  // list + padding
     if (idx < (int64_t)n + m) pos[idx] = idx < n ? (int32_t)idx : -1;
 }
 
@@ -93,18 +96,18 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
     if (kd == 0) return;
     const int na = gs->napp;
     // loads without per-entry conditions (every index is in bounds: the
-    // group record has kMaxFuse entries, the list kMaxFuse padding slots),
+    // group record has kMaxFuseSplit entries, the list kMaxFuseSplit padding slots),
     // then the entries past the group masked out, so that no load waits for
     // another
-    int32_t qk[kMaxFuse], lk[kMaxFuse], app[kMaxFuse], pq[kMaxFuse];
+    int32_t qk[kMaxFuseSplit], lk[kMaxFuseSplit], app[kMaxFuseSplit], pq[kMaxFuseSplit];
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) {
+    for (int k = 0; k < kMaxFuseSplit; ++k) {
         qk[k] = gs->q[k];
         lk[k] = gs->l[k];
         app[k] = cols[n + 1 + k];
     }
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) {
+    for (int k = 0; k < kMaxFuseSplit; ++k) {
         const bool in = k < kd && qk[k] >= 0;
         pq[k] = pos[in ? qk[k] : 0];
         if (!in) {
@@ -115,12 +118,12 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
         if (k >= na) app[k] = -1;
     }
     // the last event of the group decides: entered -> basic, left -> nonbasic
-    bool qb[kMaxFuse], ab[kMaxFuse];  // entered column k / appended column s basic at the end
+    bool qb[kMaxFuseSplit], ab[kMaxFuseSplit];  // entered column k / appended column s basic at the end
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) {
+    for (int k = 0; k < kMaxFuseSplit; ++k) {
         bool bq = false, ba = false;
 #pragma unroll
-        for (int e = 0; e < kMaxFuse; ++e) {
+        for (int e = 0; e < kMaxFuseSplit; ++e) {
             if (qk[e] == qk[k]) bq = true;
             if (lk[e] == qk[k]) bq = false;
             if (qk[e] == app[k]) ba = true;
@@ -129,19 +132,19 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
         qb[k] = bq;
         ab[k] = ba;
     }
-    bool free_k[kMaxFuse];  // entered column k still basic and holding a slot below n
+    bool free_k[kMaxFuseSplit];  // entered column k still basic and holding a slot below n
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) {
+    for (int k = 0; k < kMaxFuseSplit; ++k) {
         bool first = true;  // a column entered twice holds its slot once
 #pragma unroll
         for (int e = 0; e < k; ++e) first &= qk[e] != qk[k];
         free_k[k] = k < kd && first && pq[k] >= 0 && pq[k] < n && qb[k];
     }
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k)
+    for (int k = 0; k < kMaxFuseSplit; ++k)
         if (k < kd && qb[k] && pq[k] >= 0) pos[qk[k]] = -1;
 #pragma unroll
-    for (int s = 0; s < kMaxFuse; ++s) {
+    for (int s = 0; s < kMaxFuseSplit; ++s) {
         if (s < na) {
             const int32_t c = app[s];
             if (ab[s]) {
@@ -149,7 +152,7 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
             } else {
                 int32_t t = -1;
 #pragma unroll
-                for (int k = 0; k < kMaxFuse; ++k)
+                for (int k = 0; k < kMaxFuseSplit; ++k)
                     if (t < 0 && free_k[k]) {
                         t = pq[k];
                         free_k[k] = false;
@@ -688,7 +691,7 @@ __device__ __forceinline__ double start_entry(const double *__restrict__ T, int6
     return T[(int64_t)col * ld + row];
 }
 
-template <int BD, bool First>
+template <int BD, bool First, int KM>
 __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                             const double *__restrict__ A, const double *__restrict__ cv,
                                             int32_t K, int32_t KF, SPart *__restrict__ sparts,
@@ -724,7 +727,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     const int lane = tid & 63;
     const int32_t kd0 = gs->kdone, na0 = gs->napp;
     int32_t cq = -1, cl = -1, ca = -1, cp = -1;
-    if (lane < kMaxFuse) {
+    if (lane < KM) {
         cq = gs->q[lane];
         cl = gs->l[lane];
         ca = cols[n + 1 + lane];
@@ -737,7 +740,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     if (cq >= 0) cp = pos[cq];
     bool qb = false, ab = false, first = true;  // basic at the end (the last event decides)
 #pragma unroll
-    for (int e = 0; e < kMaxFuse; ++e) {
+    for (int e = 0; e < KM; ++e) {
         const int32_t qe = __builtin_amdgcn_readlane(cq, e), le = __builtin_amdgcn_readlane(cl, e);
         if (qe >= 0 && qe == cq) qb = true;
         if (le >= 0 && le == cq) qb = false;
@@ -755,7 +758,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     {
         uint64_t fm = free_mask, mm = move_mask;
 #pragma unroll
-        for (int u = 0; u < kMaxFuse; ++u) {
+        for (int u = 0; u < KM; ++u) {
             if (fm == 0 || mm == 0) break;
             const int32_t k = __builtin_ctzll(fm), a = __builtin_ctzll(mm);
             fm &= fm - 1;
@@ -764,31 +767,28 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         if (t > n) c_t = -1;  // appended slots are empty after the close
     }
-    // stores the close (one thread of workgroup 0)
+    // Stores the close: wave 0 of workgroup 0, every lane active (no lane
+    // reads another's registers inside divergent code). Lane k stores its own
+    // entries; the a-th column to move takes the a-th freed slot.
     auto store_close = [&]() {
-#pragma unroll
-        for (int e = 0; e < kMaxFuse; ++e) {
-            const int32_t f = __builtin_amdgcn_readlane(cflags, e);
-            if (f & 1) pos[__builtin_amdgcn_readlane(cq, e)] = -1;
-            if (f & 2) pos[__builtin_amdgcn_readlane(ca, e)] = -1;
-            if (f & 4) cols[n + 1 + e] = -1;
+        if (cflags & 1) pos[cq] = -1;
+        if (cflags & 2) pos[ca] = -1;
+        if (cflags & 4) cols[n + 1 + lane] = -1;
+        const int32_t rank = __popcll(move_mask & ((1ull << lane) - 1));
+        uint64_t fm = free_mask;
+        for (int32_t u = 0; u < rank; ++u) fm &= fm - 1;
+        const int32_t ts = __shfl(cp, fm ? __builtin_ctzll(fm) : 0, 64);
+        if (((move_mask >> lane) & 1) && fm) {
+            cols[ts] = ca;
+            pos[ca] = ts;
         }
-        uint64_t fm = free_mask, mm = move_mask;
-#pragma unroll
-        for (int u = 0; u < kMaxFuse; ++u) {
-            if (fm == 0 || mm == 0) break;
-            const int32_t k = __builtin_ctzll(fm), a = __builtin_ctzll(mm);
-            fm &= fm - 1;
-            mm &= mm - 1;
-            const int32_t ts = __builtin_amdgcn_readlane(cp, k), cm = __builtin_amdgcn_readlane(ca, a);
-            cols[ts] = cm;
-            pos[cm] = ts;
+        if (lane == 0) {
+            gs->kdone = 0;
+            gs->napp = 0;
         }
-        gs->kdone = 0;
-        gs->napp = 0;
     };
     if (s0.status != LP_RUNNING) {
-        if (w == 0 && tid == 0) store_close();
+        if (w == 0 && tid < 64) store_close();
         return;
     }
 
@@ -816,10 +816,10 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
         if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     }
-    double frow[kMaxFuse], rslot[kMaxFuse];
-    int32_t rk[kMaxFuse];
+    double frow[KM], rslot[KM];
+    int32_t rk[KM];
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) {
+    for (int k = 0; k < KM; ++k) {
         frow[k] = 0.0;
         rslot[k] = 0.0;
         rk[k] = -1;
@@ -856,27 +856,27 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         if (stop) {
             if (j == 0) {  // the close is stored once every workgroup has read the list
                 if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
-                if (w == 0 && tid == 0) store_close();
+                if (w == 0 && tid < 64) store_close();
             }
             break;
         }
 
         // Step 2 on this thread's row of column q and the RHS after the j
         // earlier pivots; the row's entry of column q is kept as F_j[i]. The
-        // coefficients of all kMaxFuse steps are loaded in one batch (index
+        // coefficients of all KM steps are loaded in one batch (index
         // clamped into the buffer) and the steps k >= j are masked out by
         // selects, so that no load waits behind another.
         const int32_t tqs = tq < 0 ? 0 : tq;
-        double Rq[kMaxFuse], Rb[kMaxFuse];
+        double Rq[KM], Rb[KM];
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k) {
+        for (int k = 0; k < KM; ++k) {
             const int64_t kk = k < K ? k : K - 1;
             Rq[k] = Rk[kk * Lg + tqs];
             Rb[k] = Rk[kk * Lg + n];
         }
         double a = start_entry<First>(T, ld, n, A, cv, q, is), bb = rhs0;
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k) {
+        for (int k = 0; k < KM; ++k) {
             const bool on = k < j, piv = i == rk[k];
             const double na = piv ? Rq[k] : fma(-frow[k], Rq[k], a);
             const double nb = piv ? Rb[k] : fma(-frow[k], Rb[k], bb);
@@ -884,7 +884,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             bb = on ? nb : bb;
         }
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k)
+        for (int k = 0; k < KM; ++k)
             if (k == j) frow[k] = a;
         if (has_row) Fk[(int64_t)j * ld + i] = a;
         // a NaN (in the column, the RHS or a ratio) becomes a NaN candidate,
@@ -913,7 +913,10 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         else if (r == kNoIndex && tid == 0)
             rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0};
         if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
-        if (j == 0 && w == 0 && tid == 0) store_close();  // every workgroup has read the list
+        if (j == 0 && w == 0) {  // every workgroup has read the list
+            if (tid < 64) store_close();
+            __syncthreads();  // before the decision record below
+        }
 
         // the decision, reduced by every workgroup from all Step 2 partials
         // (every wave reduces all G partials itself; the winner's payload
@@ -963,7 +966,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         kd = j + 1;
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k)
+        for (int k = 0; k < KM; ++k)
             if (k == j) rk[k] = r;
         if (i == r) {
             basis_i = q;
@@ -982,9 +985,9 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // j earlier pivots, R_j[t] = that / p, and the row-0 entry after
         // pivot j (R = 0 for a slot not filled yet: its column is a unit
         // vector that no pivot of the group has changed)
-        double Fr[kMaxFuse];  // F_k[r], one batch as above
+        double Fr[KM];  // F_k[r], one batch as above
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k) Fr[k] = Fk[(int64_t)(k < K ? k : K - 1) * ld + r];
+        for (int k = 0; k < KM; ++k) Fr[k] = Fk[(int64_t)(k < K ? k : K - 1) * ld + r];
         const double F0 = Fk[(int64_t)j * ld];
         double R = 0.0;
         if (c_t >= 0) {
@@ -992,7 +995,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             // taken as is, since the store above may not be visible yet)
             double y = t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r);
 #pragma unroll
-            for (int k = 0; k < kMaxFuse; ++k) {
+            for (int k = 0; k < KM; ++k) {
                 const double ny = (r == rk[k]) ? rslot[k] : fma(-Fr[k], rslot[k], y);
                 y = k < j ? ny : y;
             }
@@ -1000,7 +1003,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             D_t = fma(-F0, R, D_t);
         }
 #pragma unroll
-        for (int k = 0; k < kMaxFuse; ++k)
+        for (int k = 0; k < KM; ++k)
             if (k == j) rslot[k] = R;
         if (has_slot) Rk[(int64_t)j * Lg + t] = R;
         double dv = __builtin_inf();
@@ -1025,7 +1028,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     // columns the group changes: some R entry of the slot nonzero
     bool nz = false;
 #pragma unroll
-    for (int k = 0; k < kMaxFuse; ++k) nz |= k < kd && rslot[k] != 0.0;
+    for (int k = 0; k < KM; ++k) nz |= k < kd && rslot[k] != 0.0;
     const unsigned long long cnt = __popcll(__ballot(nz));
     if ((tid & 63) == 0 && cnt) {
         atomicAdd(cols_done, cnt);
@@ -1037,7 +1040,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     }
 }
 
-template <int BD, bool First>
+template <int BD, bool First, int KM>
 __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                  const double *__restrict__ A, const double *__restrict__ cv,
                                                  int32_t K, int32_t KF, SPart *__restrict__ sparts,
@@ -1048,7 +1051,7 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
                                                  uint32_t spin_limit) {
-    decide_body<BD, First>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
+    decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
                 spin_limit);
     // every workgroup leaves through here; the last one resets the barrier
     __syncthreads();

@@ -60,8 +60,16 @@ UpdateFn pick_pure(int K) {
         case 8: return update_pure<B, C, 8>;
         case 12: return update_pure<B, C, 12>;
         case 16: return update_pure<B, C, 16>;
-        default: return nullptr;
+        default: break;
     }
+    if constexpr (C >= 4) {  // groups above 16 pivots: 4 or 8 slots per workgroup
+        switch (fused_update_kf(K)) {
+            case 24: return update_pure<B, C, 24>;
+            case 32: return update_pure<B, C, 32>;
+            default: break;
+        }
+    }
+    return nullptr;
 }
 
 // The pure update pass (with the one-launch decision kernel), same shapes.
@@ -93,7 +101,7 @@ UpdateFn pick_k(int K) {
 // Tile shapes with instances: 64, 128 or 256 threads (one row pair each) by
 // 1, 2, 4 or 8 list slots.
 UpdateFn find_update(int block, int cols, int rv, int K) {
-    if (rv != 1) return nullptr;
+    if (rv != 1 || K > kMaxFuseSplit) return nullptr;
 #define LP_FSHAPE(B, C) \
     if (block == B && cols == C) return pick_k<B, C>(K);
     LP_FSHAPE(256, 1) LP_FSHAPE(256, 2) LP_FSHAPE(256, 4) LP_FSHAPE(256, 8)
@@ -105,27 +113,44 @@ UpdateFn find_update(int block, int cols, int rv, int K) {
 
 }  // namespace
 
-bool fused_update_supported(int block, int cols, int rv, int K) { return find_update(block, cols, rv, K) != nullptr; }
+bool fused_update_supported(int block, int cols, int rv, int K, bool one_launch) {
+    return (one_launch ? find_update_pure(block, cols, rv, K) : find_update(block, cols, rv, K)) != nullptr;
+}
 
-template <int BD, bool First>
+template <int BD, bool First, int KM>
 void decide_bd(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
-    hipLaunchKernelGGL((k_gdecide<BD, First>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n, A, c,
-                       a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis, a.log_r,
-                       a.log_q, a.rparts, a.gsync, a.decide_spin);
+    hipLaunchKernelGGL((k_gdecide<BD, First, KM>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n,
+                       A, c, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis,
+                       a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin);
+}
+
+// the instance for the group size (its KF pivot slots kept in registers)
+template <int BD, bool First>
+void decide_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
+    switch (a.KF) {
+        case 2: decide_bd<BD, First, 2>(a, A, c, s); break;
+        case 4: decide_bd<BD, First, 4>(a, A, c, s); break;
+        case 8: decide_bd<BD, First, 8>(a, A, c, s); break;
+        case 12: decide_bd<BD, First, 12>(a, A, c, s); break;
+        case 16: decide_bd<BD, First, 16>(a, A, c, s); break;
+        case 24: decide_bd<BD, First, 24>(a, A, c, s); break;
+        case 32: decide_bd<BD, First, 32>(a, A, c, s); break;
+        default: break;
+    }
 }
 
 void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
     if (a.decide_block == 512)
-        decide_bd<512, false>(a, nullptr, nullptr, s);
+        decide_kf<512, false>(a, nullptr, nullptr, s);
     else
-        decide_bd<256, false>(a, nullptr, nullptr, s);
+        decide_kf<256, false>(a, nullptr, nullptr, s);
 }
 
 void launch_first_decide(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
     if (a.decide_block == 512)
-        decide_bd<512, true>(a, A, c, s);
+        decide_kf<512, true>(a, A, c, s);
     else
-        decide_bd<256, true>(a, A, c, s);
+        decide_kf<256, true>(a, A, c, s);
 }
 
 namespace {
@@ -159,6 +184,8 @@ void launch_first_update(const FusedArgs &a, const double *A, const double *c, h
         case 8: first_kf<8>(a, A, c, s, e0, e1); break;
         case 12: first_kf<12>(a, A, c, s, e0, e1); break;
         case 16: first_kf<16>(a, A, c, s, e0, e1); break;
+        case 24: first_kf<24>(a, A, c, s, e0, e1); break;
+        case 32: first_kf<32>(a, A, c, s, e0, e1); break;
         default: break;
     }
 }

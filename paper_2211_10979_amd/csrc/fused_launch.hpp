@@ -38,8 +38,11 @@ struct FusedArgs {
     double *dump;       // a zero column the pure update pass writes for slots past the list
 };
 
-// Update instances exist for groups of up to 2, 4, 8, 12 and 16 pivots.
-inline int32_t fused_update_kf(int32_t K) { return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : 16; }
+// Update instances exist for groups of up to 2, 4, 8, 12, 16, 24 and 32
+// pivots (above 16 with the one-launch decision kernel only).
+inline int32_t fused_update_kf(int32_t K) {
+    return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : K <= 16 ? 16 : K <= 24 ? 24 : 32;
+}
 
 // The one-launch decision kernel: G workgroups of `block` threads, one row
 // and one list slot per thread; used when G <= kMaxDecideWgs.
@@ -58,8 +61,9 @@ inline int32_t select_workgroups_for(int32_t m) {
     return g < 1 ? 1 : (g > kMaxSelectWgs ? kMaxSelectWgs : g);
 }
 
-// True when an update kernel instance exists for this tile shape and group size.
-bool fused_update_supported(int block, int cols, int rv, int K);
+// True when an update kernel instance exists for this tile shape and group
+// size, with the one-launch decision kernel (the pure pass) or without.
+bool fused_update_supported(int block, int cols, int rv, int K, bool one_launch);
 
 // All decisions of a group in one launch (a.decide_wgs > 0).
 void launch_fused_decide(const FusedArgs &a, hipStream_t s);

@@ -46,7 +46,7 @@ struct UpdateConfig {
 // per workgroup below 4096 rows; with pivot fusion, kFusedCols columns (the
 // group's pivot columns are then loaded once per kFusedCols columns).
 constexpr int kFusedCols = 8;
-constexpr int kAutoFuse = 16;
+constexpr int kAutoFuse = 16;  // the group size when fuse_pivots is 0
 
 UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fused) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
@@ -89,7 +89,10 @@ struct lp_ctx {
     int32_t *cols = nullptr;  // rewrite list (n+2)
     int32_t *pos = nullptr;   // position of each nonbasic column in the list (n+m)
     double *Rl = nullptr;     // normalised pivot row by list position (n+2)
-    DevState *host_st = nullptr;  // pinned, two slots for the pipelined status read-back
+    DevState *host_st = nullptr;  // pinned: two slots for the pipelined status read-back, one for the end
+    unsigned long long *host_cols = nullptr;  // pinned: the work counters at the end of the last solve
+    double *host_out = nullptr;               // pinned: extraction output
+    bool counters_cached = false;             // host_st[2] and host_cols hold the device's current values
     double eps_d = 1e-9, eps_p = 1e-9;
     int64_t max_pivots = 0, log_cap = 0;
     int nparts = 0;
@@ -177,6 +180,8 @@ void free_ctx(lp_ctx *h) {
     if (h->gsync) (void)hipFree(h->gsync);
     if (h->dump) (void)hipFree(h->dump);
     if (h->host_st) (void)hipHostFree(h->host_st);
+    if (h->host_cols) (void)hipHostFree(h->host_cols);
+    if (h->host_out) (void)hipHostFree(h->host_out);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
     for (auto &e : h->ev_slot)
@@ -204,7 +209,7 @@ int validate_opts(const lp_options &o) {
         o.update_block != 512 && o.update_block != 1024)
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
-    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 16]");
+    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 32]");
     if (o.decide_kernel < 0 || o.decide_kernel > 1) return set_error(LP_E_INVAL, "decide_kernel must be 0 or 1");
     if (o.decide_spin < 0) return set_error(LP_E_INVAL, "decide_spin must be >= 0");
     if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
@@ -239,13 +244,22 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     // form that only the one-pivot kernels have.
     const bool one_pivot_form = o.update_grid_stride > 0 || o.update_hints != 0 || o.select_workgroups > 1 ||
                                 o.rows_per_thread > 1 || o.cols_per_block > 8 || o.update_block > 256;
-    h->fuse = o.fuse_pivots > 0 ? o.fuse_pivots : (one_pivot_form ? 1 : kAutoFuse);
-    h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, h->fuse > 1);
-    if (o.fuse_pivots == 0 && h->fuse > 1 &&
-        !fused_update_supported(h->ucfg.block, h->ucfg.cols, h->ucfg.rv, h->fuse)) {
+    // Groups above kMaxFuseSplit pivots need the one-launch decision kernel
+    // (at most kMaxDecideWgs workgroups over the rows and the list).
+    const int32_t dblock = o.decide_block > 0 ? o.decide_block : 256;
+    auto one_launch = [&](int K) {
+        return o.decide_kernel == 0 && decide_workgroups_for(m, (int64_t)n + 1 + K, dblock) <= kMaxDecideWgs;
+    };
+    if (o.fuse_pivots > 0) {
+        h->fuse = o.fuse_pivots;
+    } else {
         h->fuse = 1;
-        h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, false);
+        if (!one_pivot_form) {  // kAutoFuse where kernels exist for this shape
+            const UpdateConfig u = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, true);
+            if (fused_update_supported(u.block, u.cols, u.rv, kAutoFuse, one_launch(kAutoFuse))) h->fuse = kAutoFuse;
+        }
     }
+    h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, h->fuse > 1);
     if (h->ucfg.block == 256) h->ucfg.nt = o.update_hints & 3;
     if (o.update_grid_stride > 0) {  // grid-stride kernel: one column, one pair per thread per tile
         h->ucfg.cols = 1;
@@ -267,14 +281,20 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         return set_error(LP_E_INVAL, "update_block needs m + 1 > 256, and values other than 256 need "
                                      "cols_per_block and rows_per_thread <= 2");
     }
+    if (h->fuse > kMaxFuseSplit && !one_launch(h->fuse)) {
+        delete h;
+        return set_error(LP_E_INVAL, "fuse_pivots above 16 needs the one-launch decision kernel (decide_kernel 0 "
+                                     "and at most 128 decision workgroups)");
+    }
     if (h->fuse > 1) {
         const UpdateConfig &u = h->ucfg;
         if (u.gs_per_cu > 0 || u.nt != 0 || o.select_workgroups > 1 ||
-            !fused_update_supported(u.block, u.cols, u.rv, h->fuse)) {
+            !fused_update_supported(u.block, u.cols, u.rv, h->fuse, one_launch(h->fuse))) {
             delete h;
             return set_error(LP_E_INVAL, "fuse_pivots > 1 needs update_block <= 256, cols_per_block <= 8, "
                                          "rows_per_thread 1, update_hints 0, update_grid_stride 0 and "
-                                         "select_workgroups <= 1");
+                                         "select_workgroups <= 1; above 16 pivots, update_block 256 and "
+                                         "cols_per_block 2, 4 or 8");
         }
     }
     h->Lg = h->fuse > 1 ? (int64_t)n + 1 + h->fuse : (int64_t)n + 2;
@@ -340,7 +360,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     // the fused update reads the list and R of a whole slot group at once, so
     // both are padded past the last slot
-    if (int rc = dev_alloc((void **)&h->cols, ((size_t)h->Lg + 16) * sizeof(int32_t))) return fail(rc);
+    if (int rc = dev_alloc((void **)&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double))) return fail(rc);
     if (hipMemset(h->Rl, 0, ((size_t)kf * h->Lg + 16) * sizeof(double)) != hipSuccess)
@@ -363,7 +383,10 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
             return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     }
     {
-        hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&h->host_out, ((size_t)n + m + 1) * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
     }
     if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess ||
@@ -404,6 +427,7 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     const int32_t m = h->m, n = h->n;
     const int64_t ld = h->ld;
     defer = defer && !h->eager_build && h->fuse > 1 && h->decide_wgs > 0;
+    h->counters_cached = false;
     if (!defer) enqueue_full_build(h, dA, db, dc);
     h->pending = defer;
     h->first_ran = false;
@@ -424,7 +448,7 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.nparts = h->nparts;
     if (h->fuse > 1) {
         const int32_t kf = fused_update_kf(h->fuse);
-        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)kf * ld), h->Lg + 16);
+        const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)kf * ld), h->Lg + kMaxFuse);
         hipLaunchKernelGGL(k_ginit, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, h->stream, h->st, init,
                            h->gs, h->basis, m, n, (int32_t)h->fuse, kf, h->F, ld, h->cols, h->pos, h->cols_done,
                            h->T, defer ? db : nullptr);
@@ -662,6 +686,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     h->update_ms_applied = 0.0;
     h->applied_launches = 0;
     h->first_ms = 0.0;
+    h->counters_cached = false;
     // the first chunk is the first group of a deferred build when one is pending
     auto launch = [h](int sl) -> int {
         h->first_slot[sl] = h->pending;
@@ -692,9 +717,13 @@ int run_until(lp_ctx *h, int64_t stop_at) {
         slot = next;
     }
     LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
+    // the final state and the work counters, read back with the last sync
+    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[2], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    LP_HIP_CHECK(hipMemcpyAsync(h->host_cols, h->cols_done, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                h->stream));
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    DevState s;
-    LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    const DevState s = h->host_st[2];
+    h->counters_cached = true;
     if (int rc = harvest_timing(h, slot ^ 1, s.pivots - last)) return rc;  // the chunk queued last
     h->pivots_host = s.pivots;
     h->status_host = s.status;
@@ -806,16 +835,19 @@ int lp_get_solution(const lp_ctx *hc, lp_result *res, double *x, double *y) {
     if (!hc->ran) return set_error(LP_E_STATE, "no solve has run on this context");
     lp_ctx *h = const_cast<lp_ctx *>(hc);
     DeviceGuard g(h->device);
-    hipLaunchKernelGGL(k_extract, dim3(1), dim3(1024), 0, h->stream, h->T, h->ld, h->m, h->n, h->basis, h->out);
+    const int64_t ny = (int64_t)h->n + h->m + 1;
+    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
+                       h->n, h->out);
+    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
+                       h->n, (const int32_t *)h->basis, h->out);
     LP_HIP_CHECK(hipGetLastError());
-    std::vector<double> buf((size_t)h->n + h->m + 1);
-    LP_HIP_CHECK(hipMemcpyAsync(buf.data(), h->out, buf.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    DevState s;
+    const double *buf = h->host_out;
+    LP_HIP_CHECK(hipMemcpyAsync(h->host_out, h->out, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    s = h->host_st[0];
-    if (x) std::memcpy(x, buf.data(), (size_t)h->n * sizeof(double));
-    if (y) std::memcpy(y, buf.data() + h->n, (size_t)h->m * sizeof(double));
+    const DevState s = h->host_st[0];
+    if (x) std::memcpy(x, buf, (size_t)h->n * sizeof(double));
+    if (y) std::memcpy(y, buf + h->n, (size_t)h->m * sizeof(double));
     if (res) {
         res->status = s.status;
         res->reserved = 0;
@@ -892,9 +924,14 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t) {
     DeviceGuard g(h->device);
     unsigned long long cols[4] = {0, 0, 0, 0};
     DevState s;
-    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    LP_HIP_CHECK(hipMemcpy(cols, h->cols_done, sizeof(cols), hipMemcpyDeviceToHost));
-    LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (h->counters_cached) {  // nothing has run since the last solve read them back
+        std::memcpy(cols, h->host_cols, sizeof(cols));
+        s = h->host_st[2];
+    } else {
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        LP_HIP_CHECK(hipMemcpy(cols, h->cols_done, sizeof(cols), hipMemcpyDeviceToHost));
+        LP_HIP_CHECK(hipMemcpy(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost));
+    }
     t->solve_ms = h->last_ms;
     t->update_ms = h->update_ms;
     t->update_launches = h->update_launches;

@@ -548,26 +548,27 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
     }
 }
 
-// Finalization: x (n), y (m) and the objective into out[0 .. n+m]. y_i is
-// the row-0 entry of slack column n+i-1: read from the tableau when that
-// column is nonbasic, 0 when it is basic (a basic column is a unit vector
-// with 0 in row 0, and may not be stored: see k_store_basic). The y slots
-// first mark "nonbasic" (1), the basic slacks then clear theirs (0).
-static __global__ __launch_bounds__(1024) void k_extract(const double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
-                                                 const int32_t *__restrict__ basis, double *__restrict__ out) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t W = (int64_t)n + m + 1;
-    for (int32_t j = tid; j < n; j += nt) out[j] = 0.0;
-    for (int32_t i = tid; i < m; i += nt) out[n + i] = 1.0;
-    __syncthreads();
-    for (int32_t i = 1 + tid; i <= m; i += nt) {
-        const int32_t bv = basis[i - 1];
-        out[bv] = bv < n ? T[(W - 1) * ld + i] : 0.0;
-    }
-    __syncthreads();
-    for (int32_t i = tid; i < m; i += nt)
-        if (out[n + i] != 0.0) out[n + i] = T[((int64_t)n + i) * ld];
-    if (tid == 0) out[n + m] = T[(W - 1) * ld];
+// Finalization: x (n), y (m) and the objective into out[0 .. n+m], in two
+// launches of one thread per entry. First x = 0, y_i = the row-0 entry of
+// slack column n+i-1 (0 when that column is basic: row 0 of every slack
+// column is stored, also by a deferred build) and the objective; then x_j =
+// the RHS entry of the row in which structural column j is basic.
+static __global__ __launch_bounds__(256) void k_extract_y(const double *__restrict__ T, int64_t ld, int32_t m,
+                                                          int32_t n, double *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n)
+        out[idx] = 0.0;
+    else if (idx <= (int64_t)n + m)
+        out[idx] = T[idx * ld];  // column idx: slack idx - n, or the RHS (the objective)
+}
+
+static __global__ __launch_bounds__(256) void k_extract_x(const double *__restrict__ T, int64_t ld, int32_t m,
+                                                          int32_t n, const int32_t *__restrict__ basis,
+                                                          double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (i > m) return;
+    const int32_t bv = basis[i - 1];
+    if (bv < n) out[bv] = T[((int64_t)n + m) * ld + i];
 }
 
 // Stores every basic column as the unit vector it is: the basic column of

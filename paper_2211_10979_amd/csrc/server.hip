@@ -535,7 +535,10 @@ bool run_large(lp_server *s, int w, Request *r, const LargeLayout &L, char *bloc
         if (!ok || pin[slot].status != LP_RUNNING) break;
         slot ^= 1;
     }
-    hipLaunchKernelGGL(k_extract, dim3(1), dim3(1024), 0, st, d.T, ld, m, n, d.basis, d.out);
+    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)(((int64_t)n + m + 1 + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
+                       d.out);
+    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
+                       (const int32_t *)d.basis, d.out);
     std::vector<double> tmp((size_t)n + m + 1);
     DevState fin{};
     ok = ok && hipMemcpyAsync(tmp.data(), d.out, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st) ==

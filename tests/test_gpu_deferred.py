@@ -73,7 +73,7 @@ def compare_final(h, o):
     return orow.tolist(), ocol.tolist()
 
 
-@pytest.mark.parametrize("K", [2, 4, 11, 16])
+@pytest.mark.parametrize("K", [2, 4, 11, 16, 24, 32])
 def test_degenerate_battery_deferred(K):
     """120 small LPs of several shapes through one context each, reloaded;
     the battery has in-group re-entries, so slack columns are stored on
@@ -98,7 +98,7 @@ def test_degenerate_battery_deferred(K):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K", [7, 16])
+@pytest.mark.parametrize("K", [7, 16, 29])
 def test_stepping_after_reload(K):
     """A first lp_step of 0 pivots (the first pass only builds), then
     budgets that cut groups short; the tableau after every step."""
@@ -190,16 +190,17 @@ def test_timing_counters_and_eager_option():
             lpgpu.lp_solve(d.h)
             res, x, y = lpgpu.lp_get_solution(d.h)
             t = lpgpu.lp_get_timing(d.h)
+            K = lpgpu.lp_get_info(d.h).update_fuse
             out[eager] = (res, x, y, lpgpu.lp_get_tableau(d.h))
             if eager:
                 assert t["first_pass_ms"] == 0 and t["first_pass_pivots"] == 0 and t["first_pass_columns"] == 0
             else:
                 assert t["first_pass_ms"] > 0
-                assert t["first_pass_pivots"] == min(16, res["pivots"])
+                assert t["first_pass_pivots"] == min(K, res["pivots"])
                 assert 0 < t["first_pass_changed"] <= t["updated_columns"]
-                assert lp.n + 1 < t["first_pass_columns"] <= lp.n + 1 + 16
+                assert lp.n + 1 < t["first_pass_columns"] <= lp.n + 1 + K
             # the update launches timed are those after the first group
-            assert t["applied_launches"] == -(-(res["pivots"] - t["first_pass_pivots"]) // 16)
+            assert t["applied_launches"] == -(-(res["pivots"] - t["first_pass_pivots"]) // K)
         finally:
             d.close()
     (r0, x0, y0, T0), (r1, x1, y1, T1) = out[0], out[1]

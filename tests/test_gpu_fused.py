@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 
 lpgpu = pytest.importorskip("paper_2211_10979_amd.lpgpu")
 
+AUTO_FUSE = 16  # the library's group size when fuse_pivots is 0
+
 
 def say(*a):
     print(*a, flush=True)
@@ -87,7 +89,8 @@ def solve_and_compare(A, b, c, **opts):
         o.close()
 
 
-@pytest.mark.parametrize("K,decide", [(2, 0), (3, 0), (4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (4, 1), (16, 1)])
+@pytest.mark.parametrize("K,decide", [(2, 0), (3, 0), (4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (20, 0), (32, 0),
+                                     (4, 1), (16, 1)])
 def test_degenerate_battery(K, decide):
     """120 small LPs; the battery contains in-group re-entries of both kinds.
     decide = 0: all decisions of a group in one launch; 1: two launches per
@@ -103,7 +106,8 @@ def test_degenerate_battery(K, decide):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (7, 1), (16, 1)])
+@pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (24, 0), (31, 0), (7, 1),
+                                     (16, 1)])
 def test_group_boundaries_by_stepping(K, decide):
     """lp_step budgets that cut groups short and ones that span several
     groups: the tableau matches the oracle's after every step."""
@@ -133,7 +137,7 @@ def test_group_boundaries_by_stepping(K, decide):
         o.close()
 
 
-@pytest.mark.parametrize("K,decide", [(1, 0), (3, 0), (4, 0), (8, 0), (12, 0), (16, 0), (12, 1)])
+@pytest.mark.parametrize("K,decide", [(1, 0), (3, 0), (4, 0), (8, 0), (12, 0), (16, 0), (24, 0), (32, 0), (12, 1)])
 def test_dense_2000_full_solve(K, decide):
     lp = lpgen.workload("dense_2000x2000")
     say(f"fused K={K} decide_kernel={decide}: dense_2000x2000")
@@ -234,7 +238,8 @@ def test_work_counter_counts_the_union_of_a_group():
 def test_options_are_checked():
     lp = lpgen.dense_lp(2, 600, 200)  # m + 1 > 256: every update option applies
     A, b, c = lp.A, lp.b, lp.c
-    for bad in (dict(fuse_pivots=17), dict(fuse_pivots=-1), dict(fuse_pivots=4, cols_per_block=16),
+    for bad in (dict(fuse_pivots=33), dict(fuse_pivots=17, decide_kernel=1), dict(fuse_pivots=-1),
+                dict(fuse_pivots=4, cols_per_block=16), dict(fuse_pivots=24, cols_per_block=1),
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
                 dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1),
@@ -249,6 +254,11 @@ def test_options_are_checked():
     finally:
         lpgpu.lp_destroy(h)
     h = lpgpu.lp_create(A, b, c)
+    try:
+        assert lpgpu.lp_get_info(h).update_fuse == AUTO_FUSE
+    finally:
+        lpgpu.lp_destroy(h)
+    h = lpgpu.lp_create(A, b, c, decide_kernel=1)  # two launches per pivot: groups of at most 16
     try:
         assert lpgpu.lp_get_info(h).update_fuse == 16
     finally:
