@@ -701,7 +701,8 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
                                             int32_t *__restrict__ cols, int32_t *__restrict__ pos,
                                             int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
                                             int32_t *__restrict__ log_q, GRatio *__restrict__ rparts,
-                                            GridSync *__restrict__ gsync, uint32_t spin_limit) {
+                                            GridSync *__restrict__ gsync, uint32_t spin_limit,
+                                            double *__restrict__ PV) {
     // one set of reduction slots per call site (ratio test, staging, start)
     __shared__ double sv_r[BD / 64], sv_s[BD / 64], sv_0[BD / 64];
     __shared__ int32_t si_r[BD / 64], si_s[BD / 64], si_0[BD / 64];
@@ -1018,6 +1019,36 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
     }
 
+    // The pivot rows after the group, for every slot: the row of pivot a
+    // takes R_a[t] at pivot a (the select of the chain), then the later
+    // pivots' fma (or their R if the row pivots again): the operations of the
+    // chain in its order. k_gfix stores them after the update pass, which
+    // runs the chain without the select.
+    if (kd > 0) {
+        __shared__ double sM[KM][KM];  // sM[b][a] = F_b[r_a] for a < b < kd
+        for (int e = tid; e < KM * KM; e += BD) {
+            const int b = e / KM, a = e % KM;
+            int32_t ra = 0;
+#pragma unroll
+            for (int u = 0; u < KM; ++u)
+                if (u == a) ra = rk[u];
+            if (a < b && b < kd) sM[b][a] = Fk[(int64_t)b * ld + ra];
+        }
+        __syncthreads();
+        if (has_slot) {
+#pragma unroll
+            for (int a = 0; a < KM; ++a) {
+                if (a < kd) {
+                    double x = rslot[a];
+#pragma unroll
+                    for (int b = a + 1; b < KM; ++b)
+                        if (b < kd) x = (rk[a] == rk[b]) ? rslot[b] : fma(-sM[b][a], rslot[b], x);
+                    PV[(int64_t)a * Lg + t] = x;
+                }
+            }
+        }
+    }
+
     // The update pass applies KF pivots: the ones the group did not reach
     // become exact identities (F = 0, R = 0, no pivot row).
     for (int k = kd; k < KF; ++k) {
@@ -1050,9 +1081,9 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  int32_t *__restrict__ pos, int32_t *__restrict__ basis,
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
-                                                 uint32_t spin_limit) {
-    decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r, log_q, rparts, gsync,
-                spin_limit);
+                                                 uint32_t spin_limit, double *__restrict__ PV) {
+    decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r,
+                               log_q, rparts, gsync, spin_limit, PV);
     // every workgroup leaves through here; the last one resets the barrier
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1222,13 +1253,9 @@ __device__ __forceinline__ void pure_tile(double *__restrict__ T, int64_t ld, in
     const int32_t i0 = 2 * v;
     const int64_t ldv = ld / 2;
     const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
-    int32_t rk[KF];
     double2 f[KF];
 #pragma unroll
-    for (int k = 0; k < KF; ++k) {
-        rk[k] = gs->r[k];
-        f[k] = F2[k * ldv + vs];
-    }
+    for (int k = 0; k < KF; ++k) f[k] = F2[k * ldv + vs];
     double2 *p[C];
     double2 x[C];
 #pragma unroll
@@ -1243,13 +1270,15 @@ __device__ __forceinline__ void pure_tile(double *__restrict__ T, int64_t ld, in
         sR[c][k] = c0 + c < Lv ? Rk[(int64_t)k * Lg + c0 + c] : 0.0;
     }
     __syncthreads();
+    // the chain without the pivot-row select: k_gfix then stores the pivot
+    // rows (their values after the group, from the decision kernel)
 #pragma unroll
     for (int k = 0; k < KF; ++k)
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const double R = sR[c][k];
-            x[c].x = (i0 == rk[k]) ? R : fma(-f[k].x, R, x[c].x);
-            x[c].y = (i0 + 1 == rk[k]) ? R : fma(-f[k].y, R, x[c].y);
+            x[c].x = fma(-f[k].x, R, x[c].x);
+            x[c].y = fma(-f[k].y, R, x[c].y);
         }
     if (live) {
 #pragma unroll
@@ -1261,12 +1290,13 @@ template <int B, int C, int KF>
 __global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
                                                     int64_t Lg, int32_t rowchunks, const int32_t *__restrict__ cols,
                                                     const double *__restrict__ Rk, const double *__restrict__ Fk,
-                                                    const GroupState *__restrict__ gs, double *__restrict__ dump) {
+                                                    const GroupState *__restrict__ gs, double *__restrict__ dump,
+                                                    int32_t slot0) {
     if (gs->kdone == 0) return;
     const int32_t Lv = n + 1 + gs->napp;
     const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
     const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
-    const int32_t c0 = g * C;
+    const int32_t c0 = slot0 + g * C;  // slots from slot0 on
     if (c0 >= Lv) return;
     pure_tile<B, C, KF>(T, ld, m, Lg, Lv, rc, c0, cols, Rk, Fk, gs, dump);
 }
@@ -1277,39 +1307,26 @@ __global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int6
 // -c) is read row-major, transposed through LDS and written to the tableau
 // after the group's KF pivots are applied to it, with the same chain as the
 // pure pass applies to a built column (the same operations in the same order
-// on the same start value, hence the same bits; a tile that holds no pivot
-// row skips the pivot-row select, which would pick the fma result in every
-// row). A group of no pivots writes the tile as the plain build does.
-// Workgroups past the tiles run the pure pass over slots n.. (the right-hand
-// side, built by k_ginit, and the columns appended during the group, which
-// the decision kernel stored as unit vectors when they left the basis).
+// on the same start value, hence the same bits; like the pure pass it runs
+// the chain without the pivot-row select, and k_gfix stores the pivot rows).
+// A group of no pivots writes the tile as the plain build does. The pure
+// pass takes the slots from n on (the right-hand side, built by k_ginit, and
+// the columns appended during the group, which the decision kernel stored as
+// unit vectors when they left the basis).
 constexpr int kFirstRows = 32;  // tile rows (tableau rows)
 constexpr int kFirstTile = 64;  // tile columns
-constexpr int kFirstCols = 8;   // list slots per workgroup of the pure part
 
 template <int KF>
 __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t ld, int32_t m, int32_t n, int64_t Lg,
-                                                int32_t ntx, int32_t ntiles, int32_t rowchunks,
-                                                const double *__restrict__ A, const double *__restrict__ cv,
-                                                const int32_t *__restrict__ cols, const double *__restrict__ Rk,
-                                                const double *__restrict__ Fk, const GroupState *__restrict__ gs,
-                                                double *__restrict__ dump) {
+                                                int32_t ntx, const double *__restrict__ A, const double *__restrict__ cv,
+                                                const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                                const GroupState *__restrict__ gs) {
     constexpr int TR = kFirstRows, TC = kFirstTile;
     constexpr int NP = TR / 2;          // row pairs of a tile
     constexpr int CG = 256 / NP;        // column groups of the write phase
     constexpr int NR = (KF * TC + 255) / 256;  // R entries per thread to stage
     constexpr int NF = (KF * NP + 255) / 256;  // F pairs per thread to stage
     const int32_t kd = gs->kdone;
-    if ((int32_t)blockIdx.x >= ntiles) {
-        if (kd == 0) return;
-        const int32_t b = (int32_t)blockIdx.x - ntiles;
-        const int32_t rc = b % rowchunks;
-        const int32_t c0 = n + (b / rowchunks) * kFirstCols;
-        const int32_t Lv = n + 1 + gs->napp;
-        if (c0 >= Lv) return;
-        pure_tile<256, kFirstCols, KF>(T, ld, m, Lg, Lv, rc, c0, cols, Rk, Fk, gs, dump);
-        return;
-    }
     __shared__ double tile[TR][TC + 1];
     __shared__ double sR[KF][TC];
     __shared__ double2 sF[KF][NP];
@@ -1334,8 +1351,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
             fv[u] = t < KF * NP && i0 + 2 * v < ld ? F2[k * ldv + i0 / 2 + v] : double2{0.0, 0.0};
         }
     }
-    // the tile of A: 16-byte loads need an even n and a 16-byte aligned A
-    {
+    {  // the tile of A: 16-byte loads need an even n and a 16-byte aligned A
         const int pr = tid & 31, rw = tid >> 5;  // column pair, row group
         const bool vec_a = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
         double2 va[TR / 8];
@@ -1390,18 +1406,12 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
         }
         return;
     }
-    int32_t rk[KF];
-    bool sel = false;  // the tile holds a pivot row (uniform)
-#pragma unroll
-    for (int k = 0; k < KF; ++k) {
-        rk[k] = gs->r[k];
-        sel |= rk[k] >= i0 && rk[k] < i0 + TR;
-    }
-    double2 f[KF];
-#pragma unroll
-    for (int k = 0; k < KF; ++k) f[k] = sF[k][p];
-    if (sel) {
-#pragma unroll
+    // the chain without the pivot-row select: k_gfix then stores the pivot
+    // rows (their values after the group, from the decision kernel)
+    if constexpr (KF >= 24) {
+        // F read from LDS in the chain (one column at a time), not held in
+        // 4 KF registers: the occupancy of the smaller groups
+#pragma unroll 1
         for (int u = 0; u < TC / CG; ++u) {
             const int cl = cg + CG * u;
             const int64_t j = j0 + cl;
@@ -1409,12 +1419,16 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
 #pragma unroll
             for (int k = 0; k < KF; ++k) {
                 const double R = sR[k][cl];
-                x.x = (iw == rk[k]) ? R : fma(-f[k].x, R, x.x);
-                x.y = (iw + 1 == rk[k]) ? R : fma(-f[k].y, R, x.y);
+                const double2 f = sF[k][p];
+                x.x = fma(-f.x, R, x.x);
+                x.y = fma(-f.y, R, x.y);
             }
             if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
         }
-    } else {  // the same chain: no row of the tile is a pivot row
+    } else {
+        double2 f[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) f[k] = sF[k][p];
 #pragma unroll
         for (int u = 0; u < TC / CG; ++u) {
             const int cl = cg + CG * u;
@@ -1429,6 +1443,21 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
             if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
         }
     }
+}
+
+// The pivot rows of the group's list columns after its update pass: row
+// r_a of the column in slot t takes PV[a][t], its value after the group that
+// the decision kernel computed (the pass applied the chain without the
+// pivot-row select, which only these rows need). A row that pivots twice gets
+// the same value from both entries.
+static __global__ __launch_bounds__(256) void k_gfix(double *__restrict__ T, int64_t ld, int32_t n, int64_t Lg,
+                                                     const int32_t *__restrict__ cols, const double *__restrict__ PV,
+                                                     const GroupState *__restrict__ gs) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t a = (int32_t)(idx / Lg), t = (int32_t)(idx % Lg);
+    if (a >= gs->kdone || t > n + gs->napp) return;
+    const int32_t c = cols[t];
+    if (c >= 0) T[(int64_t)c * ld + gs->r[a]] = PV[idx];
 }
 
 }  // namespace lpgpu

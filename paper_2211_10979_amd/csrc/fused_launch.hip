@@ -43,11 +43,11 @@ void update_pure(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hip
     if (e0)
         hipExtLaunchKernelGGL((k_gupdate_pure<B, C, KF>), dim3(grid), dim3(B), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n,
                               Lg, rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
-                              (const GroupState *)a.gs, a.dump);
+                              (const GroupState *)a.gs, a.dump, 0);
     else
         hipLaunchKernelGGL((k_gupdate_pure<B, C, KF>), dim3(grid), dim3(B), 0, s, a.T, a.ld, a.m, a.n, Lg, rowchunks,
                            (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
-                           (const GroupState *)a.gs, a.dump);
+                           (const GroupState *)a.gs, a.dump, 0);
 }
 
 using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
@@ -121,7 +121,7 @@ template <int BD, bool First, int KM>
 void decide_bd(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
     hipLaunchKernelGGL((k_gdecide<BD, First, KM>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n,
                        A, c, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis,
-                       a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin);
+                       a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin, a.PV);
 }
 
 // the instance for the group size (its KF pivot slots kept in registers)
@@ -160,18 +160,24 @@ void first_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t 
     const int64_t Lg = (int64_t)a.n + 1 + a.K;
     const int32_t ntx = (a.n + kFirstTile - 1) / kFirstTile;
     const int32_t nty = (int32_t)((a.ld + kFirstRows - 1) / kFirstRows);
-    const int32_t ntiles = ntx * nty;
+    const unsigned tiles = (unsigned)((int64_t)ntx * nty);
+    // the tiles of the structural columns, then the pure pass over slots n ..
+    // n+K (the RHS and the appended columns): 256 threads by 8 slots
     const int32_t rowchunks = (int32_t)((((int64_t)a.m + 2) / 2 + 255) / 256);  // row pairs
-    const int32_t slot_groups = (1 + a.K + kFirstCols - 1) / kFirstCols;      // slots n .. n+K
-    const unsigned grid = (unsigned)((int64_t)ntiles + (int64_t)rowchunks * slot_groups);
-    if (e0)
-        hipExtLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg, ntx,
-                              ntiles, rowchunks, A, c, (const int32_t *)a.cols, (const double *)a.Rk,
-                              (const double *)a.Fk, (const GroupState *)a.gs, a.dump);
-    else
-        hipLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, ntx, ntiles, rowchunks,
-                           A, c, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
-                           (const GroupState *)a.gs, a.dump);
+    const unsigned pure = (unsigned)((int64_t)rowchunks * ((1 + a.K + 7) / 8));
+    if (e0) {
+        hipExtLaunchKernelGGL((k_gfirst<KF>), dim3(tiles), dim3(256), 0, s, e0, nullptr, 0, a.T, a.ld, a.m, a.n, Lg,
+                              ntx, A, c, (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
+        hipExtLaunchKernelGGL((k_gupdate_pure<256, 8, KF>), dim3(pure), dim3(256), 0, s, nullptr, e1, 0, a.T, a.ld,
+                              a.m, a.n, Lg, rowchunks, (const int32_t *)a.cols, (const double *)a.Rk,
+                              (const double *)a.Fk, (const GroupState *)a.gs, a.dump, a.n);
+    } else {
+        hipLaunchKernelGGL((k_gfirst<KF>), dim3(tiles), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, ntx, A, c,
+                           (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
+        hipLaunchKernelGGL((k_gupdate_pure<256, 8, KF>), dim3(pure), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg,
+                           rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, a.dump, a.n);
+    }
 }
 
 }  // namespace
@@ -188,6 +194,7 @@ void launch_first_update(const FusedArgs &a, const double *A, const double *c, h
         case 32: first_kf<32>(a, A, c, s, e0, e1); break;
         default: break;
     }
+    launch_fix(a, s);
 }
 
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s) {
@@ -239,9 +246,17 @@ void launch_fused_update(const FusedArgs &a, int block, int cols, int rv, hipStr
     const unsigned grid = (unsigned)((int64_t)a.rowchunks * a.nparts);
     if (a.decide_wgs > 0) {
         if (UpdateFn f = find_update_pure(block, cols, rv, a.K)) f(a, grid, s, e0, e1);
+        launch_fix(a, s);
     } else if (UpdateFn f = find_update(block, cols, rv, a.K)) {
         f(a, grid, s, e0, e1);
     }
+}
+
+void launch_fix(const FusedArgs &a, hipStream_t s) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int64_t total = (int64_t)a.K * Lg;
+    hipLaunchKernelGGL(k_gfix, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.T, a.ld, a.n, Lg,
+                       (const int32_t *)a.cols, (const double *)a.PV, (const GroupState *)a.gs);
 }
 
 }  // namespace lpgpu

@@ -36,6 +36,7 @@ struct FusedArgs {
     GridSync *gsync;     // its barrier counters, zero between launches
     uint32_t decide_spin;
     double *dump;       // a zero column the pure update pass writes for slots past the list
+    double *PV;         // the group's pivot rows after the group, K rows of n + 1 + K doubles
 };
 
 // Update instances exist for groups of up to 2, 4, 8, 12, 16, 24 and 32
@@ -78,6 +79,9 @@ void launch_first_update(const FusedArgs &a, const double *A, const double *c, h
 // Steps 1-2 (select) and the Step 3 inputs (stage) of pivot j of a group.
 void launch_fused_select(const FusedArgs &a, int j, hipStream_t s);
 void launch_fused_stage(const FusedArgs &a, int j, hipStream_t s);
+
+// The pivot rows after the pure pass (k_gfix; the pure passes launch it).
+void launch_fix(const FusedArgs &a, hipStream_t s);
 
 // The group's update pass; with events, timed by the dispatch.
 void launch_fused_update(const FusedArgs &a, int block, int cols, int rv, hipStream_t s, hipEvent_t e0,

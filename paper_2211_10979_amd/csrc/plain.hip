@@ -46,7 +46,7 @@ struct UpdateConfig {
 // per workgroup below 4096 rows; with pivot fusion, kFusedCols columns (the
 // group's pivot columns are then loaded once per kFusedCols columns).
 constexpr int kFusedCols = 8;
-constexpr int kAutoFuse = 16;  // the group size when fuse_pivots is 0
+constexpr int kAutoFuse = 24;  // the group size when fuse_pivots is 0 (kMaxFuseSplit where 24 has no kernels)
 
 UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fused) {
     const int64_t nvec = ((int64_t)m + 2) / 2;
@@ -108,6 +108,7 @@ struct lp_ctx {
     GroupState *gs = nullptr;                 // K > 1: decisions of the current group
     double *D = nullptr;                      // K > 1: row-0 entry of every slot during a group
     double *dump = nullptr;                   // K > 1: zero column written for slots past the list
+    double *PV = nullptr;                     // K > 1: pivot rows after the group (one-launch decisions)
     SPart *sparts = nullptr;                  // K > 1: Step 1 partials of the staging kernel
     GRatio *grparts = nullptr;                // K > 1: Step 2 partials of the select workgroups
     GridSync *gsync = nullptr;                // K > 1: barrier counters of the decision kernel
@@ -173,6 +174,7 @@ void free_ctx(lp_ctx *h) {
     if (h->cols) (void)hipFree(h->cols);
     if (h->pos) (void)hipFree(h->pos);
     if (h->Rl) (void)hipFree(h->Rl);
+    if (h->PV) (void)hipFree(h->PV);
     if (h->gs) (void)hipFree(h->gs);
     if (h->D) (void)hipFree(h->D);
     if (h->sparts) (void)hipFree(h->sparts);
@@ -254,9 +256,15 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         h->fuse = o.fuse_pivots;
     } else {
         h->fuse = 1;
-        if (!one_pivot_form) {  // kAutoFuse where kernels exist for this shape
+        if (!one_pivot_form) {  // kAutoFuse, else kMaxFuseSplit, where kernels exist for this shape
             const UpdateConfig u = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, true);
-            if (fused_update_supported(u.block, u.cols, u.rv, kAutoFuse, one_launch(kAutoFuse))) h->fuse = kAutoFuse;
+            for (int K : {kAutoFuse, kMaxFuseSplit}) {
+                if ((K <= kMaxFuseSplit || one_launch(K)) &&
+                    fused_update_supported(u.block, u.cols, u.rv, K, one_launch(K))) {
+                    h->fuse = K;
+                    break;
+                }
+            }
         }
     }
     h->ucfg = pick_update_config(m, o.cols_per_block, o.rows_per_thread, o.update_block, h->fuse > 1);
@@ -377,6 +385,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->grparts, kMaxDecideWgs * sizeof(GRatio))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->gsync, sizeof(GridSync))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->dump, (size_t)h->ld * sizeof(double))) return fail(rc);
+        if (int rc = dev_alloc((void **)&h->PV, (size_t)fused_update_kf(h->fuse) * h->Lg * sizeof(double)))
+            return fail(rc);
         if (hipMemset(h->dump, 0, (size_t)h->ld * sizeof(double)) != hipSuccess)
             return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
         if (hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess)
@@ -535,6 +545,7 @@ FusedArgs fused_args(lp_ctx *h) {
     a.K = h->fuse;
     a.KF = fused_update_kf(h->fuse);
     a.dump = h->dump;
+    a.PV = h->PV;
     a.rowchunks = (int32_t)(((int64_t)h->m + h->ucfg.block) / h->ucfg.block);  // one row per thread
     a.nsparts = h->nsparts;
     a.nparts = h->nparts;

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 lpgpu = pytest.importorskip("paper_2211_10979_amd.lpgpu")
 
-AUTO_FUSE = 16  # the library's group size when fuse_pivots is 0
+AUTO_FUSE = 24  # the library's group size when fuse_pivots is 0
 
 
 def say(*a):
