@@ -1026,26 +1026,29 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     // runs the chain without the select.
     if (kd > 0) {
         __shared__ double sM[KM][KM];  // sM[b][a] = F_b[r_a] for a < b < kd
-        for (int e = tid; e < KM * KM; e += BD) {
-            const int b = e / KM, a = e % KM;
-            int32_t ra = 0;
+        // thread b < kd loads F_b at the earlier pivot rows (one batch)
 #pragma unroll
-            for (int u = 0; u < KM; ++u)
-                if (u == a) ra = rk[u];
-            if (a < b && b < kd) sM[b][a] = Fk[(int64_t)b * ld + ra];
-        }
+        for (int a = 0; a < KM; ++a)
+            if (tid > a && tid < kd) sM[tid][a] = Fk[(int64_t)tid * ld + rk[a]];
         __syncthreads();
         if (has_slot) {
+            // every earlier pivot row updated by pivot b, b in order: for each
+            // row the operations of its chain in its order, and b independent
+            // updates per step
+            double pv[KM];
 #pragma unroll
-            for (int a = 0; a < KM; ++a) {
-                if (a < kd) {
-                    double x = rslot[a];
+            for (int a = 0; a < KM; ++a) pv[a] = rslot[a];
 #pragma unroll
-                    for (int b = a + 1; b < KM; ++b)
-                        if (b < kd) x = (rk[a] == rk[b]) ? rslot[b] : fma(-sM[b][a], rslot[b], x);
-                    PV[(int64_t)a * Lg + t] = x;
+            for (int b = 1; b < KM; ++b) {
+                if (b < kd) {
+#pragma unroll
+                    for (int a = 0; a < b; ++a)
+                        pv[a] = (rk[a] == rk[b]) ? rslot[b] : fma(-sM[b][a], rslot[b], pv[a]);
                 }
             }
+#pragma unroll
+            for (int a = 0; a < KM; ++a)
+                if (a < kd) PV[(int64_t)a * Lg + t] = pv[a];
         }
     }
 
