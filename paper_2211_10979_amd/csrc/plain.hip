@@ -93,6 +93,7 @@ struct lp_ctx {
     unsigned long long *host_cols = nullptr;  // pinned: the work counters at the end of the last solve
     double *host_out = nullptr;               // pinned: extraction output
     bool counters_cached = false;             // host_st[2] and host_cols hold the device's current values
+    bool solution_cached = false;             // host_out holds the extraction of the current tableau
     double eps_d = 1e-9, eps_p = 1e-9;
     int64_t max_pivots = 0, log_cap = 0;
     int nparts = 0;
@@ -438,6 +439,7 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     const int64_t ld = h->ld;
     defer = defer && !h->eager_build && h->fuse > 1 && h->decide_wgs > 0;
     h->counters_cached = false;
+    h->solution_cached = false;
     if (!defer) enqueue_full_build(h, dA, db, dc);
     h->pending = defer;
     h->first_ran = false;
@@ -687,6 +689,19 @@ int harvest_timing(lp_ctx *h, int slot, int64_t advanced) {
     return LP_OK;
 }
 
+// Finalization into pinned host memory: x, y and the objective (k_extract_y,
+// k_extract_x), copied on the stream.
+int enqueue_extract(lp_ctx *h) {
+    const int64_t ny = (int64_t)h->n + h->m + 1;
+    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
+                       h->n, h->out);
+    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
+                       h->n, (const int32_t *)h->basis, h->out);
+    LP_HIP_CHECK(hipGetLastError());
+    LP_HIP_CHECK(hipMemcpyAsync(h->host_out, h->out, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return LP_OK;
+}
+
 // Runs pivots until the status leaves RUNNING or `stop_at` pivots are done.
 // Chunks are pipelined two deep: chunk k+1 is queued before the status of
 // chunk k is read back, so the device never waits for the host.
@@ -698,6 +713,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     h->applied_launches = 0;
     h->first_ms = 0.0;
     h->counters_cached = false;
+    h->solution_cached = false;
     // the first chunk is the first group of a deferred build when one is pending
     auto launch = [h](int sl) -> int {
         h->first_slot[sl] = h->pending;
@@ -728,13 +744,16 @@ int run_until(lp_ctx *h, int64_t stop_at) {
         slot = next;
     }
     LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
-    // the final state and the work counters, read back with the last sync
+    // the solution, the final state and the work counters, read back with
+    // the last sync
+    if (int rc = enqueue_extract(h)) return rc;
     LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[2], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipMemcpyAsync(h->host_cols, h->cols_done, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 h->stream));
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
     const DevState s = h->host_st[2];
     h->counters_cached = true;
+    h->solution_cached = true;
     if (int rc = harvest_timing(h, slot ^ 1, s.pivots - last)) return rc;  // the chunk queued last
     h->pivots_host = s.pivots;
     h->status_host = s.status;
@@ -846,17 +865,16 @@ int lp_get_solution(const lp_ctx *hc, lp_result *res, double *x, double *y) {
     if (!hc->ran) return set_error(LP_E_STATE, "no solve has run on this context");
     lp_ctx *h = const_cast<lp_ctx *>(hc);
     DeviceGuard g(h->device);
-    const int64_t ny = (int64_t)h->n + h->m + 1;
-    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
-                       h->n, h->out);
-    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
-                       h->n, (const int32_t *)h->basis, h->out);
-    LP_HIP_CHECK(hipGetLastError());
     const double *buf = h->host_out;
-    LP_HIP_CHECK(hipMemcpyAsync(h->host_out, h->out, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
-    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    const DevState s = h->host_st[0];
+    DevState s;
+    if (h->solution_cached) {  // extracted at the end of the last solve, nothing has run since
+        s = h->host_st[2];
+    } else {
+        if (int rc = enqueue_extract(h)) return rc;
+        LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        s = h->host_st[0];
+    }
     if (x) std::memcpy(x, buf, (size_t)h->n * sizeof(double));
     if (y) std::memcpy(y, buf + h->n, (size_t)h->m * sizeof(double));
     if (res) {
