@@ -1411,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
     }
     // the chain without the pivot-row select: k_gfix then stores the pivot
     // rows (their values after the group, from the decision kernel)
-    if constexpr (KF >= 24) {
+    if constexpr (KF >= 32) {
         // F read from LDS in the chain (one column at a time), not held in
         // 4 KF registers: the occupancy of the smaller groups
 #pragma unroll 1
