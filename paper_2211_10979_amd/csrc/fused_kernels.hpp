@@ -188,6 +188,7 @@ struct GRatio {
     double p;
     int32_t leave;
     int32_t lpos;
+    double rb;  // k_gdecide: the RHS entry of row r after the earlier pivots of the group
 };
 
 // Lexicographic argmin that carries an int payload along with the winner.
@@ -801,6 +802,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     const double rhs0 = T[(W - 1) * ld + is];
     int32_t basis_i = (has_row && i >= 1) ? basis[i - 1] : -1;
     bool inlist_i = false;
+    double bcur = rhs0;  // this row's RHS entry after the pivots decided so far
     double D_t = c_t >= 0 ? start_entry<First>(T, ld, n, A, cv, c_t, 0) : 0.0;
     if (s0.fresh) {
         // Step 1 partials of the first pivot after the build (later groups
@@ -866,23 +868,19 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // earlier pivots; the row's entry of column q is kept as F_j[i]. The
         // coefficients of all KM steps are loaded in one batch (index
         // clamped into the buffer) and the steps k >= j are masked out by
-        // selects, so that no load waits behind another.
+        // selects, so that no load waits behind another. The RHS entry is
+        // carried from pivot to pivot (bcur) with the same operations.
         const int32_t tqs = tq < 0 ? 0 : tq;
-        double Rq[KM], Rb[KM];
+        double Rq[KM];
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int64_t kk = k < K ? k : K - 1;
-            Rq[k] = Rk[kk * Lg + tqs];
-            Rb[k] = Rk[kk * Lg + n];
-        }
-        double a = start_entry<First>(T, ld, n, A, cv, q, is), bb = rhs0;
+        for (int k = 0; k < KM; ++k) Rq[k] = Rk[(int64_t)(k < K ? k : K - 1) * Lg + tqs];
+        double a = start_entry<First>(T, ld, n, A, cv, q, is);
+        const double bb = bcur;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const bool on = k < j, piv = i == rk[k];
             const double na = piv ? Rq[k] : fma(-frow[k], Rq[k], a);
-            const double nb = piv ? Rb[k] : fma(-frow[k], Rb[k], bb);
             a = on ? na : a;
-            bb = on ? nb : bb;
         }
 #pragma unroll
         for (int k = 0; k < KM; ++k)
@@ -910,9 +908,9 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // row r (by thread 0 when no row qualifies); lpos carries "the
         // leaving column has a slot" here
         if (r != kNoIndex && r_mine == r)
-            rparts[w] = GRatio{rv, r, rv != rv, a, basis_i, (int32_t)inlist_i};
+            rparts[w] = GRatio{rv, r, rv != rv, a, basis_i, (int32_t)inlist_i, bb};
         else if (r == kNoIndex && tid == 0)
-            rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0};
+            rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0, 0.0};
         if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
         if (j == 0 && w == 0) {  // every workgroup has read the list
             if (tid < 64) store_close();
@@ -922,10 +920,10 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // the decision, reduced by every workgroup from all Step 2 partials
         // (every wave reduces all G partials itself; the winner's payload
         // is read from the lane that holds it)
-        double p;
+        double p, rb;
         int32_t leave, inl;
         {
-            const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0};
+            const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0, 0.0};
             GRatio pa = lane < G ? rparts[lane] : none;
             const GRatio pb = lane + 64 < G ? rparts[lane + 64] : none;
             if (lex_less(pb.v, pb.r, pa.v, pa.r)) pa = pb;
@@ -934,6 +932,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             int32_t wl = lane;
             wave_argmin_dpp(rv, r, wl);
             p = readlane_f64(pa.p, wl);
+            rb = readlane_f64(pa.rb, wl);
             leave = __builtin_amdgcn_readlane(pa.leave, wl);
             inl = __builtin_amdgcn_readlane(pa.lpos, wl);
         }
@@ -966,6 +965,12 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             st->fresh = 0;
         }
         kd = j + 1;
+        {
+            // the RHS after pivot j: R_j of the RHS slot is its row-r entry
+            // over p, the value the slot's own staging computes
+            const double Rn = rb / p;
+            bcur = (i == r) ? Rn : fma(-a, Rn, bcur);
+        }
 #pragma unroll
         for (int k = 0; k < KM; ++k)
             if (k == j) rk[k] = r;
