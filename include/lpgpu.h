@@ -110,7 +110,8 @@ typedef struct {
                                update_block 0 or <= 256, cols_per_block <= 8,
                                rows_per_thread 0 or 1, update_hints 0, update_grid_stride 0 and
                                select_workgroups <= 1; K > 16 also needs the one-launch
-                               decision kernel and cols_per_block 0, 4 or 8. */
+                               decision kernel with decide_block 0 or 256, and cols_per_block 0,
+                               4 or 8. */
     int32_t decide_kernel;  /* K > 1: 0 = auto (one launch for all decisions of a group when
                                G = max(m + 1, n + 1 + K) / decide_block rounded up is at most
                                128 workgroups, else two launches per pivot); 1 = two launches
@@ -118,7 +119,7 @@ typedef struct {
     int32_t decide_spin;    /* polls before a grid-barrier wait of the decision kernel gives up
                                with LP_STALLED (0 = default, about 0.2 s) */
     int32_t decide_block;   /* threads per workgroup of the decision kernel (256 or 512; 0 = auto:
-                               256) */
+                               256); 512 holds groups of at most 16 pivots */
     int32_t eager_build;    /* 0 = auto: with the one-launch decision kernel, lp_reload_device
                                defers the build of the structural columns to the first update
                                pass (which reads A and c instead of the tableau) and leaves the

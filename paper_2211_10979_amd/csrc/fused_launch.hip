@@ -133,9 +133,14 @@ void decide_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t
         case 8: decide_bd<BD, First, 8>(a, A, c, s); break;
         case 12: decide_bd<BD, First, 12>(a, A, c, s); break;
         case 16: decide_bd<BD, First, 16>(a, A, c, s); break;
-        case 24: decide_bd<BD, First, 24>(a, A, c, s); break;
-        case 32: decide_bd<BD, First, 32>(a, A, c, s); break;
         default: break;
+    }
+    if constexpr (BD == 256) {  // larger groups: 256 threads per workgroup only (the host checks)
+        switch (a.KF) {
+            case 24: decide_bd<BD, First, 24>(a, A, c, s); break;
+            case 32: decide_bd<BD, First, 32>(a, A, c, s); break;
+            default: break;
+        }
     }
 }
 

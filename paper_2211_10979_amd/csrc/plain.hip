@@ -250,8 +250,9 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     // Groups above kMaxFuseSplit pivots need the one-launch decision kernel
     // (at most kMaxDecideWgs workgroups over the rows and the list).
     const int32_t dblock = o.decide_block > 0 ? o.decide_block : 256;
-    auto one_launch = [&](int K) {
-        return o.decide_kernel == 0 && decide_workgroups_for(m, (int64_t)n + 1 + K, dblock) <= kMaxDecideWgs;
+    auto one_launch = [&](int K) {  // (512-thread decision workgroups hold groups of at most 16)
+        return o.decide_kernel == 0 && decide_workgroups_for(m, (int64_t)n + 1 + K, dblock) <= kMaxDecideWgs &&
+               (dblock == 256 || K <= kMaxFuseSplit);
     };
     if (o.fuse_pivots > 0) {
         h->fuse = o.fuse_pivots;
@@ -292,8 +293,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     }
     if (h->fuse > kMaxFuseSplit && !one_launch(h->fuse)) {
         delete h;
-        return set_error(LP_E_INVAL, "fuse_pivots above 16 needs the one-launch decision kernel (decide_kernel 0 "
-                                     "and at most 128 decision workgroups)");
+        return set_error(LP_E_INVAL, "fuse_pivots above 16 needs the one-launch decision kernel (decide_kernel 0, "
+                                     "decide_block 256 and at most 128 decision workgroups)");
     }
     if (h->fuse > 1) {
         const UpdateConfig &u = h->ucfg;

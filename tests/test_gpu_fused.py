@@ -243,7 +243,8 @@ def test_options_are_checked():
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
                 dict(fuse_pivots=3, update_grid_stride=2), dict(fuse_pivots=2, update_hints=1),
-                dict(decide_kernel=2), dict(decide_kernel=-1), dict(decide_spin=-5), dict(decide_block=128)):
+                dict(decide_kernel=2), dict(decide_kernel=-1), dict(decide_spin=-5), dict(decide_block=128),
+                dict(fuse_pivots=24, decide_block=512)):
         with pytest.raises(lpgpu.LPError) as e:
             lpgpu.lp_create(A, b, c, **bad)
         assert e.value.code == lpgpu.LP_E_INVAL
@@ -259,6 +260,11 @@ def test_options_are_checked():
     finally:
         lpgpu.lp_destroy(h)
     h = lpgpu.lp_create(A, b, c, decide_kernel=1)  # two launches per pivot: groups of at most 16
+    try:
+        assert lpgpu.lp_get_info(h).update_fuse == 16
+    finally:
+        lpgpu.lp_destroy(h)
+    h = lpgpu.lp_create(A, b, c, decide_block=512)  # 512-thread decision workgroups: at most 16
     try:
         assert lpgpu.lp_get_info(h).update_fuse == 16
     finally:
