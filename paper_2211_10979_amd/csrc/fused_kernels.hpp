@@ -680,6 +680,29 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
     return *s_ok != 0;
 }
 
+// Steps k < j of a chain (rows: x <- R_k if the row is r_k, else
+// fma(-F_k, R_k, x)), unrolled over the first N of the KM entries (N >= j;
+// the steps k >= j are masked out). Tiers of N keep the work near j.
+template <int N, int KM>
+__device__ __forceinline__ double chain_steps(double x, int j, int32_t row, const int32_t (&rk)[KM],
+                                              const double (&F)[KM], const double (&R)[KM]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double nx = (row == rk[k]) ? R[k] : fma(-F[k], R[k], x);
+        x = k < j ? nx : x;
+    }
+    return x;
+}
+
+template <int KM>
+__device__ __forceinline__ double chain_tiered(double x, int j, int32_t row, const int32_t (&rk)[KM],
+                                               const double (&F)[KM], const double (&R)[KM]) {
+    constexpr int N1 = KM < 8 ? KM : 8, N2 = KM < 16 ? KM : 16;
+    if (j <= N1) return chain_steps<N1, KM>(x, j, row, rk, F, R);
+    if (j <= N2) return chain_steps<N2, KM>(x, j, row, rk, F, R);
+    return chain_steps<KM, KM>(x, j, row, rk, F, R);
+}
+
 // Entry (row, col) of the tableau at the start of the group. The first group
 // after a deferred build reads the structural columns from A and c (the
 // tableau holds them only after that group's update pass); everything else
@@ -874,14 +897,8 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         double Rq[KM];
 #pragma unroll
         for (int k = 0; k < KM; ++k) Rq[k] = Rk[(int64_t)(k < K ? k : K - 1) * Lg + tqs];
-        double a = start_entry<First>(T, ld, n, A, cv, q, is);
+        const double a = chain_tiered<KM>(start_entry<First>(T, ld, n, A, cv, q, is), j, i, rk, frow, Rq);
         const double bb = bcur;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const bool on = k < j, piv = i == rk[k];
-            const double na = piv ? Rq[k] : fma(-frow[k], Rq[k], a);
-            a = on ? na : a;
-        }
 #pragma unroll
         for (int k = 0; k < KM; ++k)
             if (k == j) frow[k] = a;
@@ -999,12 +1016,8 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         if (c_t >= 0) {
             // (the slot just appended holds e_r, whose entry in row r is 1:
             // taken as is, since the store above may not be visible yet)
-            double y = t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r);
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                const double ny = (r == rk[k]) ? rslot[k] : fma(-Fr[k], rslot[k], y);
-                y = k < j ? ny : y;
-            }
+            const double y0 = t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r);
+            const double y = chain_tiered<KM>(y0, j, r, rk, Fr, rslot);
             R = y / p;
             D_t = fma(-F0, R, D_t);
         }
