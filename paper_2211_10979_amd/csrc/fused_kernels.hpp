@@ -28,11 +28,23 @@
 // column's slot t indexes R_k[t] (the normalised pivot-row entry of pivot k)
 // and D[t] (its row-0 entry after the pivots staged so far).
 //
-// Launches per group, on one stream:
+// Launches per group, on one stream. The default path (at most
+// kMaxDecideWgs decision workgroups):
+//   k_gdecide        all the group's decisions in one launch (grid barriers),
+//                    the close of the previous group, and the pivot rows after
+//                    the group (PV);
+//   k_gupdate_pure   applies the group's pivots to every list column, the
+//                    chain without the pivot-row select;
+//   k_gfix           stores the pivot rows from PV.
+// The first group after a deferred build runs k_gdecide<.., true, ..> (reading
+// A and c) and k_gfirst (the build of the structural columns with the group
+// applied) plus a pure pass over the tail slots, then k_gfix. Otherwise, two
+// launches per pivot:
 //   k_gselect<j>, k_gstage<j>   for j = 0 .. K-1
 //   k_gupdate                   applies the kdone pivots the group decided.
-// k_gselect<0> also closes the previous group: the columns that entered and
-// stay basic give up their slots to the appended columns that stay nonbasic.
+// k_gselect<0> and k_gdecide also close the previous group: the columns that
+// entered and stay basic give up their slots to the appended columns that
+// stay nonbasic.
 #pragma once
 
 #include <type_traits>
