@@ -208,3 +208,40 @@ def test_timing_counters_and_eager_option():
     assert np.array_equal(x0, x1) and np.array_equal(y0, y1) and np.array_equal(T0, T1)
     with pytest.raises(Exception):
         lpgpu.lp_create(lp.A[:10, :10], lp.b[:10], lp.c[:10], eager_build=2)
+
+
+def test_dense_8000_bench_configuration():
+    """The benchmark workload at full size in the configuration the benchmark
+    times: a context from device arrays with kernel timing on, reloaded from
+    device arrays (deferred build) twice; each solve's log, solution and
+    final tableau equal the oracle's."""
+    lp = lpgen.workload("dense_8000x8000")
+    say("dense_8000x8000 deferred build: oracle")
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    o.step(-1)
+    ox, oy, oobj = o.extract()
+    orow, ocol = o.log()
+    OT = o.tableau()
+    obasis = o.basis()
+    o.close()
+    d = Deferred(lp.m, lp.n, time_kernels=1)
+    try:
+        assert lpgpu.lp_get_info(d.h).decide_workgroups > 0
+        for k in range(2):
+            say(f"dense_8000x8000 deferred build: gpu solve {k}")
+            d.reload(lp.A, lp.b, lp.c)
+            lpgpu.lp_solve(d.h)
+            res, x, y = lpgpu.lp_get_solution(d.h)
+            rows, cols = lpgpu.lp_get_pivots(d.h)
+            assert res["status"] == lpgpu.LP_OPTIMAL and res["pivots"] == len(orow)
+            assert rows.tolist() == orow.tolist() and cols.tolist() == ocol.tolist()
+            assert res["objective"] == oobj
+            assert np.array_equal(x, ox) and np.array_equal(y, oy)
+            assert lpgpu.lp_get_basis(d.h).tolist() == obasis.tolist()
+            t = lpgpu.lp_get_timing(d.h)
+            assert t["first_pass_columns"] > lp.n and t["applied_launches"] >= 1
+            T = lpgpu.lp_get_tableau(d.h)
+            assert np.array_equal(T, OT)
+            del T
+    finally:
+        d.close()
