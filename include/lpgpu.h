@@ -125,6 +125,16 @@ typedef struct {
                                pass (which reads A and c instead of the tableau) and leaves the
                                slack columns unwritten until they leave the basis; 1 = build
                                the whole tableau at once (default 0) */
+    int32_t status_readback; /* when the host reads the solver state (status, pivots) to decide
+                               on the next group: 1 = one group behind (the next group is
+                               queued before the state of the current one is read, so one
+                               group is launched after the solve ends and returns at once);
+                               2 = right after each group's decisions, while its update pass
+                               runs (no group after the end; the host's reaction time must
+                               stay below one update pass). 0 = auto: 2 with the one-launch
+                               decision kernel, one group per chunk and a tableau of at least
+                               256 MiB, else 1. 2 needs the one-launch decision kernel and
+                               chunk_pivots 0 or at most fuse_pivots. */
 } lp_options;
 
 typedef struct {
@@ -150,6 +160,7 @@ typedef struct {
     int32_t update_fuse;    /* pivots per pass over the tableau (fuse_pivots in use) */
     int32_t decide_workgroups; /* K > 1: workgroups of the one-launch decision kernel (its update
                                pass is k_gupdate_pure); 0 = two launches per pivot (k_gupdate) */
+    int32_t status_readback;   /* status_readback in use (1 or 2) */
 } lp_info;
 
 /* Library version string. Never fails. */

@@ -63,6 +63,7 @@ int lp_options_default(lp_options *o) {
     o->decide_spin = 0;
     o->decide_block = 0;
     o->eager_build = 0;
+    o->status_readback = 0;
     return LP_OK;
 }
 

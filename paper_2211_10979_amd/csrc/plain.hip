@@ -124,6 +124,9 @@ struct lp_ctx {
     // come, and whether basic columns may be unstored (slack columns are
     // written only when they leave the basis).
     bool eager_build = false;
+    // The host reads the state right after each group's decisions (instead
+    // of one group behind), while the group's update pass runs.
+    bool early_status = false;
     const double *pend_A = nullptr, *pend_b = nullptr, *pend_c = nullptr;
     bool pending = false;
     bool first_ran = false;  // the first group of the current build was such a group
@@ -218,8 +221,15 @@ int validate_opts(const lp_options &o) {
     if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
         return set_error(LP_E_INVAL, "decide_block must be 0 (auto), 256 or 512");
     if (o.eager_build < 0 || o.eager_build > 1) return set_error(LP_E_INVAL, "eager_build must be 0 or 1");
+    if (o.status_readback < 0 || o.status_readback > 2)
+        return set_error(LP_E_INVAL, "status_readback must be 0 (auto), 1 or 2");
     return LP_OK;
 }
+
+// status_readback 0 reads the state right after the decisions (2) from a
+// tableau of this size on: its update pass then outlasts the host's reaction
+// time (event wake-up, read-back, launches: tens of microseconds).
+constexpr size_t kEarlyStatusBytes = size_t(256) << 20;
 
 // Allocates everything except the inputs; the tableau is not built yet.
 int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
@@ -324,6 +334,8 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         free_ctx(h);
         return rc;
     };
+    if (o.status_readback == 2 && h->fuse <= 1)
+        return fail(set_error(LP_E_INVAL, "status_readback 2 needs pivot fusion (fuse_pivots > 1)"));
     auto dev_alloc = [&](void **p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
         if (e != hipSuccess) {
@@ -382,6 +394,12 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
         h->decide_wgs = (o.decide_kernel == 0 && g <= kMaxDecideWgs) ? g : 0;
         h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
+        const bool can_early = h->decide_wgs > 0 && h->chunk == 1;
+        if (o.status_readback == 2 && !can_early)
+            return fail(set_error(LP_E_INVAL,
+                                  "status_readback 2 needs the one-launch decision kernel and one group per chunk"));
+        h->early_status = can_early && (o.status_readback == 2 ||
+                                        (o.status_readback == 0 && lp_tableau_bytes(m, n) >= kEarlyStatusBytes));
         const size_t nsp = std::max<size_t>((size_t)h->nsparts, (size_t)kMaxDecideWgs);
         if (int rc = dev_alloc((void **)&h->sparts, nsp * sizeof(SPart))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->grparts, kMaxDecideWgs * sizeof(GRatio))) return fail(rc);
@@ -703,6 +721,70 @@ int enqueue_extract(lp_ctx *h) {
     return LP_OK;
 }
 
+// Solver-state read-back right after each group's decisions: the next
+// group is launched while the current group's update pass runs, so no group
+// is queued after the solve ends.
+int run_until_early(lp_ctx *h, int64_t stop_at) {
+    int64_t last = h->pivots_host;  // pivots before the group being harvested
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
+    LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
+    int slot = 0;
+    int64_t advanced = 0;  // pivots of the group in the other slot, harvested once its pass is done
+    bool have_prev = false;
+    for (;;) {
+        // the group's decisions, the state they leave read back, then its
+        // update pass (queued at once: the device never waits for the host)
+        const FusedArgs a = fused_args(h);
+        const bool first = h->pending;
+        h->first_slot[slot] = first;
+        if (first) {
+            h->pending = false;
+            h->first_ran = true;
+            launch_first_decide(a, h->pend_A, h->pend_c, h->stream);
+        } else {
+            launch_fused_decide(a, h->stream);
+        }
+        LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[slot], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        LP_HIP_CHECK(hipEventRecord(h->ev_slot[slot], h->stream));
+        if (first) {
+            launch_first_update(a, h->pend_A, h->pend_c, h->stream, h->timing ? h->ev_first[0] : nullptr,
+                                h->timing ? h->ev_first[1] : nullptr);
+        } else {
+            const UpdateConfig &u = h->ucfg;
+            launch_fused_update(a, u.block, u.cols, u.rv, h->stream, h->timing ? h->ev_upd[slot][0] : nullptr,
+                                h->timing ? h->ev_upd[slot][1] : nullptr);
+        }
+        LP_HIP_CHECK(hipGetLastError());
+        LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
+        const DevState s = h->host_st[slot];
+        // the previous group's update pass ran before these decisions
+        if (have_prev)
+            if (int rc = harvest_timing(h, slot ^ 1, advanced)) return rc;
+        advanced = s.pivots - last;
+        last = s.pivots;
+        have_prev = true;
+        if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
+        slot ^= 1;
+    }
+    LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
+    if (int rc = enqueue_extract(h)) return rc;
+    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[2], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    LP_HIP_CHECK(hipMemcpyAsync(h->host_cols, h->cols_done, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                h->stream));
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    const DevState s = h->host_st[2];
+    h->counters_cached = true;
+    h->solution_cached = true;
+    if (int rc = harvest_timing(h, slot, advanced)) return rc;  // the last group
+    h->pivots_host = s.pivots;
+    h->status_host = s.status;
+    float ms = 0.f;
+    LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
+    h->last_ms = ms;
+    h->ran = true;
+    return LP_OK;
+}
+
 // Runs pivots until the status leaves RUNNING or `stop_at` pivots are done.
 // Chunks are pipelined two deep: chunk k+1 is queued before the status of
 // chunk k is read back, so the device never waits for the host.
@@ -715,6 +797,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     h->first_ms = 0.0;
     h->counters_cached = false;
     h->solution_cached = false;
+    if (h->early_status) return run_until_early(h, stop_at);
     // the first chunk is the first group of a deferred build when one is pending
     auto launch = [h](int sl) -> int {
         h->first_slot[sl] = h->pending;
@@ -946,6 +1029,7 @@ int lp_get_info(const lp_ctx *h, lp_info *info) {
     info->update_hints = h->ucfg.nt;
     info->update_fuse = h->fuse;
     info->decide_workgroups = h->fuse > 1 ? h->decide_wgs : 0;
+    info->status_readback = h->early_status ? 2 : 1;
     return LP_OK;
 }
 

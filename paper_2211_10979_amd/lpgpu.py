@@ -62,6 +62,7 @@ class lp_options(ctypes.Structure):
         ("decide_spin", ctypes.c_int32),
         ("decide_block", ctypes.c_int32),
         ("eager_build", ctypes.c_int32),
+        ("status_readback", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ class lp_info(ctypes.Structure):
         ("update_hints", ctypes.c_int32),
         ("update_fuse", ctypes.c_int32),
         ("decide_workgroups", ctypes.c_int32),
+        ("status_readback", ctypes.c_int32),
     ]
 
 

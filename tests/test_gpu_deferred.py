@@ -98,13 +98,15 @@ def test_degenerate_battery_deferred(K):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K", [7, 16, 29])
-def test_stepping_after_reload(K):
+@pytest.mark.parametrize("K,readback", [(7, 0), (16, 0), (29, 0), (7, 2), (29, 2)])
+def test_stepping_after_reload(K, readback):
     """A first lp_step of 0 pivots (the first pass only builds), then
-    budgets that cut groups short; the tableau after every step."""
+    budgets that cut groups short; the tableau after every step. Read-back 2
+    reads the solver state right after each group's decisions."""
     lp = lpgen.workload("dense_200x200")
-    say(f"deferred build K={K}: dense_200x200 stepping")
-    d = Deferred(lp.m, lp.n, fuse_pivots=K)
+    say(f"deferred build K={K} status_readback={readback}: dense_200x200 stepping")
+    d = Deferred(lp.m, lp.n, fuse_pivots=K, status_readback=readback)
+    assert lpgpu.lp_get_info(d.h).status_readback == (2 if readback == 2 else 1)
     o = oracle.OracleLP(lp.A, lp.b, lp.c)
     try:
         d.reload(lp.A, lp.b, lp.c)
@@ -245,3 +247,60 @@ def test_dense_8000_bench_configuration():
             del T
     finally:
         d.close()
+
+
+@pytest.mark.parametrize("K", [4, 24])
+def test_degenerate_battery_early_status(K):
+    """The degenerate battery with the solver state read right after each
+    group's decisions (status_readback = 2)."""
+    say(f"deferred build K={K}: degenerate battery, status_readback 2")
+    for seed in range(120):
+        A, b, c = degenerate_lp(seed, seed % 4)
+        m, n = A.shape
+        d = Deferred(m, n, fuse_pivots=K, status_readback=2)
+        o = oracle.OracleLP(A, b, c)
+        try:
+            d.reload(A, b, c)
+            lpgpu.lp_solve(d.h)
+            o.step(-1)
+            compare_final(d.h, o)
+        finally:
+            d.close()
+            o.close()
+
+
+def test_status_readback_counters_and_choice():
+    """With the state read after the decisions no group is launched after the
+    end (at most one pass that applies nothing: a group whose first pricing
+    finds the optimum); one group behind, one is. Same results either way.
+    The automatic choice and the rejected combinations."""
+    lp = lpgen.workload("dense_2000x2000")
+    say("status_readback: counters on dense_2000x2000")
+    out = {}
+    for rb in (1, 2):
+        d = Deferred(lp.m, lp.n, time_kernels=1, status_readback=rb)
+        try:
+            assert lpgpu.lp_get_info(d.h).status_readback == rb
+            d.reload(lp.A, lp.b, lp.c)
+            lpgpu.lp_solve(d.h)
+            res, x, y = lpgpu.lp_get_solution(d.h)
+            t = lpgpu.lp_get_timing(d.h)
+            idle = t["update_launches"] - t["applied_launches"]
+            assert idle in ((0, 1) if rb == 2 else (1, 2)), (rb, t)
+            out[rb] = (res, x, y, lpgpu.lp_get_tableau(d.h), lpgpu.lp_get_pivots(d.h))
+        finally:
+            d.close()
+    (r1, x1, y1, T1, l1), (r2, x2, y2, T2, l2) = out[1], out[2]
+    assert r1["pivots"] == r2["pivots"] and r1["objective"] == r2["objective"]
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2) and np.array_equal(T1, T2)
+    assert l1[0].tolist() == l2[0].tolist() and l1[1].tolist() == l2[1].tolist()
+    small = lpgen.workload("dense_200x200")
+    h = lpgpu.lp_create(small.A, small.b, small.c)
+    try:
+        assert lpgpu.lp_get_info(h).status_readback == 1  # auto: a small tableau
+    finally:
+        lpgpu.lp_destroy(h)
+    for bad in (dict(status_readback=3), dict(status_readback=2, fuse_pivots=1),
+                dict(status_readback=2, decide_kernel=1), dict(status_readback=2, chunk_pivots=100)):
+        with pytest.raises(Exception):
+            lpgpu.lp_create(small.A, small.b, small.c, **bad)
