@@ -10,7 +10,10 @@ Reads whatever the directory holds:
   * `*_counter_collection.csv` (from --pmc): per-kernel average of each
     counter over the dispatches of that kernel (optionally only those whose
     value reaches --min-value, e.g. to leave out launches that returned at
-    once).
+    once);
+  * with --by-grid, `*_kernel_trace.csv` (from --kernel-trace): the same
+    duration figures per kernel and grid size, which tells apart launches of
+    one kernel over different extents.
 Durations are in microseconds.
 """
 
@@ -71,7 +74,18 @@ def counters_csv(path, min_value=0.0):
     return out
 
 
-def summarize(directory, kernel=None, min_value=0.0):
+def kernel_trace_by_grid(path):
+    """Per (kernel, grid size in threads): dispatch durations in us."""
+    durs = defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            durs[(_short(r["Kernel_Name"]), grid)].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return durs
+
+
+def summarize(directory, kernel=None, min_value=0.0, by_grid=False):
     out = []
     stats = []
     for p in sorted(glob.glob(os.path.join(directory, "**", "*_kernel_stats.csv"), recursive=True)):
@@ -90,6 +104,17 @@ def summarize(directory, kernel=None, min_value=0.0):
                 continue
             out.append(f"| {r['kernel']} | {r['calls']} | {r['total_us']:.1f} | {r['avg_us']:.2f} | "
                        f"{r['min_us']:.2f} | {r['max_us']:.2f} |")
+    if by_grid:
+        for p in sorted(glob.glob(os.path.join(directory, "**", "*_kernel_trace.csv"), recursive=True)):
+            out.append("")
+            out.append(f"by grid: {os.path.relpath(p, directory)}")
+            out.append("")
+            out.append("| kernel | grid threads | calls | avg us | min us | max us |")
+            out.append("|---|---|---|---|---|---|")
+            for (k, grid), v in sorted(kernel_trace_by_grid(p).items(), key=lambda kv: -sum(kv[1])):
+                if kernel and kernel not in k:
+                    continue
+                out.append(f"| {k} | {grid} | {len(v)} | {statistics.fmean(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
     for p in sorted(glob.glob(os.path.join(directory, "**", "*_counter_collection.csv"), recursive=True)):
         cs = counters_csv(p, min_value)
         out.append("")
@@ -112,8 +137,10 @@ def main():
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--min-value", type=float, default=0.0,
                     help="counters: average only dispatches whose value is at least this")
+    ap.add_argument("--by-grid", action="store_true",
+                    help="also durations per kernel and grid size, from the kernel trace")
     a = ap.parse_args()
-    print(summarize(a.directory, a.kernel, a.min_value))
+    print(summarize(a.directory, a.kernel, a.min_value, a.by_grid))
 
 
 if __name__ == "__main__":
