@@ -149,6 +149,7 @@ def bench_plain(args, lpgpu, lpgen, torch):
         rows, cols = lpgpu.lp_get_pivots(h)
         info = lpgpu.lp_get_info(h)
         fuse = info.update_fuse
+        readback = info.status_readback
         if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24 or 32 pivots
             kf = next(k for k in (2, 4, 8, 12, 16, 24, 32) if k >= fuse)
             name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"
@@ -177,6 +178,7 @@ def bench_plain(args, lpgpu, lpgen, torch):
         certificates_ok=bool(ok),
         certificate_max_residual=max(resid.values()),
         fuse_pivots=fuse,
+        status_readback=readback,
         end_to_end_alg_gbs=alg_total / elapsed / 1e9,
         end_to_end_alg_frac=alg_total / elapsed / 1e9 / HBM_PEAK_GBS,
         device_solve_ms_per_step=solve_ms / args.steps,
