@@ -768,10 +768,12 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
     }
     LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
     if (int rc = enqueue_extract(h)) return rc;
-    LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[2], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     LP_HIP_CHECK(hipMemcpyAsync(h->host_cols, h->cols_done, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 h->stream));
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    // the state read after the last decisions is final: the update pass, the
+    // pivot-row stores and the extraction do not write it
+    h->host_st[2] = h->host_st[slot];
     const DevState s = h->host_st[2];
     h->counters_cached = true;
     h->solution_cached = true;
