@@ -127,6 +127,7 @@ struct lp_ctx {
     // The host reads the state right after each group's decisions (instead
     // of one group behind), while the group's update pass runs.
     bool early_status = false;
+    int64_t dev_stop_at = 0;  // the pause point the device state holds (the last one enqueued)
     const double *pend_A = nullptr, *pend_b = nullptr, *pend_c = nullptr;
     bool pending = false;
     bool first_ran = false;  // the first group of the current build was such a group
@@ -470,7 +471,7 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.status = LP_RUNNING;
     init.go = 0;
     init.pivots = 0;
-    init.stop_at = 0;
+    init.stop_at = INT64_MAX;  // no budget: what lp_solve asks for
     init.max_pivots = h->max_pivots;
     init.log_cap = h->log_cap;
     init.eps_d = h->eps_d;
@@ -489,6 +490,7 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
                            h->basis, m, n, h->F, ld, h->cols, h->pos, h->cols_done);
     }
     LP_HIP_CHECK(hipGetLastError());
+    h->dev_stop_at = init.stop_at;
     h->pivots_host = 0;
     h->status_host = LP_RUNNING;
     h->ran = false;
@@ -721,12 +723,19 @@ int enqueue_extract(lp_ctx *h) {
     return LP_OK;
 }
 
+// The pause point of the device state, written only when it changes.
+void set_stop(lp_ctx *h, int64_t stop_at) {
+    if (stop_at == h->dev_stop_at) return;
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
+    h->dev_stop_at = stop_at;
+}
+
 // Solver-state read-back right after each group's decisions: the next
 // group is launched while the current group's update pass runs, so no group
 // is queued after the solve ends.
 int run_until_early(lp_ctx *h, int64_t stop_at) {
     int64_t last = h->pivots_host;  // pivots before the group being harvested
-    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
+    set_stop(h, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
     int64_t advanced = 0;  // pivots of the group in the other slot, harvested once its pass is done
@@ -811,7 +820,7 @@ int run_until(lp_ctx *h, int64_t stop_at) {
         return launch_chunk(h, sl);
     };
     int64_t last = h->pivots_host;  // pivots before the chunk being harvested
-    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(1), 0, h->stream, h->st, stop_at);
+    set_stop(h, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
     if (int rc = launch(0)) return rc;
