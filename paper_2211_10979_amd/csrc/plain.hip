@@ -91,6 +91,7 @@ struct lp_ctx {
     double *Rl = nullptr;     // normalised pivot row by list position (n+2)
     DevState *host_st = nullptr;  // pinned: two slots for the pipelined status read-back, one for the end
     unsigned long long *host_cols = nullptr;  // pinned: the work counters at the end of the last solve
+    unsigned char *host_blk = nullptr;        // pinned: two copies of the state block (status read-back 2)
     double *host_out = nullptr;               // pinned: extraction output
     bool counters_cached = false;             // host_st[2] and host_cols hold the device's current values
     bool solution_cached = false;             // host_out holds the extraction of the current tableau
@@ -165,7 +166,6 @@ void free_ctx(lp_ctx *h) {
     }
     for (auto e : h->ev_first)
         if (e) (void)hipEventDestroy(e);
-    if (h->cols_done) (void)hipFree(h->cols_done);
     if (h->rparts) (void)hipFree(h->rparts);
     if (h->ticket) (void)hipFree(h->ticket);
     if (h->own_T && h->T) (void)hipFree(h->T);
@@ -188,6 +188,7 @@ void free_ctx(lp_ctx *h) {
     if (h->dump) (void)hipFree(h->dump);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->host_cols) (void)hipHostFree(h->host_cols);
+    if (h->host_blk) (void)hipHostFree(h->host_blk);
     if (h->host_out) (void)hipHostFree(h->host_out);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -226,6 +227,10 @@ int validate_opts(const lp_options &o) {
         return set_error(LP_E_INVAL, "status_readback must be 0 (auto), 1 or 2");
     return LP_OK;
 }
+
+// The state block: DevState, then the work counters at a 64-byte offset.
+constexpr size_t kCountersAt = (sizeof(DevState) + 63) / 64 * 64;
+constexpr size_t kStateBlock = kCountersAt + 4 * sizeof(unsigned long long);
 
 // status_readback 0 reads the state right after the decisions (2) from a
 // tableau of this size on: its update pass then outlasts the host's reaction
@@ -367,14 +372,16 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     const int kf = h->fuse > 1 ? fused_update_kf(h->fuse) : 1;
     if (int rc = dev_alloc((void **)&h->F, (size_t)kf * h->ld * sizeof(double))) return fail(rc);
     if (int rc = dev_alloc((void **)&h->parts, (size_t)h->nparts * sizeof(ArgMin))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->st, sizeof(DevState))) return fail(rc);
+    // the state block: the solver state, then the four work counters, so
+    // that one copy reads both
+    if (int rc = dev_alloc((void **)&h->st, kStateBlock)) return fail(rc);
+    h->cols_done = reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(h->st) + kCountersAt);
     if (int rc = dev_alloc((void **)&h->basis, (size_t)m * sizeof(int32_t))) return fail(rc);
     if (h->log_cap) {
         if (int rc = dev_alloc((void **)&h->log_r, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
         if (int rc = dev_alloc((void **)&h->log_q, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
     }
     if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->cols_done, 4 * sizeof(unsigned long long))) return fail(rc);
     if (hipMemset(h->cols_done, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (int rc = dev_alloc((void **)&h->rparts, 64 * sizeof(RatioPart))) return fail(rc);
@@ -416,6 +423,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_blk, 2 * kStateBlock, hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&h->host_out, ((size_t)n + m + 1) * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
@@ -753,7 +761,8 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         } else {
             launch_fused_decide(a, h->stream);
         }
-        LP_HIP_CHECK(hipMemcpyAsync(&h->host_st[slot], h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        unsigned char *blk = h->host_blk + slot * kStateBlock;  // the state and the work counters
+        LP_HIP_CHECK(hipMemcpyAsync(blk, h->st, kStateBlock, hipMemcpyDeviceToHost, h->stream));
         LP_HIP_CHECK(hipEventRecord(h->ev_slot[slot], h->stream));
         if (first) {
             launch_first_update(a, h->pend_A, h->pend_c, h->stream, h->timing ? h->ev_first[0] : nullptr,
@@ -765,6 +774,7 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         }
         LP_HIP_CHECK(hipGetLastError());
         LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
+        std::memcpy(&h->host_st[slot], blk, sizeof(DevState));
         const DevState s = h->host_st[slot];
         // the previous group's update pass ran before these decisions
         if (have_prev)
@@ -777,12 +787,12 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
     }
     LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
     if (int rc = enqueue_extract(h)) return rc;
-    LP_HIP_CHECK(hipMemcpyAsync(h->host_cols, h->cols_done, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                h->stream));
     LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-    // the state read after the last decisions is final: the update pass, the
-    // pivot-row stores and the extraction do not write it
+    // the state and the work counters read after the last decisions are
+    // final: only the decision kernels write them (not the update pass, the
+    // pivot-row stores or the extraction)
     h->host_st[2] = h->host_st[slot];
+    std::memcpy(h->host_cols, h->host_blk + slot * kStateBlock + kCountersAt, 4 * sizeof(unsigned long long));
     const DevState s = h->host_st[2];
     h->counters_cached = true;
     h->solution_cached = true;
