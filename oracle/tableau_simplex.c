@@ -26,8 +26,14 @@
  *                        T[r][j] = R_j; basis[r-1] = q.
  *   Iterate/Finalization repeat Steps 1-3 until optimal or unbounded. An
  *                        iteration cap (checked after Step 2, before the
- *                        pivot) stops with ITER_LIMIT. A NaN seen by Step 1 or
- *                        Step 2 stops with NUMERICAL.
+ *                        pivot) stops with ITER_LIMIT.
+ *   Non-finite values    the paper does not discuss them. Read here as: Step 1
+ *                        stops with NUMERICAL when row 0 holds a NaN or its
+ *                        smallest entry is -inf; Step 2 stops with NUMERICAL
+ *                        when, in some row 1..m (eligible or not), the
+ *                        entering column holds a value that is not finite or
+ *                        the RHS holds a NaN. A ratio that overflows is an
+ *                        ordinary infinite ratio.
  *
  * Arithmetic: IEEE binary64, division for R and the ratios, one fused
  * multiply-add per updated entry. Build with -ffp-contract=off and no
@@ -125,7 +131,8 @@ oracle_lp *oracle_create(int m, int n, const double *A, const double *b, const d
     return o;
 }
 
-/* Step 1. Returns the entering column, -1 when optimal, -2 on NaN. */
+/* Step 1. Returns the entering column, -1 when optimal, -2 when row 0 holds a
+ * NaN or its smallest entry is -inf. */
 static int choose_entering(const oracle_lp *o)
 {
     int q = 0;
@@ -138,11 +145,13 @@ static int choose_entering(const oracle_lp *o)
             q = j;
         }
     }
+    if (best == -INFINITY) return -2;
     if (best >= -o->eps_d) return -1;
     return q;
 }
 
-/* Step 2. Returns the leaving row in [1, m], -1 when unbounded, -2 on NaN. */
+/* Step 2. Returns the leaving row in [1, m], -1 when unbounded, -2 when some
+ * row holds a non-finite entering-column value or a NaN right-hand side. */
 static int choose_leaving(const oracle_lp *o, int q)
 {
     const int W = o->W;
@@ -151,10 +160,9 @@ static int choose_leaving(const oracle_lp *o, int q)
     for (int i = 1; i <= o->m; ++i) {
         double a = TAB(o, i, q);
         double rhs = TAB(o, i, W - 1);
-        if (isnan(a) || isnan(rhs)) return -2;
+        if (!isfinite(a) || isnan(rhs)) return -2;
         if (a > o->eps_p) {
-            double ratio = rhs / a;
-            if (isnan(ratio)) return -2;
+            double ratio = rhs / a; /* finite a > 0 and a non-NaN rhs: never NaN */
             if (r < 0 || ratio < best) {
                 best = ratio;
                 r = i;

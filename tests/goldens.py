@@ -19,8 +19,10 @@ def read_fixture(name):
                 out[key].append([float(v) for v in vals])
             elif key == "pivot":
                 out["pivot"].append(tuple(int(v) for v in vals))
-            elif key in ("m", "n"):
+            elif key in ("m", "n", "pivots"):
                 out[key] = int(vals[0])
+            elif key == "status":
+                out[key] = vals[0]
             elif key == "objective":
                 out[key] = float(vals[0])
             else:

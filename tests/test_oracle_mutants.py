@@ -36,7 +36,16 @@ MUTANTS = {
     "cap_off_by_one": ("if (o->pivots >= o->max_pivots)", "if (o->pivots > o->max_pivots)"),
     "pivot_row_not_normalised": ("for (int j = 0; j < W; ++j) row[j] = R[j];", "for (int j = 0; j < W; ++j) row[j] = row[j];"),
     "x_from_wrong_row": ("x[o->basis[i - 1]] = TAB(o, i, W - 1);", "x[o->basis[i - 1]] = TAB(o, i - 1, W - 1);"),
+    "step1_nan_ignored": ("if (isnan(v)) return -2;", "(void)0;"),
+    "step1_neg_inf_ignored": ("if (best == -INFINITY) return -2;", "(void)0;"),
+    "step2_inf_column_ignored": ("if (!isfinite(a) || isnan(rhs)) return -2;", "if (isnan(a) || isnan(rhs)) return -2;"),
+    "step2_nan_rhs_ignored": ("if (!isfinite(a) || isnan(rhs)) return -2;", "if (!isfinite(a)) return -2;"),
+    "step2_nan_rhs_eligible_rows_only": ("if (!isfinite(a) || isnan(rhs)) return -2;\n        if (a > o->eps_p) {",
+                                         "if (!isfinite(a)) return -2;\n        if (a > o->eps_p) {\n            if (isnan(rhs)) return -2;"),
 }
+
+NONFINITE_FIXTURES = ["nonfinite_step2_nan_rhs.txt", "nonfinite_step1_neg_inf.txt",
+                      "nonfinite_step2_inf_column.txt", "nonfinite_step1_nan.txt"]
 
 
 def _battery(lib):
@@ -52,6 +61,12 @@ def _battery(lib):
     if abs(r["objective"] - fx["objective"]) > 1e-12 or not np.allclose(r["y"], fx["y"]) \
             or not np.allclose(r["x"], fx["x"]):
         return "hand example solution"
+    for name in NONFINITE_FIXTURES:
+        nf = read_fixture(name)
+        r = solve(nf["A"], nf["b"], nf["c"])
+        if oracle.STATUS_NAMES[r["status"]] != nf["status"] or r["pivots"] != nf["pivots"] \
+                or list(zip(r["rows"].tolist(), r["cols"].tolist())) != nf["pivot"]:
+            return f"non-finite fixture {name}"
     rng = np.random.default_rng(5)
     for t in range(12):
         m, n = int(rng.integers(1, 6)), int(rng.integers(1, 6))

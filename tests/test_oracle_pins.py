@@ -61,6 +61,34 @@ def test_hand_example():
     assert np.allclose(o.tableau(), fx["T"], rtol=1e-14, atol=1e-14)
 
 
+NONFINITE_FIXTURES = ["nonfinite_step2_nan_rhs.txt", "nonfinite_step1_neg_inf.txt",
+                      "nonfinite_step2_inf_column.txt", "nonfinite_step1_nan.txt"]
+
+
+@pytest.mark.parametrize("name", NONFINITE_FIXTURES)
+def test_nonfinite_stop(name):
+    """Hand-worked overflows: the stop, the step it happens in and the pivots before it."""
+    fx = read_fixture(name)
+    r = oracle.solve(fx["A"], fx["b"], fx["c"])
+    assert oracle.STATUS_NAMES[r["status"]] == fx["status"]
+    assert r["pivots"] == fx["pivots"]
+    assert list(zip(r["rows"].tolist(), r["cols"].tolist())) == fx["pivot"]
+
+
+def test_nonfinite_never_reaches_a_basic_column():
+    """After every pivot the basic columns are exact unit vectors, also when
+    the LP overflows (the pivot column is always finite when Step 3 runs)."""
+    for name in NONFINITE_FIXTURES:
+        fx = read_fixture(name)
+        o = oracle.OracleLP(fx["A"], fx["b"], fx["c"], threads=1)
+        while o.step(1) == oracle.RUNNING:
+            T, basis = o.tableau(), o.basis()
+            for i, j in enumerate(basis):
+                unit = np.zeros(o.m + 1)
+                unit[i + 1] = 1.0
+                assert np.array_equal(T[:, j], unit), (name, j)
+
+
 # ---------------------------------------------------------------- brute force
 
 
