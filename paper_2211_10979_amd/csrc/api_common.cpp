@@ -14,6 +14,24 @@ int set_error(int code, const std::string &msg) {
     return code;
 }
 
+Options resolve_options(const lp_options *opt) {
+    lp_options o;
+    lp_options_default(&o);
+    if (opt) o = *opt;
+    Options r{};
+    lp_tuning_default(&r);
+    if (o.tuning) static_cast<lp_tuning &>(r) = *o.tuning;
+    r.eps_dual = o.eps_dual;
+    r.eps_pivot = o.eps_pivot;
+    r.max_pivots = o.max_pivots;
+    r.record_pivots = o.record_pivots;
+    r.stream = o.stream;
+    r.device_buffer = o.device_buffer;
+    r.device_buffer_bytes = o.device_buffer_bytes;
+    r.device = o.device;
+    return r;
+}
+
 }  // namespace lpgpu
 
 extern "C" {
@@ -42,28 +60,17 @@ int lp_options_default(lp_options *o) {
     o->eps_pivot = 1e-9;
     o->max_pivots = 0;
     o->record_pivots = 1;
-    o->device = 0;
     o->stream = nullptr;
     o->device_buffer = nullptr;
     o->device_buffer_bytes = 0;
-    o->chunk_pivots = 0;
-    o->cols_per_block = 0;
-    o->use_graph = 1;
-    o->time_kernels = 0;
-    o->rows_per_thread = 0;
-    o->batch_block = 0;
-    o->batch_unroll = 0;
-    o->update_hints = 0;
-    o->update_block = 0;
-    o->update_grid_stride = 0;
-    o->update_unroll = 0;
-    o->select_workgroups = 0;
-    o->fuse_pivots = 0;
-    o->decide_kernel = 0;
-    o->decide_spin = 0;
-    o->decide_block = 0;
-    o->eager_build = 0;
-    o->status_readback = 0;
+    o->device = 0;
+    o->tuning = nullptr;
+    return LP_OK;
+}
+
+int lp_tuning_default(lp_tuning *t) {
+    if (!t) return LP_E_INVAL;
+    *t = lp_tuning{};
     return LP_OK;
 }
 

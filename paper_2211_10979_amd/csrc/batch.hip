@@ -293,9 +293,7 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     if (!out) return set_error(LP_E_INVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || !m || !n || !A || !bv || !cv) return set_error(LP_E_INVAL, "bad batch arguments");
-    lp_options o;
-    lp_options_default(&o);
-    if (opt_in) o = *opt_in;
+    const Options o = resolve_options(opt_in);
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
     int ndev = 0;

@@ -103,7 +103,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDesc &d, BatchState *
     int32_t status = LP_RUNNING;
     int64_t cols_done = 0;
     for (;;) {
-        if (v != v) {
+        if (step1_bad(v)) {
             status = LP_NUMERICAL;
             break;
         }
@@ -121,13 +121,11 @@ __device__ __forceinline__ void batch_solve_one(const BatchDesc &d, BatchState *
         int bad = 0;
         for (int32_t i = 1 + tid; i <= m; i += BT) {
             const double a = colq[i], bb = rhs[i];
-            if (a != a || bb != bb) {
+            if (step2_bad(a, bb)) {
                 bad = 1;
             } else if (a > s.eps_p) {
                 const double ratio = bb / a;
-                if (ratio != ratio)
-                    bad = 1;
-                else if (lex_less(ratio, i, rv, r)) {
+                if (lex_less(ratio, i, rv, r)) {
                     rv = ratio;
                     r = i;
                 }

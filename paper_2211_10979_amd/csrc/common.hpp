@@ -49,6 +49,19 @@ __device__ __forceinline__ bool lex_less(double av, int32_t ai, double bv, int32
     return av < bv || (av == bv && ai < bi);
 }
 
+// Non-finite values (the paper does not discuss them; the reading shared with
+// the CPU reference): Step 1 stops with LP_NUMERICAL when its minimum over
+// row 0 is a NaN (a NaN wins every argmin, so the minimum is NaN iff row 0
+// holds one) or -inf; Step 2 stops with LP_NUMERICAL when, in some row 1..m,
+// the entering column's entry is not finite or the RHS entry is a NaN. A
+// ratio is then never a NaN (finite over finite, or +-inf over finite), and
+// the pivot column F is finite, so every basic column's normalised pivot-row
+// entry is exactly +-0 and skipping basic columns in Step 3 changes no value.
+__device__ __forceinline__ bool step1_bad(double v) { return v != v || v == -__builtin_inf(); }
+__device__ __forceinline__ bool step2_bad(double a, double rhs) {
+    return !__builtin_isfinite(a) || rhs != rhs;
+}
+
 // An empty slot: +inf with the largest index loses to every real candidate.
 constexpr int32_t kNoIndex = 0x7fffffff;
 
@@ -79,6 +92,19 @@ __device__ __forceinline__ void block_argmin(double &v, int32_t &i, double *sv, 
     i = lane < nw ? si[lane] : kNoIndex;
     wave_argmin(v, i);
 }
+
+// The options of a call with its tuning record resolved (a NULL lp_options
+// or a NULL tuning pointer gives the defaults).
+struct Options : lp_tuning {
+    double eps_dual, eps_pivot;
+    int64_t max_pivots;
+    int32_t record_pivots;
+    void *stream;
+    void *device_buffer;
+    size_t device_buffer_bytes;
+    int32_t device;
+};
+Options resolve_options(const lp_options *opt);
 
 // Thread-local last error text and a setter returning the code.
 int set_error(int code, const std::string &msg);

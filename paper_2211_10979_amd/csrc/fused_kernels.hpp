@@ -60,6 +60,9 @@ constexpr int kMaxFuseSplit = 16;  // with the two launches per pivot (k_gselect
 struct GroupState {
     int32_t kdone;  // pivots decided in this group
     int32_t napp;   // leaving columns appended to the list (slots n+1 ..)
+    int32_t stalled;  // 1: a grid-barrier wait of the decision kernel gave up; the update
+                      // passes then apply nothing (the group's inputs are incomplete)
+    int32_t pad_;
     int32_t r[kMaxFuse];
     int32_t q[kMaxFuse];
     int32_t l[kMaxFuse];  // leaving column of pivot k
@@ -78,6 +81,7 @@ static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int3
         *st = init;
         gs->kdone = 0;
         gs->napp = 0;
+        gs->stalled = 0;
         cols_done[0] = 0;
         cols_done[1] = 0;
         cols_done[2] = 0;
@@ -367,9 +371,9 @@ __global__ __launch_bounds__(256) void k_gselect(const double *__restrict__ T, i
     else
         reduce_parts(sparts, nsparts, tid, nt, v, q, tq);
     block_argmin_t(v, q, tq, sv, si, sl);
-    if (v != v || v >= -s.eps_d) {
+    if (step1_bad(v) || v >= -s.eps_d) {
         if (w == 0 && tid == 0) {
-            st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            st->status = step1_bad(v) ? LP_NUMERICAL : LP_OPTIMAL;
             if (J == 0) close_group(gs, cols, pos, n);
         }
         return;
@@ -419,13 +423,11 @@ __global__ __launch_bounds__(256) void k_gselect(const double *__restrict__ T, i
         }
         Fj[i] = a;
         if (i == 0) continue;
-        if (a != a || bb != bb) {
+        if (step2_bad(a, bb)) {
             bad = 1;
         } else if (a > s.eps_p) {
             const double ratio = bb / a;
-            if (ratio != ratio)
-                bad = 1;
-            else if (lex_less(ratio, i, rv, r)) {
+            if (lex_less(ratio, i, rv, r)) {
                 rv = ratio;
                 r = i;
                 p_best = a;
@@ -670,8 +672,15 @@ struct GridSync {
 // sequence of every arrival, so the fence makes all their writes visible
 // (fence synchronisation). An acquire on every poll would invalidate the
 // cache on every poll.
+//
+// A wait that gives up marks the solve LP_STALLED and the group as stalled.
+// Arrivals of workgroups that gave up still count, so a late workgroup can
+// pass a barrier that the others abandoned: every workgroup therefore
+// re-reads the status after each wait and leaves if the solve has stalled,
+// and the final status is written only over LP_RUNNING (finish_status), so
+// LP_STALLED is never overwritten.
 __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, uint32_t spin_limit,
-                                             DevState *st, int32_t *s_ok) {
+                                             DevState *st, GroupState *gs, int32_t *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(&gsync->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -684,12 +693,22 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, u
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        if (!ok) atomicExch(&st->status, (int32_t)LP_STALLED);
+        if (!ok) {
+            atomicExch(&st->status, (int32_t)LP_STALLED);
+            atomicExch(&gs->stalled, 1);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (ok && __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == LP_STALLED)
+            ok = false;
         *s_ok = ok;
     }
     __syncthreads();
     return *s_ok != 0;
+}
+
+// The status that ends the solve, written only while it is LP_RUNNING.
+__device__ __forceinline__ void finish_status(DevState *st, int32_t status) {
+    atomicCAS(&st->status, (int32_t)LP_RUNNING, status);
 }
 
 // Steps k < j of a chain (rows: x <- R_k if the row is r_k, else
@@ -852,7 +871,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         block_argmin_dpp<BD>(dv, di, ds, sv_0, si_0, sl_0);
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
-        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
     }
     double frow[KM], rslot[KM];
     int32_t rk[KM];
@@ -883,17 +902,17 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         // (the same decisions in every workgroup: the same partials)
         bool stop = budget;
-        if (!stop && (v != v || v >= -s0.eps_d)) {
-            if (w == 0 && tid == 0) st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+        if (!stop && (step1_bad(v) || v >= -s0.eps_d)) {
+            if (w == 0 && tid == 0) finish_status(st, step1_bad(v) ? LP_NUMERICAL : LP_OPTIMAL);
             stop = true;
         }
         if (!stop && tq < 0) {  // a broken list ends the solve instead of reading outside R
-            if (w == 0 && tid == 0) st->status = LP_NUMERICAL;
+            if (w == 0 && tid == 0) finish_status(st, LP_NUMERICAL);
             stop = true;
         }
         if (stop) {
             if (j == 0) {  // the close is stored once every workgroup has read the list
-                if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+                if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
                 if (w == 0 && tid < 64) store_close();
             }
             break;
@@ -915,12 +934,13 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         for (int k = 0; k < KM; ++k)
             if (k == j) frow[k] = a;
         if (has_row) Fk[(int64_t)j * ld + i] = a;
-        // a NaN (in the column, the RHS or a ratio) becomes a NaN candidate,
-        // which wins the argmin and so reaches the decision as "bad"
+        // a non-finite column entry or a NaN RHS entry (step2_bad) becomes
+        // a NaN candidate, which wins the argmin and so reaches the decision
+        // as "bad"
         double rv = __builtin_inf();
         int32_t r = kNoIndex;
         if (has_row && i >= 1) {
-            if (a != a || bb != bb) {
+            if (step2_bad(a, bb)) {
                 rv = __builtin_nan("");
                 r = i;
             } else if (a > s0.eps_p) {
@@ -940,7 +960,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             rparts[w] = GRatio{rv, r, rv != rv, a, basis_i, (int32_t)inlist_i, bb};
         else if (r == kNoIndex && tid == 0)
             rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0, 0.0};
-        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
         if (j == 0 && w == 0) {  // every workgroup has read the list
             if (tid < 64) store_close();
             __syncthreads();  // before the decision record below
@@ -968,7 +988,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         const int bad_all = rv != rv;
         if (bad_all || r == kNoIndex || s0.pivots + j >= s0.max_pivots) {
             if (w == 0 && tid == 0)
-                st->status = bad_all ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
+                finish_status(st, bad_all ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT));
             break;
         }
         const int32_t aslot = inl ? -1 : n + 1 + napp;  // appended slot of the leaving column
@@ -1046,7 +1066,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         block_argmin_dpp<BD>(dv, di, ds, sv_s, si_s, sl_s);
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
-        if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, &s_ok)) return;
+        if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
     }
 
     // The pivot rows after the group, for every slot: the row of pivot a
@@ -1325,7 +1345,7 @@ __global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int6
                                                     const double *__restrict__ Rk, const double *__restrict__ Fk,
                                                     const GroupState *__restrict__ gs, double *__restrict__ dump,
                                                     int32_t slot0) {
-    if (gs->kdone == 0) return;
+    if (gs->kdone == 0 || gs->stalled) return;
     const int32_t Lv = n + 1 + gs->napp;
     const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
     const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
@@ -1359,7 +1379,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
     constexpr int CG = 256 / NP;        // column groups of the write phase
     constexpr int NR = (KF * TC + 255) / 256;  // R entries per thread to stage
     constexpr int NF = (KF * NP + 255) / 256;  // F pairs per thread to stage
-    const int32_t kd = gs->kdone;
+    const int32_t kd = gs->stalled ? 0 : gs->kdone;  // a stalled group: the build alone
     __shared__ double tile[TR][TC + 1];
     __shared__ double sR[KF][TC];
     __shared__ double2 sF[KF][NP];
@@ -1488,7 +1508,7 @@ static __global__ __launch_bounds__(256) void k_gfix(double *__restrict__ T, int
                                                      const GroupState *__restrict__ gs) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t a = (int32_t)(idx / Lg), t = (int32_t)(idx % Lg);
-    if (a >= gs->kdone || t > n + gs->napp) return;
+    if (a >= gs->kdone || gs->stalled || t > n + gs->napp) return;
     const int32_t c = cols[t];
     if (c >= 0) T[(int64_t)c * ld + gs->r[a]] = PV[idx];
 }

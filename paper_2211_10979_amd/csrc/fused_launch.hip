@@ -144,6 +144,49 @@ void decide_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t
     }
 }
 
+namespace {
+
+template <int BD, int KM>
+int occupancy_pair() {
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, reinterpret_cast<const void *>(&k_gdecide<BD, false, KM>),
+                                                     BD, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(&k_gdecide<BD, true, KM>),
+                                                     BD, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return a < b ? a : b;
+}
+
+template <int BD>
+int occupancy_kf(int KF) {
+    switch (KF) {
+        case 2: return occupancy_pair<BD, 2>();
+        case 4: return occupancy_pair<BD, 4>();
+        case 8: return occupancy_pair<BD, 8>();
+        case 12: return occupancy_pair<BD, 12>();
+        case 16: return occupancy_pair<BD, 16>();
+        default: break;
+    }
+    if constexpr (BD == 256) {
+        switch (KF) {
+            case 24: return occupancy_pair<BD, 24>();
+            case 32: return occupancy_pair<BD, 32>();
+            default: break;
+        }
+    }
+    return 0;
+}
+
+}  // namespace
+
+int decide_blocks_per_cu(int block, int KF) {
+    if (block == 512) return occupancy_kf<512>(KF);
+    if (block == 256) return occupancy_kf<256>(KF);
+    return 0;
+}
+
 void launch_fused_decide(const FusedArgs &a, hipStream_t s) {
     if (a.decide_block == 512)
         decide_kf<512, false>(a, nullptr, nullptr, s);

@@ -66,6 +66,13 @@ inline int32_t select_workgroups_for(int32_t m) {
 // size, with the one-launch decision kernel (the pure pass) or without.
 bool fused_update_supported(int block, int cols, int rv, int K, bool one_launch);
 
+// Workgroups of the one-launch decision kernel (threads `block`, group size
+// instance KF) that one compute unit holds at once, the smaller of its two
+// forms (reading the tableau, or A and c after a deferred build); 0 if the
+// instance does not exist. Its grid barriers need all G workgroups resident,
+// so the kernel is used only while G <= this figure times the compute units.
+int decide_blocks_per_cu(int block, int KF);
+
 // All decisions of a group in one launch (a.decide_wgs > 0).
 void launch_fused_decide(const FusedArgs &a, hipStream_t s);
 

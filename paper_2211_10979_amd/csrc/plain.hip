@@ -198,7 +198,7 @@ void free_ctx(lp_ctx *h) {
     delete h;
 }
 
-int validate_opts(const lp_options &o) {
+int validate_opts(const Options &o) {
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
     if (o.cols_per_block != 0 && !valid_cols(o.cols_per_block))
@@ -239,9 +239,7 @@ constexpr size_t kEarlyStatusBytes = size_t(256) << 20;
 
 // Allocates everything except the inputs; the tableau is not built yet.
 int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
-    lp_options o;
-    lp_options_default(&o);
-    if (opt_in) o = *opt_in;
+    const Options o = resolve_options(opt_in);
     if (int rc = validate_opts(o)) return rc;
     int ndev = 0;
     LP_HIP_CHECK(hipGetDeviceCount(&ndev));
@@ -266,9 +264,13 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     // Groups above kMaxFuseSplit pivots need the one-launch decision kernel
     // (at most kMaxDecideWgs workgroups over the rows and the list).
     const int32_t dblock = o.decide_block > 0 ? o.decide_block : 256;
-    auto one_launch = [&](int K) {  // (512-thread decision workgroups hold groups of at most 16)
-        return o.decide_kernel == 0 && decide_workgroups_for(m, (int64_t)n + 1 + K, dblock) <= kMaxDecideWgs &&
-               (dblock == 256 || K <= kMaxFuseSplit);
+    // (512-thread decision workgroups hold groups of at most 16; the grid
+    // barriers need every decision workgroup resident at once)
+    const int cus = device_cu_count(o.device);
+    auto one_launch = [&](int K) {
+        const int32_t g = decide_workgroups_for(m, (int64_t)n + 1 + K, dblock);
+        return o.decide_kernel == 0 && g <= kMaxDecideWgs && (dblock == 256 || K <= kMaxFuseSplit) &&
+               (int64_t)decide_blocks_per_cu(dblock, fused_update_kf(K)) * cus >= g;
     };
     if (o.fuse_pivots > 0) {
         h->fuse = o.fuse_pivots;
@@ -332,7 +334,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     else
         h->chunk = o.chunk_pivots > 0 ? o.chunk_pivots : 4;
     h->select_wgs = o.select_workgroups > 0 ? o.select_workgroups : 1;
-    h->use_graph = o.use_graph != 0;
+    h->use_graph = o.plain_launches == 0;
     h->timing = o.time_kernels != 0;
     h->eager_build = o.eager_build != 0;
 
@@ -400,7 +402,7 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
         h->decide_block = o.decide_block > 0 ? o.decide_block : 256;
         const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
-        h->decide_wgs = (o.decide_kernel == 0 && g <= kMaxDecideWgs) ? g : 0;
+        h->decide_wgs = one_launch(h->fuse) ? g : 0;
         h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
         const bool can_early = h->decide_wgs > 0 && h->chunk == 1;
         if (o.status_readback == 2 && !can_early)

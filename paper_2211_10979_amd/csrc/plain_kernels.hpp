@@ -154,9 +154,9 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         }
     }
     block_argmin(v, q, sv, si);
-    if (v != v || v >= -s.eps_d) {
+    if (step1_bad(v) || v >= -s.eps_d) {
         if (tid == 0) {
-            st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            st->status = step1_bad(v) ? LP_NUMERICAL : LP_OPTIMAL;
             st->go = 0;
         }
         return;
@@ -175,13 +175,11 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     for (int32_t i = 1 + tid; i <= m; i += nt) {
         const double a = colq[i], bb = rhs[i];
         F[i] = a;
-        if (a != a || bb != bb) {
+        if (step2_bad(a, bb)) {
             bad = 1;
         } else if (a > s.eps_p) {
             const double ratio = bb / a;
-            if (ratio != ratio)
-                bad = 1;
-            else if (lex_less(ratio, i, rv, r)) {
+            if (lex_less(ratio, i, rv, r)) {
                 rv = ratio;
                 r = i;
             }
@@ -265,9 +263,9 @@ static __global__ __launch_bounds__(1024) void k_select_mw(const double *__restr
         }
     }
     block_argmin(v, q, sv, si);
-    if (v != v || v >= -s.eps_d) {
+    if (step1_bad(v) || v >= -s.eps_d) {
         if (w == 0 && tid == 0) {
-            st->status = (v != v) ? LP_NUMERICAL : LP_OPTIMAL;
+            st->status = step1_bad(v) ? LP_NUMERICAL : LP_OPTIMAL;
             st->go = 0;
         }
         return;
@@ -283,13 +281,11 @@ static __global__ __launch_bounds__(1024) void k_select_mw(const double *__restr
     for (int32_t i = i0 + tid; i <= i1; i += nt) {
         const double a = colq[i], bb = rhs[i];
         F[i] = a;
-        if (a != a || bb != bb) {
+        if (step2_bad(a, bb)) {
             bad = 1;
         } else if (a > s.eps_p) {
             const double ratio = bb / a;
-            if (ratio != ratio)
-                bad = 1;
-            else if (lex_less(ratio, i, rv, r)) {
+            if (lex_less(ratio, i, rv, r)) {
                 rv = ratio;
                 r = i;
             }

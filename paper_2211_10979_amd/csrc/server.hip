@@ -195,7 +195,7 @@ struct lp_server {
     hipStream_t sched = nullptr;
     size_t budget = 0;
     int32_t max_slots = 0;
-    lp_options opt{};
+    Options opt{};
     BatchShape shape{};
     int grid = 0;
     size_t lds = 0;
@@ -699,9 +699,7 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
     if (!out) return set_error(LP_E_INVAL, "out is NULL");
     *out = nullptr;
     if (hbm_budget_bytes < ((size_t)1 << 20)) return set_error(LP_E_INVAL, "budget below 1 MiB");
-    lp_options o;
-    lp_options_default(&o);
-    if (opt_in) o = *opt_in;
+    const Options o = resolve_options(opt_in);
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
     int ndev = 0;
@@ -895,8 +893,9 @@ int lp_server_get_pivots(lp_server *s, uint64_t ticket, int32_t *rows, int32_t *
     return LP_OK;
 }
 
-int lp_server_get_stats(lp_server *s, lp_server_stats *st) {
-    if (!s || !st) return set_error(LP_E_INVAL, "NULL argument");
+int lp_server_stats(const lp_server *cs, struct lp_server_stats *st) {
+    if (!cs || !st) return set_error(LP_E_INVAL, "NULL argument");
+    lp_server *s = const_cast<lp_server *>(cs);  // only the lock is taken
     std::lock_guard<std::mutex> lock(s->mu);
     st->submitted = s->submitted;
     st->completed = s->completed;
@@ -915,6 +914,8 @@ int lp_server_get_stats(lp_server *s, lp_server_stats *st) {
     if (s->last_error) return set_error(s->last_error, "a device operation of the server failed");
     return LP_OK;
 }
+
+int lp_server_get_stats(const lp_server *s, struct lp_server_stats *st) { return lp_server_stats(s, st); }
 
 void lp_server_destroy(lp_server *s) {
     if (!s) return;
