@@ -20,7 +20,10 @@
  *     one needed gives LP_ITER_LIMIT;
  *   - Step 3: p = T[r][q]; F = column q before the update; R_j = T[r][j] / p;
  *     T[i][j] = fma(-F_i, R_j, T[i][j]) for i != r; T[r][j] = R_j;
- *   - a NaN met by Step 1 or Step 2 gives LP_NUMERICAL.
+ *   - non-finite values (LP_NUMERICAL): Step 1 stops when row 0 holds a NaN
+ *     or its smallest entry is -inf; Step 2 stops when, in some row 1..m,
+ *     the entering column holds a value that is not finite or the RHS holds
+ *     a NaN (an overflowing ratio is an ordinary infinite ratio).
  * Results: x_j is the RHS of the row where j is basic (0 when nonbasic),
  * y_i = T[0][n+i-1] (the duals), objective = T[0][W-1]. The same LP gives the
  * same pivot sequence alone, in a batch and in the server.
@@ -46,7 +49,7 @@ enum {
     LP_OPTIMAL = 0,    /* Step 1 found no entering column */
     LP_UNBOUNDED = 1,  /* Step 2 found no eligible row */
     LP_ITER_LIMIT = 2, /* max_pivots pivots done, another one needed */
-    LP_NUMERICAL = 3,  /* a NaN reached Step 1 or Step 2 */
+    LP_NUMERICAL = 3,  /* Step 1 or Step 2 met a non-finite value (see the contract above) */
     LP_RUNNING = 4,    /* not finished (lp_step budget ran out, or not solved yet) */
     LP_STALLED = 5     /* a wait of the one-launch decision kernel timed out (its workgroups
                           were not all resident); the solve was abandoned */
@@ -68,21 +71,17 @@ typedef struct lp_ctx lp_ctx;
 typedef struct lp_batch lp_batch;
 typedef struct lp_server lp_server;
 
+/*
+ * Execution and kernel-shape choices. None of them changes a result: every
+ * choice gives the same pivots and bit-identical tableaux. All zero (as
+ * lp_tuning_default sets it) means automatic choices throughout.
+ */
 typedef struct {
-    double eps_dual;        /* enter only if T[0][j] < -eps_dual             (default 1e-9) */
-    double eps_pivot;       /* row eligible only if T[i][q] > eps_pivot       (default 1e-9) */
-    int64_t max_pivots;     /* <= 0 selects 50*(m+n)                          (default 0) */
-    int32_t record_pivots;  /* 1 = keep the (r, q) log                       (default 1) */
-    int32_t device;         /* HIP device ordinal                             (default 0) */
-    void *stream;           /* hipStream_t to run on; NULL = library-owned    (default NULL) */
-    void *device_buffer;    /* optional caller-owned device memory for the tableau, at least
-                               lp_tableau_bytes(m, n) bytes and 256-byte aligned; it must
-                               outlive the context                            (default NULL) */
-    size_t device_buffer_bytes;
     int32_t chunk_pivots;   /* pivots per replay of the captured graph; 0 = auto (4, or one group
                                of fuse_pivots pivots when K > 1) */
     int32_t cols_per_block; /* update kernel: listed columns per workgroup (1, 2, 4, 8, 16; 0 = auto) */
-    int32_t use_graph;      /* 1 = replay a captured hipGraph, 0 = plain launches (default 1) */
+    int32_t plain_launches; /* 1 = launch the kernels directly instead of replaying a captured
+                               hipGraph (default 0) */
     int32_t time_kernels;   /* 1 = time every update kernel with HIP events (lp_get_timing); the
                                kernels are then launched directly, not from a graph (default 0) */
     int32_t rows_per_thread;/* update kernel: row pairs per thread and column (1, 2, 4, 8; 0 = auto) */
@@ -135,6 +134,21 @@ typedef struct {
                                decision kernel, one group per chunk and a tableau of at least
                                256 MiB, else 1. 2 needs the one-launch decision kernel and
                                chunk_pivots 0 or at most fuse_pivots. */
+} lp_tuning;
+
+/* Options of a solve (the fields listed first are the method's own). */
+typedef struct {
+    double eps_dual;        /* enter only if T[0][j] < -eps_dual             (default 1e-9) */
+    double eps_pivot;       /* row eligible only if T[i][q] > eps_pivot       (default 1e-9) */
+    int64_t max_pivots;     /* <= 0 selects 50*(m+n)                          (default 0) */
+    int32_t record_pivots;  /* 1 = keep the (r, q) log                       (default 1) */
+    void *stream;           /* hipStream_t to run on; NULL = library-owned    (default NULL) */
+    void *device_buffer;    /* optional caller-owned device memory for the tableau, at least
+                               lp_tableau_bytes(m, n) bytes and 256-byte aligned; it must
+                               outlive the context                            (default NULL) */
+    size_t device_buffer_bytes;
+    int32_t device;         /* HIP device ordinal                             (default 0) */
+    const lp_tuning *tuning; /* execution choices, read during the call; NULL = defaults */
 } lp_options;
 
 typedef struct {
@@ -172,8 +186,11 @@ const char *lp_error_string(int code);
 /* Text of the last error raised on the calling thread ("" if none). */
 const char *lp_last_error(void);
 
-/* Fills *o with the defaults listed above. LP_E_INVAL if o is NULL. */
+/* Fills *o with the defaults listed above (tuning NULL). LP_E_INVAL if o is NULL. */
 int lp_options_default(lp_options *o);
+
+/* Fills *t with the automatic choices (all zero). LP_E_INVAL if t is NULL. */
+int lp_tuning_default(lp_tuning *t);
 
 /* Device bytes of the tableau for an m x n LP (0 if m or n < 1). */
 size_t lp_tableau_bytes(int32_t m, int32_t n);
@@ -213,7 +230,7 @@ int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double
 
 /*
  * Runs Steps 1-3 until the LP is optimal, unbounded, hits max_pivots or meets
- * a NaN. Blocks until done. LP_OK means it ran; the outcome is in
+ * a non-finite value. Blocks until done. LP_OK means it ran; the outcome is in
  * lp_get_solution's status.
  */
 int lp_solve(lp_ctx *h);
@@ -355,7 +372,7 @@ void lp_batch_destroy(lp_batch *bt);
  * memory reused.
  */
 
-typedef struct {
+struct lp_server_stats {
     int64_t submitted;
     int64_t completed;
     int64_t rejected;
@@ -365,7 +382,7 @@ typedef struct {
     int64_t ticks;             /* scheduler iterations that launched work */
     double p50_ms, p99_ms;     /* latency, submit to completion, over completed requests */
     double mean_ms;
-} lp_server_stats;
+};
 
 /*
  * hbm_budget_bytes: ceiling on resident tableau bytes; max_slots: most LPs
@@ -393,7 +410,13 @@ int lp_server_wait(lp_server *s, uint64_t ticket, lp_result *res, double *x, dou
 /* Pivot log of a finished, not yet collected request. */
 int lp_server_get_pivots(lp_server *s, uint64_t ticket, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
 
-int lp_server_get_stats(lp_server *s, lp_server_stats *st);
+/* Counters and latency percentiles so far, a snapshot into *st (thread-safe).
+ * The record is `struct lp_server_stats` (a tag of the same name as the call,
+ * as with POSIX stat). */
+int lp_server_stats(const lp_server *s, struct lp_server_stats *st);
+
+/* The same as lp_server_stats (the earlier name). */
+int lp_server_get_stats(const lp_server *s, struct lp_server_stats *st);
 
 /* Drains every queued request, then stops the scheduler and frees everything. NULL-safe. */
 void lp_server_destroy(lp_server *s);

@@ -35,19 +35,12 @@ class LPError(RuntimeError):
         self.code = code
 
 
-class lp_options(ctypes.Structure):
+class lp_tuning(ctypes.Structure):
+    """Execution and kernel-shape choices (none changes a result); all zero = automatic."""
     _fields_ = [
-        ("eps_dual", ctypes.c_double),
-        ("eps_pivot", ctypes.c_double),
-        ("max_pivots", ctypes.c_int64),
-        ("record_pivots", ctypes.c_int32),
-        ("device", ctypes.c_int32),
-        ("stream", ctypes.c_void_p),
-        ("device_buffer", ctypes.c_void_p),
-        ("device_buffer_bytes", ctypes.c_size_t),
         ("chunk_pivots", ctypes.c_int32),
         ("cols_per_block", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("plain_launches", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32),
         ("batch_block", ctypes.c_int32),
@@ -63,6 +56,23 @@ class lp_options(ctypes.Structure):
         ("decide_block", ctypes.c_int32),
         ("eager_build", ctypes.c_int32),
         ("status_readback", ctypes.c_int32),
+    ]
+
+
+TUNING_FIELDS = frozenset(name for name, _ in lp_tuning._fields_)
+
+
+class lp_options(ctypes.Structure):
+    _fields_ = [
+        ("eps_dual", ctypes.c_double),
+        ("eps_pivot", ctypes.c_double),
+        ("max_pivots", ctypes.c_int64),
+        ("record_pivots", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("device_buffer", ctypes.c_void_p),
+        ("device_buffer_bytes", ctypes.c_size_t),
+        ("device", ctypes.c_int32),
+        ("tuning", ctypes.POINTER(lp_tuning)),
     ]
 
 
@@ -110,7 +120,8 @@ class lp_timing(ctypes.Structure):
     ]
 
 
-class lp_server_stats(ctypes.Structure):
+class lp_server_stats_t(ctypes.Structure):
+    """struct lp_server_stats."""
     _fields_ = [
         ("submitted", ctypes.c_int64),
         ("completed", ctypes.c_int64),
@@ -139,6 +150,7 @@ SIGNATURES = {
     "lp_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lp_last_error": (ctypes.c_char_p, []),
     "lp_options_default": (ctypes.c_int, [_OPT]),
+    "lp_tuning_default": (ctypes.c_int, [ctypes.POINTER(lp_tuning)]),
     "lp_tableau_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "lp_create": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _OPT]),
     "lp_create_device": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _OPT]),
@@ -170,7 +182,8 @@ SIGNATURES = {
     "lp_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _RES, _D, _D]),
     "lp_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, _RES, _D, _D]),
     "lp_server_get_pivots": (ctypes.c_int, [_P, ctypes.c_uint64, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_int64)]),
-    "lp_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lp_server_stats)]),
+    "lp_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(lp_server_stats_t)]),
+    "lp_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lp_server_stats_t)]),
     "lp_server_destroy": (None, [_P]),
 }
 
@@ -230,13 +243,27 @@ def lp_tableau_bytes(m: int, n: int) -> int:
     return library().lp_tableau_bytes(m, n)
 
 
+def lp_tuning_default(**overrides) -> lp_tuning:
+    t = lp_tuning()
+    _check(library().lp_tuning_default(ctypes.byref(t)), "lp_tuning_default")
+    for k, v in overrides.items():
+        setattr(t, k, v)
+    return t
+
+
 def lp_options_default(**overrides) -> lp_options:
     """Default options with keyword overrides. `stream` and `device_buffer`
-    may be torch objects (a torch.cuda.Stream, a CUDA tensor)."""
+    may be torch objects (a torch.cuda.Stream, a CUDA tensor). Names of
+    lp_tuning fields go into a tuning record that the options point to (kept
+    alive by the returned object)."""
     o = lp_options()
     _check(library().lp_options_default(ctypes.byref(o)), "lp_options_default")
+    tun = {k: v for k, v in overrides.items() if k in TUNING_FIELDS and v is not None}
+    if tun:
+        o._tuning = lp_tuning_default(**tun)
+        o.tuning = ctypes.pointer(o._tuning)
     for k, v in overrides.items():
-        if v is None:
+        if v is None or k in TUNING_FIELDS:
             continue
         if k == "stream" and hasattr(v, "cuda_stream"):
             v = v.cuda_stream
@@ -479,10 +506,13 @@ def lp_server_get_pivots(h, ticket):
     return rows[:k].copy(), cols[:k].copy()
 
 
-def lp_server_get_stats(h) -> dict:
-    st = lp_server_stats()
-    _check(library().lp_server_get_stats(h, ctypes.byref(st)), "lp_server_get_stats")
-    return {name: getattr(st, name) for name, _ in lp_server_stats._fields_}
+def lp_server_stats(h) -> dict:
+    st = lp_server_stats_t()
+    _check(library().lp_server_stats(h, ctypes.byref(st)), "lp_server_stats")
+    return {name: getattr(st, name) for name, _ in lp_server_stats_t._fields_}
+
+
+lp_server_get_stats = lp_server_stats
 
 
 def lp_server_destroy(h):

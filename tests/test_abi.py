@@ -35,6 +35,34 @@ def test_header_declares_the_boundary():
         assert must in names
 
 
+# The boundary's entry points and the leading option fields, in this order.
+BOUNDARY_CALLS = ["lp_options_default", "lp_tableau_bytes", "lp_create", "lp_solve", "lp_get_solution",
+                  "lp_get_pivots", "lp_destroy", "lp_error_string", "lp_batch_create", "lp_batch_solve",
+                  "lp_batch_get_solution", "lp_batch_get_pivots", "lp_batch_destroy", "lp_server_create",
+                  "lp_server_submit", "lp_server_poll", "lp_server_stats", "lp_server_destroy"]
+BOUNDARY_OPTIONS = ["eps_dual", "eps_pivot", "max_pivots", "record_pivots", "stream", "device_buffer",
+                    "device_buffer_bytes"]
+
+
+def struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", text).group(1)
+    return re.findall(r"(\w+)\s*;", body)
+
+
+def test_boundary_names_and_option_order():
+    names = declared_functions()
+    assert [n for n in BOUNDARY_CALLS if n not in names] == []
+    fields = struct_fields("lp_options")
+    assert fields[:len(BOUNDARY_OPTIONS)] == BOUNDARY_OPTIONS
+    assert fields[len(BOUNDARY_OPTIONS):] == ["device", "tuning"]
+
+
+def test_binding_layout_matches_the_header(lpgpu):
+    assert [f for f, _ in lpgpu.lp_options._fields_] == struct_fields("lp_options")
+    assert [f for f, _ in lpgpu.lp_tuning._fields_] == struct_fields("lp_tuning")
+
+
 def test_every_declared_symbol_is_exported(lpgpu):
     lib = ctypes.CDLL(lpgpu.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
@@ -51,8 +79,13 @@ def test_host_only_entry_points(lpgpu):
     assert lib.lp_error_string(lpgpu.LP_E_NEG_RHS)
     assert lib.lp_error_string(12345) == b"unknown code"
     o = lpgpu.lp_options_default()
-    assert o.eps_dual == 1e-9 and o.eps_pivot == 1e-9 and o.record_pivots == 1 and o.use_graph == 1
+    assert o.eps_dual == 1e-9 and o.eps_pivot == 1e-9 and o.record_pivots == 1 and not o.tuning
     assert lib.lp_options_default(None) == lpgpu.LP_E_INVAL
+    t = lpgpu.lp_tuning_default()
+    assert all(getattr(t, name) == 0 for name in lpgpu.TUNING_FIELDS)
+    assert lib.lp_tuning_default(None) == lpgpu.LP_E_INVAL
+    o = lpgpu.lp_options_default(fuse_pivots=4, eps_dual=1e-7)
+    assert o.eps_dual == 1e-7 and o.tuning and o.tuning.contents.fuse_pivots == 4
     # tableau bytes: ld = m+1 rounded up to 16 doubles, W = n+m+1 columns
     assert lpgpu.lp_tableau_bytes(8000, 8000) == 8016 * 16001 * 8
     assert lpgpu.lp_tableau_bytes(15, 3) == 16 * 19 * 8

@@ -287,10 +287,20 @@ def test_status_readback_counters_and_choice():
             t = lpgpu.lp_get_timing(d.h)
             idle = t["update_launches"] - t["applied_launches"]
             assert idle in ((0, 1) if rb == 2 else (1, 2)), (rb, t)
-            out[rb] = (res, x, y, lpgpu.lp_get_tableau(d.h), lpgpu.lp_get_pivots(d.h))
+            out[rb] = (res, x, y, lpgpu.lp_get_tableau(d.h), lpgpu.lp_get_pivots(d.h), t)
+            # the work counters after a pivot budget (read back with the state)
+            d.reload(lp.A, lp.b, lp.c)
+            lpgpu.lp_step(d.h, 5)
+            lpgpu.lp_step(d.h, 30)
+            out[rb] += (lpgpu.lp_get_timing(d.h),)
         finally:
             d.close()
-    (r1, x1, y1, T1, l1), (r2, x2, y2, T2, l2) = out[1], out[2]
+    (r1, x1, y1, T1, l1, t1, s1), (r2, x2, y2, T2, l2, t2, s2) = out[1], out[2]
+    # every work counter agrees between the two read-back modes: the
+    # roofline bytes of the benchmark are computed from them
+    for key in ("pivots", "updated_columns", "first_pass_pivots", "first_pass_changed", "first_pass_columns"):
+        assert t1[key] == t2[key], (key, t1[key], t2[key])
+        assert s1[key] == s2[key], (key, s1[key], s2[key])
     assert r1["pivots"] == r2["pivots"] and r1["objective"] == r2["objective"]
     assert np.array_equal(x1, x2) and np.array_equal(y1, y2) and np.array_equal(T1, T2)
     assert l1[0].tolist() == l2[0].tolist() and l1[1].tolist() == l2[1].tolist()

@@ -148,7 +148,7 @@ def test_dense_2000_full_solve(K, decide):
                                   dict(rows_per_thread=1), dict(update_block=128, cols_per_block=4, fuse_pivots=3),
                                   dict(update_block=64, cols_per_block=8),
                                   dict(update_block=128, cols_per_block=1), dict(update_block=64, cols_per_block=2),
-                                  dict(use_graph=0), dict(chunk_pivots=9), dict(time_kernels=1),
+                                  dict(plain_launches=1), dict(chunk_pivots=9), dict(time_kernels=1),
                                   dict(cols_per_block=2, fuse_pivots=8), dict(cols_per_block=4, fuse_pivots=6),
                                   dict(cols_per_block=8, fuse_pivots=7),
                                   dict(cols_per_block=4, fuse_pivots=8, time_kernels=1),

@@ -229,7 +229,7 @@ def test_general_row_layout_large_m():
                                   dict(update_grid_stride=8, update_unroll=8, update_block=512),
                                   dict(update_block=128, cols_per_block=2), dict(update_block=1024, cols_per_block=1),
                                   dict(select_workgroups=2), dict(select_workgroups=7), dict(select_workgroups=64),
-                                  dict(use_graph=0), dict(chunk_pivots=1), dict(chunk_pivots=33)])
+                                  dict(plain_launches=1), dict(chunk_pivots=1), dict(chunk_pivots=33)])
 def test_launch_options_do_not_change_results(opts):
     A, b, c = rand_lp(5, 333, 444, 1, 9, signed=True)
     g = lpgpu.solve(A, b, c, **opts)
@@ -358,7 +358,7 @@ def test_work_counter_and_kernel_timing():
         o.close()
 
 
-@pytest.mark.parametrize("opts", [dict(time_kernels=1), dict(time_kernels=1, use_graph=0)])
+@pytest.mark.parametrize("opts", [dict(time_kernels=1), dict(time_kernels=1, plain_launches=1)])
 def test_timing_mode_keeps_results(opts):
     lp = lpgen.dense_lp(5, 900, 1100)
     g = lpgpu.solve(lp.A, lp.b, lp.c, **opts)
