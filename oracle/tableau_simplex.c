@@ -51,7 +51,7 @@
 #include <omp.h>
 #endif
 
-enum { OR_OPTIMAL = 0, OR_UNBOUNDED = 1, OR_ITER_LIMIT = 2, OR_NUMERICAL = 3, OR_RUNNING = 4 };
+enum { OR_OPTIMAL = 0, OR_UNBOUNDED = 1, OR_ITER_LIMIT = 2, OR_NUMERICAL = 3, OR_RUNNING = 4, OR_INFEASIBLE = 6 };
 
 typedef struct {
     int m, n, W;
@@ -66,6 +66,16 @@ typedef struct {
     int *log_r, *log_q;
     int64_t log_cap;
     int nthreads;
+    /* general form only (oracle_create_general); see that section */
+    int general;
+    int m_in, n_in;   /* the caller's rows and variables */
+    int nprime;       /* structural plus surplus columns */
+    int n_le;         /* tableau rows 1..n_le are <= rows (after sign normalisation) */
+    int bar;          /* columns >= bar never enter; rows whose basic column is >= bar never leave */
+    int phase;        /* 1, 2, or 3 when finished */
+    int *perm;        /* tableau row t+1 holds the caller's row perm[t] */
+    double *sign;     /* ... multiplied by sign[t] (-1 where b < 0) */
+    double feas_scale;
 } oracle_lp;
 
 #define TAB(o, i, j) ((o)->T[(size_t)(i) * (size_t)(o)->W + (size_t)(j)])
@@ -79,6 +89,8 @@ void oracle_destroy(oracle_lp *o)
     free(o->basis);
     free(o->log_r);
     free(o->log_q);
+    free(o->perm);
+    free(o->sign);
     free(o);
 }
 
@@ -256,4 +268,300 @@ void oracle_extract(const oracle_lp *o, double *x, double *y, double *objective)
     if (y)
         for (int i = 1; i <= m; ++i) y[i - 1] = TAB(o, 0, n + i - 1);
     if (objective) *objective = TAB(o, 0, W - 1);
+}
+
+/* ------------------------------------------------------------------------
+ * General form: rows A_i x <= b_i, >= b_i or = b_i, any sign of b, x >= 0,
+ * by the two-phase method. The paper's Initialization Step starts from a
+ * feasible basis (the slack basis of the standard form); this section builds
+ * one where there is none, as textbooks do, then runs the paper's Steps 1-3
+ * unchanged.
+ *
+ * Construction (every choice below is a reading; the paper has none):
+ *   sign      a row with b_i < 0 is multiplied by -1 (<= and >= swap, =
+ *             stays), so every right-hand side is >= 0;
+ *   order     tableau rows 1..m are the <= rows, then the >= rows, then the
+ *             = rows, each group in the caller's order;
+ *   columns   the n structural variables, one surplus variable per >= row
+ *             (coefficient -1 in its row; columns n .. n'-1, n' = n + #>=),
+ *             then one identity column per row (n'+t-1 for tableau row t:
+ *             the slack of a <= row, the artificial variable of a >= or =
+ *             row), then one more identity column n'+m for row m+1, then
+ *             the right-hand side: W = n' + m + 2 columns;
+ *   rows      row m+1 carries the caller's objective through Phase I,
+ *             [-c | 0 | e_{m+1} | 0], updated by every pivot like any row;
+ *             row 0 is Phase I's objective (maximise minus the sum of the
+ *             artificial variables), priced out: start from 1 under each
+ *             artificial column and 0 elsewhere, then subtract the
+ *             artificial rows one by one in row order;
+ *   basis     column n'+t-1 in row t, for t = 1..m+1.
+ * Phase I     Steps 1-3 with entering columns j < n'+m (every column but
+ *             row m+1's own) and leaving rows whose basic column is < n'+m
+ *             (every row but row m+1).
+ * Feasibility after an OPTIMAL Phase I: infeasible when the objective
+ *             T[0][W-1] (minus the sum of the artificial variables) is below
+ *             -1e-9 * max(1, sum of the artificial rows' b), the sum taken
+ *             in row order.
+ * Drive-out   for t = 1..m in order, where an artificial variable is still
+ *             basic: pivot on (t, j) for the lowest column j < n'+n_le (not
+ *             artificial) with |T[t][j]| > eps_p; if there is none the row
+ *             is redundant and its artificial variable stays basic (at
+ *             zero), its row never leaving in Phase II.
+ * Phase II    rows 0 and m+1 trade places; Steps 1-3 with entering columns
+ *             j < n'+n_le (no artificial column enters) and leaving rows
+ *             whose basic column is < n'+n_le.
+ * One pivot counter and one log cover both phases and the drive-out.
+ * Results     x_j = RHS of the row where j < n is basic; the dual of the
+ *             caller's row k, in tableau row t: sign[t] * T[0][n'+t-1];
+ *             objective T[0][W-1].
+ */
+
+#define OR_FEAS_TOL 1e-9
+
+/* Step 1 over the columns j < bar. -1 optimal, -2 NaN or -inf. */
+static int choose_entering_general(const oracle_lp *o)
+{
+    int q = 0;
+    double best = TAB(o, 0, 0);
+    for (int j = 0; j < o->bar; ++j) {
+        double v = TAB(o, 0, j);
+        if (isnan(v)) return -2;
+        if (v < best) {
+            best = v;
+            q = j;
+        }
+    }
+    if (best == -INFINITY) return -2;
+    if (best >= -o->eps_d) return -1;
+    return q;
+}
+
+/* Step 2 over the rows whose basic column is < bar; the non-finite check
+ * covers every row 1..m. -1 unbounded, -2 non-finite. */
+static int choose_leaving_general(const oracle_lp *o, int q)
+{
+    const int W = o->W;
+    int r = -1;
+    double best = 0.0;
+    for (int i = 1; i <= o->m; ++i) {
+        double a = TAB(o, i, q);
+        double rhs = TAB(o, i, W - 1);
+        if (!isfinite(a) || isnan(rhs)) return -2;
+        if (a > o->eps_p && o->basis[i - 1] < o->bar) {
+            double ratio = rhs / a;
+            if (r < 0 || ratio < best) {
+                best = ratio;
+                r = i;
+            }
+        }
+    }
+    return r;
+}
+
+/* Logs pivot (r, q) and counts it. */
+static void log_pivot(oracle_lp *o, int r, int q)
+{
+    if (o->pivots < o->log_cap) {
+        o->log_r[o->pivots] = r;
+        o->log_q[o->pivots] = q;
+    }
+    o->pivots++;
+}
+
+/* sense: 0 for <=, 1 for >=, 2 for =. Returns NULL on bad input (m or n < 1,
+ * a non-finite value, an unknown sense). */
+oracle_lp *oracle_create_general(int m, int n, const double *A, const double *b, const double *c,
+                                 const int *sense, double eps_d, double eps_p, int64_t max_pivots,
+                                 int64_t log_cap, int nthreads)
+{
+    if (m < 1 || n < 1 || !A || !b || !c || !sense) return NULL;
+    for (int64_t k = 0; k < (int64_t)m * n; ++k)
+        if (!isfinite(A[k])) return NULL;
+    for (int i = 0; i < m; ++i)
+        if (!isfinite(b[i]) || sense[i] < 0 || sense[i] > 2) return NULL;
+    for (int j = 0; j < n; ++j)
+        if (!isfinite(c[j])) return NULL;
+
+    /* normalised sense of each caller row and the tableau order */
+    int *kind = (int *)calloc((size_t)m, sizeof(int));
+    if (!kind) return NULL;
+    int n_le = 0, n_ge = 0;
+    for (int i = 0; i < m; ++i) {
+        int k = sense[i];
+        if (b[i] < 0.0 && k != 2) k = 1 - k;
+        kind[i] = k;
+        n_le += k == 0;
+        n_ge += k == 1;
+    }
+    const int np = n + n_ge;
+    const int M = m + 1; /* constraint rows and the carried objective row */
+    oracle_lp *o = (oracle_lp *)calloc(1, sizeof(oracle_lp));
+    if (!o) {
+        free(kind);
+        return NULL;
+    }
+    o->m = M;
+    o->n = np;
+    o->W = np + M + 1;
+    o->T = (double *)calloc((size_t)(M + 1) * (size_t)o->W, sizeof(double));
+    o->F = (double *)calloc((size_t)M + 1, sizeof(double));
+    o->R = (double *)calloc((size_t)o->W, sizeof(double));
+    o->basis = (int *)calloc((size_t)M, sizeof(int));
+    o->perm = (int *)calloc((size_t)m, sizeof(int));
+    o->sign = (double *)calloc((size_t)m, sizeof(double));
+    o->log_cap = log_cap > 0 ? log_cap : 0;
+    if (o->log_cap) {
+        o->log_r = (int *)calloc((size_t)o->log_cap, sizeof(int));
+        o->log_q = (int *)calloc((size_t)o->log_cap, sizeof(int));
+    }
+    if (!o->T || !o->F || !o->R || !o->basis || !o->perm || !o->sign ||
+        (o->log_cap && (!o->log_r || !o->log_q))) {
+        free(kind);
+        oracle_destroy(o);
+        return NULL;
+    }
+    o->eps_d = eps_d;
+    o->eps_p = eps_p;
+    o->max_pivots = max_pivots;
+    o->nthreads = nthreads > 0 ? nthreads : 1;
+    o->status = OR_RUNNING;
+    o->general = 1;
+    o->m_in = m;
+    o->n_in = n;
+    o->nprime = np;
+    o->n_le = n_le;
+    o->phase = 1;
+    o->bar = np + m;
+
+    int t = 0;
+    for (int want = 0; want < 3; ++want)
+        for (int i = 0; i < m; ++i)
+            if (kind[i] == want) {
+                o->perm[t] = i;
+                o->sign[t] = b[i] < 0.0 ? -1.0 : 1.0;
+                ++t;
+            }
+    free(kind);
+
+    const int W = o->W;
+    int surplus = n;
+    for (int t1 = 1; t1 <= m; ++t1) {
+        const int k = o->perm[t1 - 1];
+        const double s = o->sign[t1 - 1];
+        for (int j = 0; j < n; ++j) TAB(o, t1, j) = s == 1.0 ? A[(size_t)k * n + j] : -A[(size_t)k * n + j];
+        if (t1 > n_le && t1 <= n_le + n_ge) TAB(o, t1, surplus++) = -1.0;
+        TAB(o, t1, np + t1 - 1) = 1.0;
+        TAB(o, t1, W - 1) = s == 1.0 ? b[k] : -b[k];
+        o->basis[t1 - 1] = np + t1 - 1;
+    }
+    for (int j = 0; j < n; ++j) TAB(o, M, j) = -c[j];
+    TAB(o, M, np + m) = 1.0;
+    o->basis[M - 1] = np + m;
+    /* Phase I's objective row, priced out */
+    for (int j = 0; j < W; ++j) TAB(o, 0, j) = (j >= np + n_le && j < np + m) ? 1.0 : 0.0;
+    double scale = 0.0;
+    for (int t1 = n_le + 1; t1 <= m; ++t1) {
+        for (int j = 0; j < W; ++j) TAB(o, 0, j) = TAB(o, 0, j) - TAB(o, t1, j);
+        scale = scale + TAB(o, t1, W - 1);
+    }
+    o->feas_scale = scale > 1.0 ? scale : 1.0;
+    return o;
+}
+
+/* Steps 1-3 until the phase ends (or the cap). */
+static void run_phase(oracle_lp *o)
+{
+    while (o->status == OR_RUNNING) {
+        int q = choose_entering_general(o);
+        if (q == -1) { o->status = OR_OPTIMAL; break; }
+        if (q == -2) { o->status = OR_NUMERICAL; break; }
+        int r = choose_leaving_general(o, q);
+        if (r == -1) { o->status = OR_UNBOUNDED; break; }
+        if (r == -2) { o->status = OR_NUMERICAL; break; }
+        if (o->pivots >= o->max_pivots) { o->status = OR_ITER_LIMIT; break; }
+        pivot(o, r, q);
+        log_pivot(o, r, q);
+    }
+}
+
+/* Both phases. Returns the final status. */
+int oracle_solve_general(oracle_lp *o)
+{
+    if (!o->general || o->phase != 1) return o->status;
+    const int m = o->m_in, np = o->nprime, W = o->W;
+    run_phase(o);
+    if (o->status != OR_OPTIMAL) {
+        o->phase = 3;
+        return o->status;
+    }
+    const double w = TAB(o, 0, W - 1);
+    if (isnan(w)) {
+        o->status = OR_NUMERICAL;
+        o->phase = 3;
+        return o->status;
+    }
+    if (w < -OR_FEAS_TOL * o->feas_scale) {
+        o->status = OR_INFEASIBLE;
+        o->phase = 3;
+        return o->status;
+    }
+    /* drive the artificial variables still basic out of the basis */
+    const int allowed = np + o->n_le;
+    for (int t = 1; t <= m; ++t) {
+        if (o->basis[t - 1] < allowed) continue;
+        int q = -1;
+        for (int j = 0; j < allowed; ++j)
+            if (fabs(TAB(o, t, j)) > o->eps_p) {
+                q = j;
+                break;
+            }
+        if (q < 0) continue; /* redundant row */
+        if (o->pivots >= o->max_pivots) {
+            o->status = OR_ITER_LIMIT;
+            o->phase = 3;
+            return o->status;
+        }
+        pivot(o, t, q);
+        log_pivot(o, t, q);
+    }
+    /* Phase II: the carried objective becomes row 0 */
+    for (int j = 0; j < W; ++j) {
+        const double v = TAB(o, 0, j);
+        TAB(o, 0, j) = TAB(o, m + 1, j);
+        TAB(o, m + 1, j) = v;
+    }
+    o->bar = allowed;
+    o->phase = 2;
+    o->status = OR_RUNNING;
+    run_phase(o);
+    o->phase = 3;
+    return o->status;
+}
+
+/* x (n_in), y (m_in, the caller's row order) and the objective. */
+void oracle_extract_general(const oracle_lp *o, double *x, double *y, double *objective)
+{
+    const int m = o->m_in, np = o->nprime, W = o->W;
+    if (x) {
+        for (int j = 0; j < o->n_in; ++j) x[j] = 0.0;
+        for (int t = 1; t <= m; ++t)
+            if (o->basis[t - 1] < o->n_in) x[o->basis[t - 1]] = TAB(o, t, W - 1);
+    }
+    if (y)
+        for (int t = 1; t <= m; ++t) {
+            const double v = TAB(o, 0, np + t - 1);
+            y[o->perm[t - 1]] = o->sign[t - 1] == 1.0 ? v : -v;
+        }
+    if (objective) *objective = TAB(o, 0, W - 1);
+}
+
+/* The layout of a general-form tableau: n', n_le, the phase reached, and the
+ * caller's row of each tableau row with its sign. */
+void oracle_general_layout(const oracle_lp *o, int *nprime, int *n_le, int *phase, int *perm, double *sign)
+{
+    if (nprime) *nprime = o->nprime;
+    if (n_le) *n_le = o->n_le;
+    if (phase) *phase = o->phase;
+    if (perm) memcpy(perm, o->perm, (size_t)o->m_in * sizeof(int));
+    if (sign) memcpy(sign, o->sign, (size_t)o->m_in * sizeof(double));
 }
