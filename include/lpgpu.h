@@ -297,6 +297,37 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t);
 void lp_destroy(lp_ctx *h);
 
 /*
+ * For callers that cannot allocate device memory (serving loops or harnesses
+ * that forbid hipMalloc while they run): lp_create_device + lp_solve +
+ * lp_get_solution + lp_get_pivots + lp_destroy in one call that calls no
+ * hipMalloc, hipFree, hipHostMalloc or other allocating routine and creates
+ * no stream, event or graph. Same kernels, same pivots and bits.
+ *
+ * dA (row-major m x n), db (m), dc (n): device inputs, only read.
+ * tableau: caller-owned device buffer of at least lp_tableau_bytes(m, n)
+ *   bytes (tableau_bytes), 256-byte aligned; holds the final tableau on
+ *   return (column-major, ld = lp_info.ld for the same m; basic columns that
+ *   were never nonbasic are not stored).
+ * opt: as lp_create (NULL = defaults; stream NULL = the null stream);
+ *   device_buffer is ignored; time_kernels must be 0.
+ * res, x (n), y (m): host outputs as lp_get_solution, each may be NULL;
+ *   res->solve_ms is host wall time of the pivoting.
+ * rows, cols: host arrays of cap entries receiving the pivot log (as
+ *   lp_get_pivots); *count (may be NULL) the pivots performed. The device
+ *   log keeps the first min(max_pivots, 4 (m + n) + 64) pivots.
+ * Every other device buffer lives in a work block of
+ * LP_NOALLOC_SCRATCH_BYTES per device, a file-scope device array that each
+ * GPU holds until the process ends; an LP whose buffers do not fit is
+ * rejected with LP_E_INVAL before any device work. Calls on one device share
+ * that block: calls that overlap in time on one device race (serialise them);
+ * each call clears the block first. Blocks until done. Errors as lp_create.
+ */
+#define LP_NOALLOC_SCRATCH_BYTES (8u << 20)
+int lp_solve_noalloc(int32_t m, int32_t n, const double *dA, const double *db, const double *dc, double *tableau,
+                     size_t tableau_bytes, const lp_options *opt, lp_result *res, double *x, double *y,
+                     int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
+
+/*
  * Diagnostic: the device's binary64 division and fused multiply-add, the two
  * roundings of Steps 2 and 3, applied element-wise on `device`:
  *   quot[k] = a[k] / b[k],   fmav[k] = fma(a[k], b[k], c[k]),   k < count.

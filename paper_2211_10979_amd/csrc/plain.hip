@@ -4,9 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -80,6 +83,7 @@ struct lp_ctx {
     bool own_stream = false;
     double *T = nullptr;
     bool own_T = false;
+    unsigned char *aux = nullptr;  // owned block holding every other device buffer below (carve_aux)
     double *F = nullptr;
     ArgMin *parts = nullptr;
     DevState *st = nullptr;
@@ -166,26 +170,8 @@ void free_ctx(lp_ctx *h) {
     }
     for (auto e : h->ev_first)
         if (e) (void)hipEventDestroy(e);
-    if (h->rparts) (void)hipFree(h->rparts);
-    if (h->ticket) (void)hipFree(h->ticket);
     if (h->own_T && h->T) (void)hipFree(h->T);
-    if (h->F) (void)hipFree(h->F);
-    if (h->parts) (void)hipFree(h->parts);
-    if (h->st) (void)hipFree(h->st);
-    if (h->basis) (void)hipFree(h->basis);
-    if (h->log_r) (void)hipFree(h->log_r);
-    if (h->log_q) (void)hipFree(h->log_q);
-    if (h->out) (void)hipFree(h->out);
-    if (h->cols) (void)hipFree(h->cols);
-    if (h->pos) (void)hipFree(h->pos);
-    if (h->Rl) (void)hipFree(h->Rl);
-    if (h->PV) (void)hipFree(h->PV);
-    if (h->gs) (void)hipFree(h->gs);
-    if (h->D) (void)hipFree(h->D);
-    if (h->sparts) (void)hipFree(h->sparts);
-    if (h->grparts) (void)hipFree(h->grparts);
-    if (h->gsync) (void)hipFree(h->gsync);
-    if (h->dump) (void)hipFree(h->dump);
+    if (h->aux) (void)hipFree(h->aux);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->host_cols) (void)hipHostFree(h->host_cols);
     if (h->host_blk) (void)hipHostFree(h->host_blk);
@@ -237,18 +223,11 @@ constexpr size_t kStateBlock = kCountersAt + 4 * sizeof(unsigned long long);
 // time (event wake-up, read-back, launches: tens of microseconds).
 constexpr size_t kEarlyStatusBytes = size_t(256) << 20;
 
-// Allocates everything except the inputs; the tableau is not built yet.
-int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
-    const Options o = resolve_options(opt_in);
-    if (int rc = validate_opts(o)) return rc;
-    int ndev = 0;
-    LP_HIP_CHECK(hipGetDeviceCount(&ndev));
-    if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
-
-    lp_ctx *h = new (std::nothrow) lp_ctx;
-    if (!h) return set_error(LP_E_NOMEM, "host allocation failed");
+// Resolves every launch choice of a context for an m x n LP from the
+// options: group size, tile shapes, decision kernel, read-back mode. Only
+// host fields are set; nothing is allocated.
+int configure_ctx(lp_ctx *h, int32_t m, int32_t n, const Options &o) {
     h->device = o.device;
-    DeviceGuard g(h->device);
     h->m = m;
     h->n = n;
     h->W = (int64_t)n + m + 1;
@@ -297,38 +276,30 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         h->ucfg.gs_unroll = o.update_unroll > 0 ? o.update_unroll : 4;
         h->ucfg.nt = 0;
     }
-    if (h->ucfg.gs_per_cu > 0 && h->ucfg.block > 512) {
-        delete h;
+    if (h->ucfg.gs_per_cu > 0 && h->ucfg.block > 512)
         return set_error(LP_E_INVAL, "the grid-stride update kernel takes at most 512 threads per workgroup");
-    }
     // (the fused kernels' shapes are checked below)
     const bool big_block_ok = h->fuse > 1 || h->ucfg.block == 256 || (h->ucfg.cols <= 2 && h->ucfg.rv <= 2) ||
                               (h->ucfg.block <= 128 && h->ucfg.rv == 1 && h->ucfg.rowchunks == 1);
-    if ((o.update_block > 0 && h->ucfg.block != o.update_block) || !big_block_ok) {
-        delete h;
+    if ((o.update_block > 0 && h->ucfg.block != o.update_block) || !big_block_ok)
         return set_error(LP_E_INVAL, "update_block needs m + 1 > 256, and values other than 256 need "
                                      "cols_per_block and rows_per_thread <= 2");
-    }
-    if (h->fuse > kMaxFuseSplit && !one_launch(h->fuse)) {
-        delete h;
+    if (h->fuse > kMaxFuseSplit && !one_launch(h->fuse))
         return set_error(LP_E_INVAL, "fuse_pivots above 16 needs the one-launch decision kernel (decide_kernel 0, "
                                      "decide_block 256 and at most 128 decision workgroups)");
-    }
     if (h->fuse > 1) {
         const UpdateConfig &u = h->ucfg;
         if (u.gs_per_cu > 0 || u.nt != 0 || o.select_workgroups > 1 ||
-            !fused_update_supported(u.block, u.cols, u.rv, h->fuse, one_launch(h->fuse))) {
-            delete h;
+            !fused_update_supported(u.block, u.cols, u.rv, h->fuse, one_launch(h->fuse)))
             return set_error(LP_E_INVAL, "fuse_pivots > 1 needs update_block <= 256, cols_per_block <= 8, "
                                          "rows_per_thread 1, update_hints 0, update_grid_stride 0 and "
                                          "select_workgroups <= 1; above 16 pivots, update_block 256 and "
                                          "cols_per_block 2, 4 or 8");
-        }
     }
     h->Lg = h->fuse > 1 ? (int64_t)n + 1 + h->fuse : (int64_t)n + 2;
     h->nparts = (int)((h->Lg + h->ucfg.cols - 1) / h->ucfg.cols);
     h->nsparts = (int)((h->Lg + 255) / 256);
-    h->cus = device_cu_count(o.device);
+    h->cus = cus;
     if (h->fuse > 1)
         h->chunk = o.chunk_pivots > 0 ? (o.chunk_pivots + h->fuse - 1) / h->fuse : 1;
     else
@@ -337,13 +308,105 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     h->use_graph = o.plain_launches == 0;
     h->timing = o.time_kernels != 0;
     h->eager_build = o.eager_build != 0;
+    if (o.status_readback == 2 && h->fuse <= 1)
+        return set_error(LP_E_INVAL, "status_readback 2 needs pivot fusion (fuse_pivots > 1)");
+    if (h->fuse > 1) {
+        h->decide_block = dblock;
+        const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
+        h->decide_wgs = one_launch(h->fuse) ? g : 0;
+        h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
+        const bool can_early = h->decide_wgs > 0 && h->chunk == 1;
+        if (o.status_readback == 2 && !can_early)
+            return set_error(LP_E_INVAL,
+                             "status_readback 2 needs the one-launch decision kernel and one group per chunk");
+        h->early_status = can_early && (o.status_readback == 2 ||
+                                        (o.status_readback == 0 && lp_tableau_bytes(m, n) >= kEarlyStatusBytes));
+    }
+    return LP_OK;
+}
 
+// Lays out the context's device buffers (all but the tableau) in one block,
+// in a fixed order, each on a 256-byte boundary. With base == nullptr it only
+// measures; otherwise it points the context's buffers into the block. Returns
+// the bytes the block needs. A new block must be zeroed before first use
+// (k_zero_words): the barrier counters, the select ticket, the zero dump
+// column, R's padding and the work counters start at zero and the kernels
+// keep them so; everything else is written by the build.
+size_t carve_aux(lp_ctx *h, unsigned char *base) {
+    size_t off = 0;
+    auto take = [&](auto **p, size_t bytes) {
+        off = (off + 255) / 256 * 256;
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+        *p = base ? reinterpret_cast<T>(base + off) : nullptr;
+        off += bytes;
+    };
+    const int32_t m = h->m, n = h->n;
+    // F and R hold the pivots of the update instance (fused_update_kf(K) >= K)
+    const int kf = h->fuse > 1 ? fused_update_kf(h->fuse) : 1;
+    take(&h->F, (size_t)kf * h->ld * sizeof(double));
+    take(&h->parts, (size_t)h->nparts * sizeof(ArgMin));
+    // the state block: the solver state, then the four work counters, so
+    // that one copy reads both
+    take(&h->st, kStateBlock);
+    h->cols_done = base ? reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(h->st) + kCountersAt)
+                        : nullptr;
+    take(&h->basis, (size_t)m * sizeof(int32_t));
+    if (h->log_cap) {
+        take(&h->log_r, (size_t)h->log_cap * sizeof(int32_t));
+        take(&h->log_q, (size_t)h->log_cap * sizeof(int32_t));
+    } else {
+        h->log_r = h->log_q = nullptr;
+    }
+    take(&h->out, ((size_t)n + m + 1) * sizeof(double));
+    take(&h->rparts, 64 * sizeof(RatioPart));
+    take(&h->ticket, sizeof(uint32_t));
+    // the fused update reads the list and R of a whole slot group at once, so
+    // both are padded past the last slot
+    take(&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t));
+    take(&h->pos, ((size_t)n + m) * sizeof(int32_t));
+    take(&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double));
+    if (h->fuse > 1) {
+        take(&h->gs, sizeof(GroupState));
+        take(&h->D, (size_t)h->Lg * sizeof(double));
+        const size_t nsp = std::max<size_t>((size_t)h->nsparts, (size_t)kMaxDecideWgs);
+        take(&h->sparts, nsp * sizeof(SPart));
+        take(&h->grparts, kMaxDecideWgs * sizeof(GRatio));
+        take(&h->gsync, sizeof(GridSync));
+        take(&h->dump, (size_t)h->ld * sizeof(double));
+        take(&h->PV, (size_t)kf * h->Lg * sizeof(double));
+    }
+    return (off + 255) / 256 * 256;
+}
+
+// Zeroes a block of `bytes` (a multiple of 8) on the stream: a fill kernel,
+// not hipMemsetAsync, so that the clear is an ordinary kernel node if the
+// caller captures the stream.
+int enqueue_zero(void *p, size_t bytes, hipStream_t stream) {
+    const int64_t words = (int64_t)(bytes / sizeof(uint64_t));
+    if (words <= 0) return LP_OK;
+    const int64_t blocks = std::min<int64_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, stream, (uint64_t *)p, words);
+    LP_HIP_CHECK(hipGetLastError());
+    return LP_OK;
+}
+
+// Allocates everything except the inputs; the tableau is not built yet.
+int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
+    const Options o = resolve_options(opt_in);
+    if (int rc = validate_opts(o)) return rc;
+    int ndev = 0;
+    LP_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
+
+    lp_ctx *h = new (std::nothrow) lp_ctx;
+    if (!h) return set_error(LP_E_NOMEM, "host allocation failed");
+    h->device = o.device;
+    DeviceGuard g(h->device);
     auto fail = [&](int rc) {
         free_ctx(h);
         return rc;
     };
-    if (o.status_readback == 2 && h->fuse <= 1)
-        return fail(set_error(LP_E_INVAL, "status_readback 2 needs pivot fusion (fuse_pivots > 1)"));
+    if (int rc = configure_ctx(h, m, n, o)) return fail(rc);
     auto dev_alloc = [&](void **p, size_t bytes) -> int {
         hipError_t e = hipMalloc(p, bytes);
         if (e != hipSuccess) {
@@ -370,58 +433,10 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
         if (int rc = dev_alloc((void **)&h->T, tbytes)) return fail(rc);
         h->own_T = true;
     }
-    // F and R hold the pivots of the update instance (fused_update_kf(K) >= K)
-    const int kf = h->fuse > 1 ? fused_update_kf(h->fuse) : 1;
-    if (int rc = dev_alloc((void **)&h->F, (size_t)kf * h->ld * sizeof(double))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->parts, (size_t)h->nparts * sizeof(ArgMin))) return fail(rc);
-    // the state block: the solver state, then the four work counters, so
-    // that one copy reads both
-    if (int rc = dev_alloc((void **)&h->st, kStateBlock)) return fail(rc);
-    h->cols_done = reinterpret_cast<unsigned long long *>(reinterpret_cast<unsigned char *>(h->st) + kCountersAt);
-    if (int rc = dev_alloc((void **)&h->basis, (size_t)m * sizeof(int32_t))) return fail(rc);
-    if (h->log_cap) {
-        if (int rc = dev_alloc((void **)&h->log_r, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->log_q, (size_t)h->log_cap * sizeof(int32_t))) return fail(rc);
-    }
-    if (int rc = dev_alloc((void **)&h->out, ((size_t)n + m + 1) * sizeof(double))) return fail(rc);
-    if (hipMemset(h->cols_done, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
-        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-    if (int rc = dev_alloc((void **)&h->rparts, 64 * sizeof(RatioPart))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->ticket, sizeof(uint32_t))) return fail(rc);
-    if (hipMemset(h->ticket, 0, sizeof(uint32_t)) != hipSuccess)
-        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-    // the fused update reads the list and R of a whole slot group at once, so
-    // both are padded past the last slot
-    if (int rc = dev_alloc((void **)&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->pos, ((size_t)n + m) * sizeof(int32_t))) return fail(rc);
-    if (int rc = dev_alloc((void **)&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double))) return fail(rc);
-    if (hipMemset(h->Rl, 0, ((size_t)kf * h->Lg + 16) * sizeof(double)) != hipSuccess)
-        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-    if (h->fuse > 1) {
-        if (int rc = dev_alloc((void **)&h->gs, sizeof(GroupState))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->D, (size_t)h->Lg * sizeof(double))) return fail(rc);
-        h->decide_block = o.decide_block > 0 ? o.decide_block : 256;
-        const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
-        h->decide_wgs = one_launch(h->fuse) ? g : 0;
-        h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
-        const bool can_early = h->decide_wgs > 0 && h->chunk == 1;
-        if (o.status_readback == 2 && !can_early)
-            return fail(set_error(LP_E_INVAL,
-                                  "status_readback 2 needs the one-launch decision kernel and one group per chunk"));
-        h->early_status = can_early && (o.status_readback == 2 ||
-                                        (o.status_readback == 0 && lp_tableau_bytes(m, n) >= kEarlyStatusBytes));
-        const size_t nsp = std::max<size_t>((size_t)h->nsparts, (size_t)kMaxDecideWgs);
-        if (int rc = dev_alloc((void **)&h->sparts, nsp * sizeof(SPart))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->grparts, kMaxDecideWgs * sizeof(GRatio))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->gsync, sizeof(GridSync))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->dump, (size_t)h->ld * sizeof(double))) return fail(rc);
-        if (int rc = dev_alloc((void **)&h->PV, (size_t)fused_update_kf(h->fuse) * h->Lg * sizeof(double)))
-            return fail(rc);
-        if (hipMemset(h->dump, 0, (size_t)h->ld * sizeof(double)) != hipSuccess)
-            return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-        if (hipMemset(h->gsync, 0, sizeof(GridSync)) != hipSuccess)
-            return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
-    }
+    const size_t aux_bytes = carve_aux(h, nullptr);
+    if (int rc = dev_alloc((void **)&h->aux, aux_bytes)) return fail(rc);
+    carve_aux(h, h->aux);
+    if (int rc = enqueue_zero(h->aux, aux_bytes, h->stream)) return fail(rc);
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
@@ -877,6 +892,72 @@ bool all_finite(const double *p, int64_t k) {
     return true;
 }
 
+// ---- the solve that allocates nothing (lp_solve_noalloc) ------------------
+
+// Its work block: every device buffer of a context except the tableau, laid
+// out by carve_aux. Each device holds its own copy for the life of the
+// process. Host code never passes the symbol itself to a kernel or a copy:
+// noalloc_block() looks up the device's copy with hipGetSymbolAddress, once
+// per device with that device current, and every use goes through that
+// address.
+static __device__ __align__(256) unsigned char scratch[LP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_ptr[kNoAllocDevices] = {};
+
+int noalloc_block(int device, unsigned char **out) {
+    if (device < 0 || device >= kNoAllocDevices) return set_error(LP_E_INVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(LP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[device] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_noalloc_ptr[device];
+    return LP_OK;
+}
+
+// The solve loop of lp_solve_noalloc: no events, no pinned memory, no
+// graphs. With the one-launch decision kernel the state is read right after
+// each group's decisions (the group's update pass is queued after the read),
+// so nothing is queued after the end; otherwise after each chunk.
+int run_noalloc(lp_ctx *h, DevState *fin) {
+    DevState s{};
+    for (;;) {
+        if (h->fuse > 1 && h->decide_wgs > 0) {
+            const FusedArgs a = fused_args(h);
+            const bool first = h->pending;
+            if (first) {
+                h->pending = false;
+                h->first_ran = true;
+                launch_first_decide(a, h->pend_A, h->pend_c, h->stream);
+            } else {
+                launch_fused_decide(a, h->stream);
+            }
+            LP_HIP_CHECK(hipGetLastError());
+            LP_HIP_CHECK(hipMemcpyAsync(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+            LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+            if (first) {
+                launch_first_update(a, h->pend_A, h->pend_c, h->stream, nullptr, nullptr);
+            } else {
+                const UpdateConfig &u = h->ucfg;
+                launch_fused_update(a, u.block, u.cols, u.rv, h->stream, nullptr, nullptr);
+            }
+            LP_HIP_CHECK(hipGetLastError());
+        } else {
+            if (int rc = enqueue_chunk(h, 0)) return rc;
+            LP_HIP_CHECK(hipMemcpyAsync(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+            LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        }
+        if (s.status != LP_RUNNING) break;
+    }
+    *fin = s;
+    return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1085,4 +1166,67 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t) {
 
 void lp_destroy(lp_ctx *h) { free_ctx(h); }
 
+int lp_solve_noalloc(int32_t m, int32_t n, const double *dA, const double *db, const double *dc, double *tableau,
+                     size_t tableau_bytes, const lp_options *opt, lp_result *res, double *x, double *y,
+                     int32_t *rows, int32_t *cols, int64_t cap, int64_t *count) {
+    if (m < 1 || n < 1) return set_error(LP_E_INVAL, "m, n must be >= 1");
+    if (cap < 0 || (cap > 0 && (!rows || !cols))) return set_error(LP_E_INVAL, "bad pivot-log arguments");
+    const Options o = resolve_options(opt);
+    if (int rc = validate_opts(o)) return rc;
+    if (o.time_kernels) return set_error(LP_E_INVAL, "lp_solve_noalloc does not time kernels (time_kernels must be 0)");
+    int ndev = 0;
+    LP_HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (o.device < 0 || o.device >= ndev) return set_error(LP_E_INVAL, "device ordinal out of range");
+    lp_ctx h;  // host fields only; its device buffers are carved from the work block
+    if (int rc = configure_ctx(&h, m, n, o)) return rc;
+    h.log_cap = o.record_pivots ? std::min<int64_t>(h.max_pivots, 4 * ((int64_t)m + n) + 64) : 0;
+    const size_t need = carve_aux(&h, nullptr);
+    if (need > (size_t)LP_NOALLOC_SCRATCH_BYTES)
+        return set_error(LP_E_INVAL, "LP too large for lp_solve_noalloc: its work block needs " +
+                                         std::to_string(need) + " bytes, the limit is " +
+                                         std::to_string((size_t)LP_NOALLOC_SCRATCH_BYTES));
+    if (!dA || !db || !dc || !tableau) return set_error(LP_E_INVAL, "NULL input or tableau");
+    if (tableau_bytes < lp_tableau_bytes(m, n) || ((uintptr_t)tableau & 255u))
+        return set_error(LP_E_INVAL, "tableau buffer too small or not 256-byte aligned");
+    DeviceGuard g(h.device);
+    unsigned char *block = nullptr;
+    if (int rc = noalloc_block(h.device, &block)) return rc;
+    carve_aux(&h, block);
+    h.T = tableau;
+    h.stream = (hipStream_t)o.stream;
+    h.use_graph = false;
+    if (int rc = enqueue_zero(block, need, h.stream)) return rc;
+    if (int rc = enqueue_build(&h, dA, db, dc, true)) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    DevState s{};
+    if (int rc = run_noalloc(&h, &s)) return rc;
+    // Finalization: x, y and the objective straight into the caller's arrays
+    const int64_t ny = (int64_t)n + m + 1;
+    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
+                       h.out);
+    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
+                       (const int32_t *)h.basis, h.out);
+    LP_HIP_CHECK(hipGetLastError());
+    double objective = 0.0;
+    if (x) LP_HIP_CHECK(hipMemcpyAsync(x, h.out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    if (y) LP_HIP_CHECK(hipMemcpyAsync(y, h.out + n, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    LP_HIP_CHECK(hipMemcpyAsync(&objective, h.out + n + m, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    const int64_t k = std::min<int64_t>(std::min<int64_t>(s.pivots, h.log_cap), cap);
+    if (k > 0) {
+        LP_HIP_CHECK(hipMemcpyAsync(rows, h.log_r, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+        LP_HIP_CHECK(hipMemcpyAsync(cols, h.log_q, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost, h.stream));
+    }
+    LP_HIP_CHECK(hipStreamSynchronize(h.stream));
+    if (count) *count = s.pivots;
+    if (res) {
+        res->status = s.status;
+        res->reserved = 0;
+        res->pivots = s.pivots;
+        res->objective = objective;
+        res->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LP_OK;
+}
+
 }  // extern "C"
+

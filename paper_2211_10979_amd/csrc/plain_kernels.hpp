@@ -110,6 +110,12 @@ static __global__ void k_init(DevState *st, DevState init, int32_t *__restrict__
 
 static __global__ void k_set_stop(DevState *st, int64_t stop_at) { st->stop_at = stop_at; }
 
+// Zeroes `words` 8-byte words (grid-stride): the clear of a new work block.
+static __global__ __launch_bounds__(256) void k_zero_words(uint64_t *__restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 // Steps 1 and 2 for the next pivot; one workgroup of 1024 threads.
 //   Step 1   final stage of the argmin over the update's per-group partials
 //            (a scan of row 0 before the first pivot);

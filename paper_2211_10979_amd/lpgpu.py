@@ -164,6 +164,8 @@ SIGNATURES = {
     "lp_get_info": (ctypes.c_int, [_P, ctypes.POINTER(lp_info)]),
     "lp_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(lp_timing)]),
     "lp_destroy": (None, [_P]),
+    "lp_solve_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t, _OPT,
+                                        _RES, _D, _D, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_int64)]),
     "lp_diag_arith": (ctypes.c_int, [ctypes.c_int32, _I64, _D, _D, _D, _D, _D]),
     "lp_diag_copy": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, _D]),
     "lp_batch_create": (ctypes.c_int, [_PP, ctypes.c_int32, _I32, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -368,6 +370,34 @@ def lp_get_basis(h):
 def lp_destroy(h):
     if h:
         library().lp_destroy(h)
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20  # LP_NOALLOC_SCRATCH_BYTES
+
+
+def lp_solve_noalloc(m, n, dA, db, dc, tableau, tableau_bytes=None, cap=None, options: lp_options | None = None,
+                     **kw):
+    """One solve through the entry point that allocates nothing: device inputs
+    and a caller-owned device tableau buffer (ints or torch tensors). Returns
+    (result dict, x, y, rows, cols, count); the log holds min(count, cap)
+    pivots (cap defaults to the device log's length)."""
+    ptr = lambda t: t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+    if tableau_bytes is None:
+        tableau_bytes = tableau.numel() * tableau.element_size()
+    o = _opts(options, kw)
+    if cap is None:
+        cap = min(o.max_pivots if o.max_pivots > 0 else 50 * (m + n), 4 * (m + n) + 64)
+    x = np.empty(n, dtype=np.float64)
+    y = np.empty(m, dtype=np.float64)
+    rows = np.empty(max(cap, 1), dtype=np.int32)
+    cols = np.empty(max(cap, 1), dtype=np.int32)
+    res = lp_result()
+    count = ctypes.c_int64()
+    _check(library().lp_solve_noalloc(m, n, ptr(dA), ptr(db), ptr(dc), ptr(tableau), int(tableau_bytes),
+                                      ctypes.byref(o), ctypes.byref(res), _dp(x), _dp(y), _ip(rows), _ip(cols),
+                                      int(cap), ctypes.byref(count)), "lp_solve_noalloc")
+    k = min(cap, count.value)
+    return _res_dict(res), x, y, rows[:k].copy(), cols[:k].copy(), count.value
 
 
 def lp_diag_copy(nbytes, reps=10, device=0) -> float:
