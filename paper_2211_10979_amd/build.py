@@ -58,7 +58,22 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+GEN_SRC = os.path.join(PKG, "lpgen_native.c")
+GEN_LIB = os.path.join(PKG, "liblpgen.so")
+
+
+def build_generator(verbose: bool = False) -> str:
+    """The C draws of the input generator (liblpgen.so, host code only)."""
+    cmd = ["gcc", "-O3", "-fPIC", "-shared", "-o", GEN_LIB + ".tmp", GEN_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(GEN_LIB + ".tmp", GEN_LIB)
+    return GEN_LIB
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
+    build_generator(verbose)
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)

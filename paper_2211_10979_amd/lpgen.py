@@ -44,6 +44,25 @@ SIZE_STREAM_SALT = 0x5EED
 
 _CHUNK = 1 << 20
 _POOL = None
+_NATIVE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblpgen.so")
+_NATIVE = None
+
+
+def _native():
+    """The C build of the same draws (lpgen_native.c), or None when it is not
+    built (then numpy draws the same numbers, more slowly)."""
+    global _NATIVE
+    if _NATIVE is None:
+        _NATIVE = False
+        if os.path.exists(_NATIVE_PATH) and not os.environ.get("LPGEN_NUMPY"):
+            import ctypes
+
+            lib = ctypes.CDLL(_NATIVE_PATH)
+            lib.lpgen_values.restype = ctypes.c_int64
+            lib.lpgen_values.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_void_p]
+            _NATIVE = lib
+    return _NATIVE or None
 
 
 def _pool():
@@ -119,6 +138,11 @@ class Stream:
         below 2^-54), the k-th value is the k-th draw's; otherwise the exact
         sequential rejection path is taken."""
         span = hi - lo + 1
+        lib = _native()
+        if lib is not None and 1 <= span <= (1 << 62):
+            out = np.empty(count, dtype=np.float64)
+            self.drawn += lib.lpgen_values(self.state, self.drawn, count, lo, hi, out.ctypes.data)
+            return out
         limit = np.uint64(((1 << 64) // span) * span)
         out = np.empty(count, dtype=np.float64)
         first = self.drawn

@@ -86,3 +86,33 @@ def test_rejection_path_is_taken_when_a_draw_is_rejected():
     a = lpgen.Stream(7).values(5000, 0, span - 1)
     b = lpgen.Stream(7).integers(5000, 0, span - 1).astype(np.float64)
     assert np.array_equal(a, b)
+
+
+def _numpy_draws(fn):
+    """Runs fn with the numpy draws (the C build switched off)."""
+    saved = lpgen._NATIVE
+    lpgen._NATIVE = False
+    try:
+        return fn()
+    finally:
+        lpgen._NATIVE = saved
+
+
+def test_native_draws_equal_numpy_draws():
+    if lpgen._native() is None:
+        import pytest
+
+        pytest.skip("liblpgen.so not built")
+    for seed, m, n, k in ((1, 37, 53, 0), (5, 300, 7, 12), (3, 1, 1, 9), (4, 513, 64, 511)):
+        a = lpgen.dense_lp(seed, m, n, k=k)
+        b = _numpy_draws(lambda: lpgen.dense_lp(seed, m, n, k=k))
+        assert np.array_equal(a.A, b.A) and np.array_equal(a.b, b.b) and np.array_equal(a.c, b.c)
+    # a span that rejects about one draw in 16: same values and the same
+    # stream position afterwards (the next draws agree too)
+    lo, hi = 0, 3 << 60
+    s1 = lpgen.Stream(77)
+    v1 = np.concatenate([s1.values(4000, lo, hi), s1.values(10, 1, 1000)])
+    v2 = _numpy_draws(lambda: (lambda s: np.concatenate([s.values(4000, lo, hi), s.values(10, 1, 1000)]))(
+        lpgen.Stream(77)))
+    assert np.array_equal(v1, v2)
+    assert s1.drawn > 4010  # some draws were rejected
