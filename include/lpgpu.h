@@ -416,8 +416,14 @@ struct lp_server_stats {
 };
 
 /*
- * hbm_budget_bytes: ceiling on resident tableau bytes; max_slots: most LPs
- * resident at once (<= 0: 4096). Starts the scheduler thread.
+ * hbm_budget_bytes: ceiling on resident device bytes (tableaux and their
+ * work buffers; the per-worker staging of inputs is outside it); max_slots:
+ * most LPs resident at once (<= 0: 4096). Requests are admitted in arrival
+ * order while both allow. LPs whose tableau is at most 16 MiB advance
+ * together in the batched kernel; larger ones wait resident (built) until one
+ * of the large-LP workers solves them with the single-LP kernels (pivot
+ * fusion in groups of 16 with the per-pivot decision kernels). Starts the
+ * admission, scheduler and large-LP worker threads.
  */
 int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots, const lp_options *opt);
 

@@ -2,6 +2,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fused_launch.hpp"
 
 namespace lpgpu {
@@ -181,10 +183,17 @@ int occupancy_kf(int KF) {
 
 }  // namespace
 
+// (queried once per form: the figure depends only on the compiled kernel)
 int decide_blocks_per_cu(int block, int KF) {
-    if (block == 512) return occupancy_kf<512>(KF);
-    if (block == 256) return occupancy_kf<256>(KF);
-    return 0;
+    static std::atomic<int> cache[2][kMaxFuse + 1];
+    if ((block != 256 && block != 512) || KF < 0 || KF > kMaxFuse) return 0;
+    std::atomic<int> &slot = cache[block == 512][KF];
+    int v = slot.load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = (block == 512 ? occupancy_kf<512>(KF) : occupancy_kf<256>(KF)) + 1;  // stored + 1: 0 means unknown
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v - 1;
 }
 
 void launch_fused_decide(const FusedArgs &a, hipStream_t s) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,6 +15,7 @@
 
 #include "common.hpp"
 #include "fused_launch.hpp"
+#include "lane.hpp"
 #include "plain_kernels.hpp"
 
 using namespace lpgpu;
@@ -64,10 +66,17 @@ UpdateConfig pick_update_config(int32_t m, int cols, int rv, int block, bool fus
     return {block, cols, rv, (int)((nvec + span - 1) / span), 0, 0, 0};
 }
 
+// (queried once per device)
 int device_cu_count(int device) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
-    return prop.multiProcessorCount;
+    static std::atomic<int> cache[64];
+    if (device >= 0 && device < 64) {
+        const int v = cache[device].load(std::memory_order_relaxed);
+        if (v > 0) return v;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) return 256;
+    if (device >= 0 && device < 64) cache[device].store(cus, std::memory_order_relaxed);
+    return cus;
 }
 
 bool valid_cols(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == 16; }
@@ -479,13 +488,16 @@ void enqueue_full_build(lp_ctx *h, const double *dA, const double *db, const dou
 // Deferred (`defer`, with the one-launch decision kernel): only the RHS
 // column and the solver state here; the first group reads the structural
 // columns from A and c, and its update pass writes them.
+// With dA == nullptr the tableau is built already and only the solver state
+// is set up.
 int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *dc, bool defer) {
     const int32_t m = h->m, n = h->n;
     const int64_t ld = h->ld;
-    defer = defer && !h->eager_build && h->fuse > 1 && h->decide_wgs > 0;
+    const bool built = dA == nullptr;
+    defer = defer && !built && !h->eager_build && h->fuse > 1 && h->decide_wgs > 0;
     h->counters_cached = false;
     h->solution_cached = false;
-    if (!defer) enqueue_full_build(h, dA, db, dc);
+    if (!defer && !built) enqueue_full_build(h, dA, db, dc);
     h->pending = defer;
     h->first_ran = false;
     h->lazy = defer;
@@ -1230,3 +1242,138 @@ int lp_solve_noalloc(int32_t m, int32_t n, const double *dA, const double *db, c
 
 }  // extern "C"
 
+// ---- the server's lane of large LPs ----------------------------------------
+
+namespace lpgpu {
+
+struct Lane {
+    lp_ctx *h = nullptr;
+    Options o{};
+    int32_t max_m = 0, max_n = 0;
+};
+
+namespace {
+
+// The lane's options: pivot fusion in groups of 16 with the per-pivot
+// decision kernels (k_gselect / k_gstage, no grid barrier), plain launches.
+Options lane_options(Options o, hipStream_t stream, int fuse) {
+    o.decide_kernel = 1;
+    o.fuse_pivots = fuse;
+    o.plain_launches = 1;
+    o.time_kernels = 0;
+    o.status_readback = 1;
+    o.chunk_pivots = 0;
+    o.eager_build = 0;
+    o.device_buffer = nullptr;
+    o.device_buffer_bytes = 0;
+    o.stream = stream;
+    return o;
+}
+
+// Configures a context for an m x n LP of the lane: groups of 16, or one
+// pivot per pass where the fused kernels have no instance for the shape.
+int lane_configure(const Options &base, lp_ctx *h, int32_t m, int32_t n) {
+    const int64_t cap = base.record_pivots ? 4 * ((int64_t)m + n) + 64 : 0;
+    for (int fuse : {kMaxFuseSplit, 1}) {
+        const Options o = lane_options(base, h->stream, fuse);
+        if (validate_opts(o) == LP_OK && configure_ctx(h, m, n, o) == LP_OK) {
+            h->log_cap = std::min<int64_t>(h->max_pivots, cap);
+            h->use_graph = false;
+            h->timing = false;
+            return LP_OK;
+        }
+    }
+    return set_error(LP_E_INVAL, "no lane configuration for this LP shape");
+}
+
+}  // namespace
+
+int lane_create(Lane **out, int device, hipStream_t stream, const Options &opt, int32_t max_m, int32_t max_n) {
+    *out = nullptr;
+    Lane *L = new (std::nothrow) Lane;
+    if (!L) return set_error(LP_E_NOMEM, "host allocation failed");
+    L->h = new (std::nothrow) lp_ctx;
+    if (!L->h) {
+        delete L;
+        return set_error(LP_E_NOMEM, "host allocation failed");
+    }
+    L->o = opt;
+    L->max_m = max_m;
+    L->max_n = max_n;
+    lp_ctx *h = L->h;
+    h->device = device;
+    h->stream = stream;
+    h->own_stream = false;
+    DeviceGuard g(device);
+    hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_blk, 2 * kStateBlock, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&h->host_out, ((size_t)max_n + max_m + 1) * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev_stop);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_slot[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        lane_destroy(L);
+        return set_error(LP_E_NOMEM, std::string("lane resources: ") + hipGetErrorString(e));
+    }
+    *out = L;
+    return LP_OK;
+}
+
+// (a context of its own: the lane's may be solving on another thread)
+size_t lane_work_bytes(const Lane *L, int32_t m, int32_t n) {
+    lp_ctx tmp;
+    if (m > L->max_m || n > L->max_n || lane_configure(L->o, &tmp, m, n) != LP_OK) return 0;
+    return carve_aux(&tmp, nullptr);
+}
+
+int64_t lane_log_cap(const Lane *L, int32_t m, int32_t n) {
+    lp_ctx tmp;
+    if (lane_configure(L->o, &tmp, m, n) != LP_OK) return 0;
+    return tmp.log_cap;
+}
+
+int lane_solve(Lane *L, int32_t m, int32_t n, double *T, unsigned char *work, LaneResult *out) {
+    if (m > L->max_m || n > L->max_n) return set_error(LP_E_INVAL, "LP larger than the lane");
+    lp_ctx *h = L->h;
+    DeviceGuard g(h->device);
+    if (int rc = lane_configure(L->o, h, m, n)) return rc;
+    const size_t bytes = carve_aux(h, nullptr);
+    carve_aux(h, work);
+    h->T = T;
+    if (int rc = enqueue_zero(work, bytes, h->stream)) return rc;
+    if (int rc = enqueue_build(h, nullptr, nullptr, nullptr, false)) return rc;
+    if (int rc = run_until(h, INT64_MAX)) return rc;
+    const DevState s = h->host_st[2];
+    out->status = s.status;
+    out->pivots = s.pivots;
+    out->x.assign(h->host_out, h->host_out + n);
+    out->y.assign(h->host_out + n, h->host_out + n + m);
+    out->objective = h->host_out[(size_t)n + m];
+    const int64_t k = std::min<int64_t>(s.pivots, h->log_cap);
+    out->rows.resize((size_t)k);
+    out->cols.resize((size_t)k);
+    if (k > 0) {
+        LP_HIP_CHECK(hipMemcpyAsync(out->rows.data(), h->log_r, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    h->stream));
+        LP_HIP_CHECK(hipMemcpyAsync(out->cols.data(), h->log_q, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    h->stream));
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    }
+    return LP_OK;
+}
+
+void lane_destroy(Lane *L) {
+    if (!L) return;
+    if (L->h) {
+        L->h->T = nullptr;  // the tableaux and work blocks belong to the caller
+        L->h->own_T = false;
+        L->h->aux = nullptr;
+        free_ctx(L->h);
+    }
+    delete L;
+}
+
+}  // namespace lpgpu

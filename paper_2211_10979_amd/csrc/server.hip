@@ -6,12 +6,17 @@
 //   admission  takes requests in arrival order; waits until a slot is free
 //              and the LP's bytes fit the budget; carves its memory from the
 //              arena, copies A, b, c to the device and builds the tableau on
-//              the copy stream; then hands the slot to the scheduler;
+//              the copy stream; then hands the LP to the scheduler (small
+//              tableaux) or to the large-LP lane (the LP waits there,
+//              resident, until a lane worker takes it);
 //   scheduler  replays the captured graph {queue reset, persistent batched
 //              kernel} over the resident slots, each LP at most `budget`
 //              pivots per replay, reads back the states, harvests finished
 //              LPs (solution and pivot log to the host) and frees their
-//              memory and slot.
+//              memory and slot;
+//   lane       each large-LP worker solves one resident LP at a time on its
+//              own stream with the single-LP kernels (pivot fusion with the
+//              per-pivot decision kernels), then frees its memory and slot.
 // The graph reads LPs through the device descriptor table, so it stays valid
 // while the resident set changes. Work of LPs admitted while a replay runs
 // overlaps with it on the copy stream.
@@ -31,6 +36,7 @@
 #include <vector>
 
 #include "batch_engine.hpp"
+#include "lane.hpp"
 #include "plain_kernels.hpp"
 
 using namespace lpgpu;
@@ -126,6 +132,7 @@ class Arena {
 struct Request {
     uint64_t ticket = 0;
     int32_t m = 0, n = 0;
+    bool large = false;  // solved in the large-LP lane
     std::vector<double> in;  // A (row-major), b, c
     Clock::time_point t_submit, t_done;
     bool done = false;
@@ -144,7 +151,9 @@ struct Request {
 
 // LPs whose tableau exceeds this go to the large-LP lane: one workgroup per
 // LP would take milliseconds per pivot there, while the single-LP kernels
-// spread each pivot over the whole GPU.
+// spread each pivot over the whole GPU. The lane takes LPs up to the
+// server's largest accepted size, 4096 x 4096.
+constexpr int32_t kLaneMax = 4096;
 constexpr size_t kLargeTableauBytes = (size_t)16 << 20;
 
 // Device bytes of one resident LP: tableau, lists and logs, extraction
@@ -228,13 +237,13 @@ struct lp_server {
     std::vector<double> lat_ms;
     int last_error = LP_OK;
     std::thread admit_thr[kAdmitters], sched_thr;
-    // large-LP lane: single-LP multi-workgroup kernels on their own streams
+    // large-LP lane: resident LPs waiting for a worker, and the workers'
+    // solvers (each on its own stream)
     static constexpr int kLargeWorkers = 2;
-    std::deque<Request *> pending_large;
+    std::deque<Request *> ready_large;
     int large_busy = 0;
     hipStream_t large_streams[kLargeWorkers] = {};
-    double *large_staging[kLargeWorkers] = {};
-    DevState *large_pin[kLargeWorkers] = {};  // two pinned state slots per worker
+    Lane *lanes[kLargeWorkers] = {};
     std::thread large_thr[kLargeWorkers];
     int64_t large_done = 0;
 };
@@ -246,16 +255,49 @@ void server_fail(lp_server *s, int code) {
     if (!s->last_error) s->last_error = code;
 }
 
-// Admission worker `w`: allocate, copy, build, publish the descriptor; then
-// ready. Workers take requests from the queue in arrival order; each has its
-// own copy stream and staging buffer, so their copies and builds overlap.
+// Device bytes of a request: the batched form's layout, or for the lane the
+// tableau and the lane's work block.
+size_t request_bytes(const lp_server *s, int32_t m, int32_t n, bool large) {
+    const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
+    if (!large) return layout_of(m, n, maxp, s->opt.record_pivots != 0, s->lds).total;
+    const size_t work = lane_work_bytes(s->lanes[0], m, n);
+    if (work == 0) return 0;
+    return align_up((size_t)(padded_ld(m) * ((int64_t)n + m + 1)) * sizeof(double)) + align_up(work);
+}
+
+// Fails a request that could not be admitted or built; its memory and slot
+// are returned.
+void fail_request(lp_server *s, Request *r) {
+    if (r->block) s->arena->release(r->block, r->bytes);
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (!s->last_error) s->last_error = LP_E_DEVICE;
+    s->bytes_in_use -= r->bytes;
+    s->free_slots.push_back(r->slot);
+    r->slot = -1;
+    r->block = nullptr;
+    r->status = LP_NUMERICAL;
+    r->x.assign(r->n, 0.0);
+    r->y.assign(r->m, 0.0);
+    r->t_done = Clock::now();
+    r->done = true;
+    s->completed++;
+    s->admitting--;
+    s->cv_done.notify_all();
+    s->cv_admit.notify_all();
+}
+
+// Admission worker `w`: takes requests in arrival order (both lanes share
+// one queue, so the budget admits LPs in the order they came), allocates,
+// copies and builds; then hands the LP to the scheduler or to the lane. Each
+// worker has its own copy stream and staging buffer, so their copies and
+// builds overlap.
 void admission_loop(lp_server *s, int w) {
     DeviceGuard g(s->device);
     hipStream_t copy = s->copy_streams[w];
     double *staging = s->staging[w];
     for (;;) {
         Request *r = nullptr;
-        Layout L{};
+        size_t need = 0;
         {
             std::unique_lock<std::mutex> lock(s->mu);
             s->cv_admit.wait(lock, [&] {
@@ -263,9 +305,8 @@ void admission_loop(lp_server *s, int w) {
             });
             if (s->pending.empty()) return;  // stopping and drained
             r = s->pending.front();
-            const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)r->m + r->n);
-            L = layout_of(r->m, r->n, maxp, s->opt.record_pivots != 0, s->lds);
-            if (s->free_slots.empty() || s->bytes_in_use + L.total > s->budget) {
+            need = request_bytes(s, r->m, r->n, r->large);
+            if (s->free_slots.empty() || s->bytes_in_use + need > s->budget) {
                 // head of the queue waits for memory: admission stays in order
                 s->cv_admit.wait_for(lock, std::chrono::milliseconds(2));
                 continue;
@@ -273,14 +314,14 @@ void admission_loop(lp_server *s, int w) {
             s->pending.pop_front();
             r->slot = s->free_slots.back();
             s->free_slots.pop_back();
-            s->bytes_in_use += L.total;
+            s->bytes_in_use += need;
             s->peak = std::max(s->peak, s->bytes_in_use);
             s->admitting++;
         }
-        char *block = (char *)s->arena->alloc(L.total);
+        char *block = (char *)s->arena->alloc(need);
         if (!block) {  // fragmentation or device full: retry after harvests
             std::lock_guard<std::mutex> lock(s->mu);
-            s->bytes_in_use -= L.total;
+            s->bytes_in_use -= need;
             s->free_slots.push_back(r->slot);
             r->slot = -1;
             s->pending.push_front(r);
@@ -289,11 +330,37 @@ void admission_loop(lp_server *s, int w) {
             continue;
         }
         r->block = block;
-        r->bytes = L.total;
-        BatchDesc &d = r->desc;
+        r->bytes = need;
         const int32_t m = r->m, n = r->n;
+        const int64_t ld = padded_ld(m);
+        const double *A = staging, *bb = A + (int64_t)m * n, *c = bb + m;
+        bool ok = hipMemcpyAsync(staging, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 copy) == hipSuccess;
+        dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
+        const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
+        if (r->large) {  // the tableau of Table I; the lane sets up the rest when it takes the LP
+            hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, copy, (double *)block, ld, m, n, A, c);
+            hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, copy,
+                               (double *)block, ld, m, n, bb, m + 1);
+            ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(copy) == hipSuccess;
+            std::vector<double>().swap(r->in);
+            if (!ok) {
+                fail_request(s, r);
+                continue;
+            }
+            {
+                std::lock_guard<std::mutex> lock(s->mu);
+                s->admitting--;
+                s->ready_large.push_back(r);
+            }
+            s->cv_admit.notify_all();  // the lane workers wait on this too
+            continue;
+        }
+        const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
+        const Layout L = layout_of(m, n, maxp, s->opt.record_pivots != 0, s->lds);
+        BatchDesc &d = r->desc;
         d.T = (double *)block;
-        d.ld = padded_ld(m);
+        d.ld = ld;
         d.m = m;
         d.n = n;
         int32_t *ints = (int32_t *)(block + L.tab);
@@ -310,15 +377,10 @@ void admission_loop(lp_server *s, int w) {
         d.scratch = L.scratch ? (double *)(block + L.tab + L.ints + L.out) : nullptr;
         BatchState init{};
         init.status = LP_RUNNING;
-        init.max_pivots = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
+        init.max_pivots = maxp;
         init.eps_d = s->opt.eps_dual;
         init.eps_p = s->opt.eps_pivot;
-        const double *A = staging, *bb = A + (int64_t)m * n, *c = bb + m;
-        bool ok = hipMemcpyAsync(staging, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice,
-                                 copy) == hipSuccess;
-        dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((d.ld + kBuildTile - 1) / kBuildTile));
         hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, copy, d.T, d.ld, m, n, A, c);
-        const int64_t nslack = (int64_t)(m + 1) * (d.ld / 2);
         hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, copy, d.T, d.ld, m,
                            n, bb, m + 1);
         hipLaunchKernelGGL(k_batch_init_lp, dim3(16), dim3(256), 0, copy, d, s->state + r->slot, init);
@@ -326,21 +388,8 @@ void admission_loop(lp_server *s, int w) {
                        hipSuccess;
         ok = ok && hipGetLastError() == hipSuccess && hipStreamSynchronize(copy) == hipSuccess;
         std::vector<double>().swap(r->in);
-        if (!ok) {  // the request fails; its memory and slot are returned
-            s->arena->release(r->block, r->bytes);
-            std::lock_guard<std::mutex> lock(s->mu);
-            if (!s->last_error) s->last_error = LP_E_DEVICE;
-            s->bytes_in_use -= r->bytes;
-            s->free_slots.push_back(r->slot);
-            r->slot = -1;
-            r->block = nullptr;
-            r->status = LP_NUMERICAL;
-            r->x.assign(r->n, 0.0);
-            r->y.assign(r->m, 0.0);
-            r->t_done = Clock::now();
-            r->done = true;
-            s->admitting--;
-            s->cv_done.notify_all();
+        if (!ok) {
+            fail_request(s, r);
             continue;
         }
         {
@@ -404,205 +453,48 @@ void harvest(lp_server *s, const std::vector<int> &fin) {
 
 // ---- large-LP lane -------------------------------------------------------
 
-// Arena layout of one large LP for the single-LP kernels.
-struct LargeLayout {
-    size_t tab, F, parts, st, basis, logs, cols, pos, Rl, cnt, out, total;
-    int64_t log_cap;
-    int nparts, cols_per_block, block, rowchunks;
-};
-
-LargeLayout large_layout_of(int32_t m, int32_t n, int64_t max_pivots, bool record) {
-    LargeLayout L{};
-    const int64_t ld = padded_ld(m), W = (int64_t)n + m + 1, nvec = ((int64_t)m + 2) / 2;
-    L.log_cap = record ? std::min<int64_t>(max_pivots, 4 * ((int64_t)m + n) + 64) : 0;
-    L.block = nvec <= 64 ? 64 : (nvec <= 128 ? 128 : 256);
-    L.cols_per_block = nvec > 2048 ? 1 : 4;
-    L.rowchunks = (int)((nvec + L.block - 1) / L.block);
-    L.nparts = (int)(((int64_t)n + 2 + L.cols_per_block - 1) / L.cols_per_block);
-    L.tab = align_up((size_t)(ld * W) * sizeof(double));
-    L.F = align_up((size_t)ld * sizeof(double));
-    L.parts = align_up((size_t)L.nparts * sizeof(ArgMin));
-    L.st = align_up(sizeof(DevState));
-    L.basis = align_up((size_t)m * sizeof(int32_t));
-    L.logs = align_up((size_t)(2 * L.log_cap + 1) * sizeof(int32_t));
-    L.cols = align_up(((size_t)n + 2) * sizeof(int32_t));
-    L.pos = align_up(((size_t)n + m) * sizeof(int32_t));
-    L.Rl = align_up(((size_t)n + 2) * sizeof(double));
-    L.cnt = align_up(sizeof(unsigned long long));
-    L.out = align_up(((size_t)n + m + 1) * sizeof(double));
-    L.total = L.tab + L.F + L.parts + L.st + L.basis + L.logs + L.cols + L.pos + L.Rl + L.cnt + L.out;
-    return L;
-}
-
-struct LargeLP {
-    double *T, *F, *Rl, *out;
-    ArgMin *parts;
-    DevState *st;
-    int32_t *basis, *log_r, *log_q, *cols, *pos;
-    unsigned long long *cnt;
-};
-
-template <int B, int C>
-void large_update(const LargeLayout &L, hipStream_t st, const LargeLP &d, int64_t ld, int32_t m, int32_t n) {
-    hipLaunchKernelGGL((k_update<B, C, 1, 0, 0>), dim3((unsigned)((int64_t)L.rowchunks * L.nparts)), dim3(B), 0, st,
-                       d.T, ld, m, n, L.rowchunks, d.cols, d.Rl, d.F, d.st, d.parts);
-}
-
-void large_pivot(const LargeLayout &L, hipStream_t st, const LargeLP &d, int64_t ld, int32_t m, int32_t n) {
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st, d.T, ld, m, n, d.parts, d.st, d.F, d.basis, d.log_r,
-                       d.log_q, d.pos);
-    hipLaunchKernelGGL(k_stage, dim3((unsigned)(((int64_t)n + 2 + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
-                       d.st, d.cols, d.pos, d.Rl, d.cnt);
-    if (L.block == 256 && L.cols_per_block == 1)
-        large_update<256, 1>(L, st, d, ld, m, n);
-    else if (L.block == 256)
-        large_update<256, 4>(L, st, d, ld, m, n);
-    else if (L.block == 128)
-        large_update<128, 4>(L, st, d, ld, m, n);
-    else
-        large_update<64, 4>(L, st, d, ld, m, n);
-}
-
-// Builds, solves and harvests one large LP on worker w's stream. Pivots go
-// in chunks of 4, two chunks in flight, the state read back through pinned
-// memory between them.
-bool run_large(lp_server *s, int w, Request *r, const LargeLayout &L, char *block) {
-    hipStream_t st = s->large_streams[w];
-    const int32_t m = r->m, n = r->n;
-    const int64_t ld = padded_ld(m);
-    char *p = block;
-    LargeLP d{};
-    d.T = (double *)p;
-    p += L.tab;
-    d.F = (double *)p;
-    p += L.F;
-    d.parts = (ArgMin *)p;
-    p += L.parts;
-    d.st = (DevState *)p;
-    p += L.st;
-    d.basis = (int32_t *)p;
-    p += L.basis;
-    d.log_r = (int32_t *)p;
-    d.log_q = d.log_r + L.log_cap;
-    p += L.logs;
-    d.cols = (int32_t *)p;
-    p += L.cols;
-    d.pos = (int32_t *)p;
-    p += L.pos;
-    d.Rl = (double *)p;
-    p += L.Rl;
-    d.cnt = (unsigned long long *)p;
-    p += L.cnt;
-    d.out = (double *)p;
-
-    double *stg = s->large_staging[w];
-    const double *A = stg, *bb = A + (int64_t)m * n, *c = bb + m;
-    bool ok = hipMemcpyAsync(stg, r->in.data(), r->in.size() * sizeof(double), hipMemcpyHostToDevice, st) ==
-              hipSuccess;
-    dim3 gs((unsigned)((n + kBuildTile - 1) / kBuildTile), (unsigned)((ld + kBuildTile - 1) / kBuildTile));
-    hipLaunchKernelGGL(k_build_struct, gs, dim3(256), 0, st, d.T, ld, m, n, A, c);
-    const int64_t nslack = (int64_t)(m + 1) * (ld / 2);
-    hipLaunchKernelGGL(k_build_slack, dim3((unsigned)((nslack + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n, bb,
-                       m + 1);
-    DevState init{};
-    init.status = LP_RUNNING;
-    init.stop_at = INT64_MAX;
-    init.max_pivots = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
-    init.log_cap = L.log_cap;
-    init.eps_d = s->opt.eps_dual;
-    init.eps_p = s->opt.eps_pivot;
-    init.fresh = 1;
-    init.nparts = L.nparts;
-    const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, ld), 1);
-    hipLaunchKernelGGL(k_init, dim3((unsigned)((ninit + 255) / 256)), dim3(256), 0, st, d.st, init, d.basis, m, n,
-                       d.F, ld, d.cols, d.pos, d.cnt);
-    ok = ok && hipGetLastError() == hipSuccess;
-
-    DevState *pin = s->large_pin[w];
-    constexpr int kChunk = 4;
-    auto chunk = [&](int slot) {
-        for (int k = 0; k < kChunk; ++k) large_pivot(L, st, d, ld, m, n);
-        return hipMemcpyAsync(&pin[slot], d.st, sizeof(DevState), hipMemcpyDeviceToHost, st) == hipSuccess;
-    };
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    ok = ok && hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) == hipSuccess;
-    int slot = 0;
-    ok = ok && chunk(0) && hipEventRecord(ev[0], st) == hipSuccess;
-    while (ok) {
-        ok = chunk(slot ^ 1) && hipEventRecord(ev[slot ^ 1], st) == hipSuccess &&
-             hipEventSynchronize(ev[slot]) == hipSuccess;
-        if (!ok || pin[slot].status != LP_RUNNING) break;
-        slot ^= 1;
-    }
-    hipLaunchKernelGGL(k_extract_y, dim3((unsigned)(((int64_t)n + m + 1 + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
-                       d.out);
-    hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, d.T, ld, m, n,
-                       (const int32_t *)d.basis, d.out);
-    std::vector<double> tmp((size_t)n + m + 1);
-    DevState fin{};
-    ok = ok && hipMemcpyAsync(tmp.data(), d.out, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st) ==
-                   hipSuccess &&
-         hipMemcpyAsync(&fin, d.st, sizeof(DevState), hipMemcpyDeviceToHost, st) == hipSuccess &&
-         hipStreamSynchronize(st) == hipSuccess;
-    if (ok) {
-        const int64_t k = std::min<int64_t>(fin.pivots, L.log_cap);
-        r->rows.resize((size_t)k);
-        r->cols.resize((size_t)k);
-        if (k > 0)
-            ok = hipMemcpy(r->rows.data(), d.log_r, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost) ==
-                     hipSuccess &&
-                 hipMemcpy(r->cols.data(), d.log_q, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess;
-    }
-    for (auto e : ev)
-        if (e) (void)hipEventDestroy(e);
-    (void)hipStreamSynchronize(st);
-    std::vector<double>().swap(r->in);  // the input copy has completed
-    r->x.assign(tmp.begin(), tmp.begin() + n);
-    r->y.assign(tmp.begin() + n, tmp.begin() + n + m);
-    r->objective = tmp[(size_t)n + m];
-    r->status = ok ? fin.status : LP_NUMERICAL;
-    r->pivots = fin.pivots;
-    return ok;
-}
-
+// Lane worker `w`: takes resident large LPs in admission order and solves
+// each on its own stream; harvests, frees the memory and the slot.
 void large_loop(lp_server *s, int w) {
     DeviceGuard g(s->device);
     for (;;) {
         Request *r = nullptr;
-        LargeLayout L{};
         {
             std::unique_lock<std::mutex> lock(s->mu);
-            s->cv_admit.wait(lock, [&] { return s->stopping || !s->pending_large.empty(); });
-            if (s->pending_large.empty()) return;  // stopping and drained
-            r = s->pending_large.front();
-            const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)r->m + r->n);
-            L = large_layout_of(r->m, r->n, maxp, s->opt.record_pivots != 0);
-            if (s->bytes_in_use + L.total > s->budget) {
-                s->cv_admit.wait_for(lock, std::chrono::milliseconds(2));
-                continue;
-            }
-            s->pending_large.pop_front();
-            s->bytes_in_use += L.total;
-            s->peak = std::max(s->peak, s->bytes_in_use);
+            s->cv_admit.wait(lock, [&] {
+                return !s->ready_large.empty() || (s->stopping && s->pending.empty() && s->admitting == 0);
+            });
+            if (s->ready_large.empty()) return;  // stopping and drained
+            r = s->ready_large.front();
+            s->ready_large.pop_front();
             s->large_busy++;
         }
-        char *block = (char *)s->arena->alloc(L.total);
-        if (!block) {
-            std::lock_guard<std::mutex> lock(s->mu);
-            s->bytes_in_use -= L.total;
-            s->pending_large.push_front(r);
-            s->large_busy--;
-            std::this_thread::sleep_for(std::chrono::milliseconds(1));
-            continue;
-        }
-        const bool ok = run_large(s, w, r, L, block);
-        s->arena->release(block, L.total);
+        const int32_t m = r->m, n = r->n;
+        const size_t tab = align_up((size_t)(padded_ld(m) * ((int64_t)n + m + 1)) * sizeof(double));
+        LaneResult out;
+        const int rc = lane_solve(s->lanes[w], m, n, (double *)r->block, (unsigned char *)r->block + tab, &out);
+        s->arena->release(r->block, r->bytes);
+        const auto now = Clock::now();
         std::lock_guard<std::mutex> lock(s->mu);
-        if (!ok && !s->last_error) s->last_error = LP_E_DEVICE;
-        s->bytes_in_use -= L.total;
+        if (rc != LP_OK) {
+            if (!s->last_error) s->last_error = rc;
+            out.status = LP_NUMERICAL;
+            out.x.assign(n, 0.0);
+            out.y.assign(m, 0.0);
+        }
+        r->status = out.status;
+        r->pivots = out.pivots;
+        r->objective = out.objective;
+        r->x.swap(out.x);
+        r->y.swap(out.y);
+        r->rows.swap(out.rows);
+        r->cols.swap(out.cols);
+        s->bytes_in_use -= r->bytes;
+        r->block = nullptr;
+        s->free_slots.push_back(r->slot);
+        r->slot = -1;
         s->large_busy--;
-        r->t_done = Clock::now();
+        r->t_done = now;
         r->done = true;
         s->completed++;
         s->large_done++;
@@ -672,10 +564,7 @@ void free_server(lp_server *s) {
         if (p) (void)hipFree(p);
     for (auto p : s->staging)
         if (p) (void)hipFree(p);
-    for (auto p : s->large_staging)
-        if (p) (void)hipFree(p);
-    for (auto p : s->large_pin)
-        if (p) (void)hipHostFree(p);
+    for (auto L : s->lanes) lane_destroy(L);
     for (auto cs : s->large_streams)
         if (cs) {
             (void)hipStreamSynchronize(cs);
@@ -731,14 +620,12 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
     };
     for (auto &p : s->staging)
         if (int rc = dmalloc((void **)&p, s->staging_bytes)) return fail(rc);
-    for (auto &p : s->large_staging)
-        if (int rc = dmalloc((void **)&p, s->staging_bytes)) return fail(rc);
-    for (auto &p : s->large_pin)
-        if (hipHostMalloc((void **)&p, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
-            return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
     for (auto &cs : s->large_streams)
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
             return fail(set_error(LP_E_DEVICE, "hipStreamCreate failed"));
+    for (int w = 0; w < lp_server::kLargeWorkers; ++w)
+        if (int rc = lane_create(&s->lanes[w], s->device, s->large_streams[w], o, kLaneMax, kLaneMax))
+            return fail(rc);
     if (int rc = dmalloc((void **)&s->desc, (size_t)s->max_slots * sizeof(BatchDesc))) return fail(rc);
     if (int rc = dmalloc((void **)&s->state, (size_t)s->max_slots * sizeof(BatchState))) return fail(rc);
     if (int rc = dmalloc((void **)&s->order, (size_t)s->max_slots * sizeof(int32_t))) return fail(rc);
@@ -805,10 +692,9 @@ int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const 
     }
     for (int32_t j = 0; j < n; ++j)
         if (!std::isfinite(c[j])) return set_error(LP_E_INVAL, "non-finite c");
-    const int64_t maxp = s->opt.max_pivots > 0 ? s->opt.max_pivots : 50 * ((int64_t)m + n);
-    const Layout L = layout_of(m, n, maxp, s->opt.record_pivots != 0, s->lds);
-    const size_t need = L.tab > kLargeTableauBytes ? large_layout_of(m, n, maxp, s->opt.record_pivots != 0).total
-                                                   : L.total;
+    const bool large = (size_t)(padded_ld(m) * ((int64_t)n + m + 1)) * sizeof(double) > kLargeTableauBytes;
+    const size_t need = request_bytes(s, m, n, large);
+    if (need == 0) return set_error(LP_E_INVAL, "no kernel configuration for this LP shape");
     if (need > s->budget) {
         std::lock_guard<std::mutex> lock(s->mu);
         s->rejected++;
@@ -818,6 +704,7 @@ int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const 
     if (!r) return set_error(LP_E_NOMEM, "host allocation failed");
     r->m = m;
     r->n = n;
+    r->large = large;
     r->in.resize((size_t)m * n + m + n);
     std::memcpy(r->in.data(), A, (size_t)m * n * sizeof(double));
     std::memcpy(r->in.data() + (size_t)m * n, b, (size_t)m * sizeof(double));
@@ -831,10 +718,7 @@ int lp_server_submit(lp_server *s, int32_t m, int32_t n, const double *A, const 
         r->ticket = s->next_ticket++;
         r->t_submit = Clock::now();
         s->reqs[r->ticket] = r;
-        if (L.tab > kLargeTableauBytes)
-            s->pending_large.push_back(r);
-        else
-            s->pending.push_back(r);
+        s->pending.push_back(r);
         s->submitted++;
     }
     s->cv_admit.notify_all();
@@ -902,7 +786,7 @@ int lp_server_stats(const lp_server *cs, struct lp_server_stats *st) {
     st->rejected = s->rejected;
     int64_t resident = 0;
     for (auto *r : s->slots) resident += r != nullptr;
-    st->resident_now = resident + (int64_t)s->ready.size() + s->large_busy;
+    st->resident_now = resident + (int64_t)s->ready.size() + (int64_t)s->ready_large.size() + s->large_busy;
     st->bytes_in_use = s->bytes_in_use;
     st->peak_bytes = s->peak;
     st->ticks = s->ticks;

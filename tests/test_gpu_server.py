@@ -83,15 +83,31 @@ def test_served_results_match_the_oracle():
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
 
 
-def test_large_lp_uses_global_work_area():
-    """F and R of a 3400 x 3400 LP exceed 64 KiB of LDS: the kernel keeps
-    them in the LP's global area, with the same pivots."""
-    lp = lpgen.dense_lp(21, 3400, 3400)
+def test_large_lane_matches_the_oracle():
+    """Tableaux above 16 MiB go to the large-LP lane (resident after
+    admission, solved by a lane worker with pivot fusion and the per-pivot
+    decision kernels): the top of the trace, 4096 x 4096, a 3400 x 3400 LP and
+    two mid-size ones, mixed with small LPs of the batched kernel."""
+    big = [lpgen.dense_lp(21, 4096, 4096), lpgen.dense_lp(22, 3400, 3400), lpgen.dense_lp(23, 1300, 900),
+           lpgen.dense_lp(24, 700, 2500)]
     small = mix(2, 6)
-    lps = [(lp.A, lp.b, lp.c)] + small
-    say("serving a 3400 x 3400 LP with 6 small ones")
-    results, _ = serve_all(lps)
+    lps = [(lp.A, lp.b, lp.c) for lp in big[:2]] + small[:3] + [(lp.A, lp.b, lp.c) for lp in big[2:]] + small[3:]
+    say("serving 4096 x 4096, 3400 x 3400, 1300 x 900 and 700 x 2500 LPs with 6 small ones")
+    results, stats = serve_all(lps, budget=16 * GiB)
     check(lps, results)
+    assert stats["completed"] == len(lps)
+
+
+def test_large_lane_budget_and_order():
+    """A budget that holds about two mid-size tableaux at once: every LP still
+    finishes with the oracle's result and the budget is never exceeded."""
+    lps = [(lp.A, lp.b, lp.c) for lp in (lpgen.dense_lp(30 + k, 1100 + 37 * k, 1000 + 53 * k) for k in range(5))]
+    lps += mix(8, 6)
+    budget = 80 << 20  # each mid-size tableau is 19-27 MiB with its work block
+    say("serving 5 mid-size LPs under an 80 MiB budget")
+    results, stats = serve_all(lps, budget=budget)
+    check(lps, results)
+    assert 0 < stats["peak_bytes"] <= budget
 
 
 def test_same_result_alone_and_in_the_mix():
@@ -105,6 +121,28 @@ def test_same_result_alone_and_in_the_mix():
     assert np.array_equal(xa.view(np.uint64), xm.view(np.uint64))
     assert np.array_equal(ya.view(np.uint64), ym.view(np.uint64))
     assert ra["objective"] == rm["objective"] and ra["status"] == rm["status"]
+
+
+def test_large_lane_lp_same_alone_and_in_the_mix():
+    """An LP of the large-LP lane gives the same bits alone and among other
+    large and small LPs (two lane workers and the batched kernel running at
+    once)."""
+    target = lpgen.dense_lp(41, 1500, 1500)
+    others = [lpgen.dense_lp(42 + k, 1200 + 100 * k, 1400 - 100 * k) for k in range(3)]
+    lps = mix(9, 10)
+    lps[2:2] = [(o.A, o.b, o.c) for o in others[:2]]
+    lps.insert(5, (target.A, target.b, target.c))
+    lps.append((others[2].A, others[2].b, others[2].c))
+    alone, _ = serve_all([(target.A, target.b, target.c)])
+    mixed, _ = serve_all(lps)
+    (ra, xa, ya), rows_a, cols_a = alone[0]
+    (rm, xm, ym), rows_m, cols_m = mixed[5]
+    assert rows_a.tolist() == rows_m.tolist() and cols_a.tolist() == cols_m.tolist()
+    assert np.array_equal(xa.view(np.uint64), xm.view(np.uint64))
+    assert np.array_equal(ya.view(np.uint64), ym.view(np.uint64))
+    assert ra["objective"] == rm["objective"] and ra["status"] == rm["status"]
+    o = oracle.solve(target.A, target.b, target.c)
+    assert rows_a.tolist() == o["rows"].tolist() and np.array_equal(xa, o["x"])
 
 
 def test_budget_is_never_exceeded():
