@@ -21,6 +21,12 @@ Parity status of each function (what pins it is in the test suite):
                          closed forms, reduction to `solve` on <= rows with
                          b >= 0 (bit for bit), general certificates.
   certificates_general   pinned: hand-built points.
+  bland_after (either)   pinned: the cycling example below ends at its
+                         optimum; exact-rational run of the same switching
+                         rule (pivot sequence); with Bland's rule forced from
+                         the first pivot, Bland's theorem (no basis repeats)
+                         on degenerate batteries; off, bit-identical to the
+                         plain method.
   The pivot sequence at m = n = 8000 is "parity unpinned" beyond the oracle
   itself: no exact reference finishes at that size; only the certificates pin
   its optimum independently.
@@ -94,6 +100,7 @@ def _load(path=None):
     lib.oracle_solve_general.argtypes = [P]
     lib.oracle_extract_general.argtypes = [P, dp, dp, dp]
     lib.oracle_general_layout.argtypes = [P, ip, ip, ip, ip, dp]
+    lib.oracle_set_bland.argtypes = [P, ctypes.c_int]
     if path is None:
         _lib = lib
     return lib
@@ -115,7 +122,7 @@ class OracleLP:
     """A tableau held by the C reference, advanced pivot by pivot."""
 
     def __init__(self, A, b, c, eps_d=1e-9, eps_p=1e-9, max_pivots=None, log_cap=None, threads=None,
-                 library=None):
+                 library=None, bland_after=0):
         lib = _load(library)
         A = np.ascontiguousarray(A, dtype=np.float64)
         b = np.ascontiguousarray(b, dtype=np.float64)
@@ -136,6 +143,8 @@ class OracleLP:
         if not self._h:
             raise ValueError("oracle_create rejected the LP (bad size, non-finite value or negative b)")
         self._lib = lib
+        if bland_after:
+            lib.oracle_set_bland(self._h, int(bland_after))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -181,9 +190,11 @@ class OracleLP:
         return x, y, float(obj[0])
 
 
-def solve(A, b, c, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threads=None, library=None):
-    """Solves to the end. Returns a dict with status, pivots, objective, x, y, log."""
-    o = OracleLP(A, b, c, eps_d=eps_d, eps_p=eps_p, max_pivots=max_pivots, threads=threads, library=library)
+def solve(A, b, c, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threads=None, library=None, bland_after=0):
+    """Solves to the end. Returns a dict with status, pivots, objective, x, y, log.
+    bland_after = k > 0: Bland's rule after k consecutive degenerate pivots."""
+    o = OracleLP(A, b, c, eps_d=eps_d, eps_p=eps_p, max_pivots=max_pivots, threads=threads, library=library,
+                 bland_after=bland_after)
     try:
         o.step(-1)
         x, y, obj = o.extract()
@@ -194,7 +205,8 @@ def solve(A, b, c, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threads=None, librar
         o.close()
 
 
-def solve_general(A, b, c, sense, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threads=None, library=None):
+def solve_general(A, b, c, sense, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threads=None, library=None,
+                  bland_after=0):
     """The general form (rows <=, >= or = by `sense`: LE, GE, EQ; any sign of
     b; x >= 0) by the two-phase method. Returns a dict with status, pivots,
     objective, x, y (the caller's row order), the pivot log (tableau rows:
@@ -218,6 +230,8 @@ def solve_general(A, b, c, sense, eps_d=1e-9, eps_p=1e-9, max_pivots=None, threa
     if not h:
         raise ValueError("oracle_create_general rejected the LP (bad size, non-finite value or sense)")
     try:
+        if bland_after:
+            lib.oracle_set_bland(h, int(bland_after))
         status = lib.oracle_solve_general(h)
         pivots = lib.oracle_pivots(h)
         x = np.empty(n)

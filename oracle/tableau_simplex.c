@@ -66,6 +66,9 @@ typedef struct {
     int *log_r, *log_q;
     int64_t log_cap;
     int nthreads;
+    /* anti-cycling fallback (oracle_set_bland); see that section */
+    int bland_after;  /* 0: off; k > 0: Bland's rule after k consecutive degenerate pivots */
+    int degen_run;    /* consecutive degenerate pivots so far */
     /* general form only (oracle_create_general); see that section */
     int general;
     int m_in, n_in;   /* the caller's rows and variables */
@@ -209,17 +212,24 @@ static void pivot(oracle_lp *o, int r, int q)
 
 /* Runs up to `steps` pivots (all remaining when steps < 0). Returns the status;
  * OR_RUNNING means the step budget ran out with work left. */
+static int choose_entering_bland(const oracle_lp *o, int limit);
+static int choose_leaving_bland(const oracle_lp *o, int q, int bar);
+static int use_bland(const oracle_lp *o) { return o->bland_after > 0 && o->degen_run >= o->bland_after; }
+static void count_degenerate(oracle_lp *o, int r, int q);
+
 int oracle_step(oracle_lp *o, int64_t steps)
 {
     int64_t done = 0;
     while (o->status == OR_RUNNING && (steps < 0 || done < steps)) {
-        int q = choose_entering(o);
+        const int bland = use_bland(o);
+        int q = bland ? choose_entering_bland(o, o->n + o->m) : choose_entering(o);
         if (q == -1) { o->status = OR_OPTIMAL; break; }
         if (q == -2) { o->status = OR_NUMERICAL; break; }
-        int r = choose_leaving(o, q);
+        int r = bland ? choose_leaving_bland(o, q, o->n + o->m) : choose_leaving(o, q);
         if (r == -1) { o->status = OR_UNBOUNDED; break; }
         if (r == -2) { o->status = OR_NUMERICAL; break; }
         if (o->pivots >= o->max_pivots) { o->status = OR_ITER_LIMIT; break; }
+        count_degenerate(o, r, q);
         pivot(o, r, q);
         if (o->pivots < o->log_cap) {
             o->log_r[o->pivots] = r;
@@ -471,14 +481,17 @@ oracle_lp *oracle_create_general(int m, int n, const double *A, const double *b,
 /* Steps 1-3 until the phase ends (or the cap). */
 static void run_phase(oracle_lp *o)
 {
+    o->degen_run = 0; /* each phase starts with the usual rule */
     while (o->status == OR_RUNNING) {
-        int q = choose_entering_general(o);
+        const int bland = use_bland(o);
+        int q = bland ? choose_entering_bland(o, o->bar) : choose_entering_general(o);
         if (q == -1) { o->status = OR_OPTIMAL; break; }
         if (q == -2) { o->status = OR_NUMERICAL; break; }
-        int r = choose_leaving_general(o, q);
+        int r = bland ? choose_leaving_bland(o, q, o->bar) : choose_leaving_general(o, q);
         if (r == -1) { o->status = OR_UNBOUNDED; break; }
         if (r == -2) { o->status = OR_NUMERICAL; break; }
         if (o->pivots >= o->max_pivots) { o->status = OR_ITER_LIMIT; break; }
+        count_degenerate(o, r, q);
         pivot(o, r, q);
         log_pivot(o, r, q);
     }
@@ -564,4 +577,75 @@ void oracle_general_layout(const oracle_lp *o, int *nprime, int *n_le, int *phas
     if (phase) *phase = o->phase;
     if (perm) memcpy(perm, o->perm, (size_t)o->m_in * sizeof(int));
     if (sign) memcpy(sign, o->sign, (size_t)o->m_in * sizeof(double));
+}
+
+/* ------------------------------------------------------------------------
+ * Anti-cycling fallback. The paper's rule (most negative row-0 entry, lowest
+ * index on ties; minimum ratio, lowest row on ties) can cycle on degenerate
+ * LPs; the iteration cap then ends the solve. With bland_after = k > 0 the
+ * solve switches to Bland's rule once k pivots in a row were degenerate, and
+ * back to the usual rule after the first pivot that is not:
+ *   degenerate   a pivot whose ratio T[r][W-1] / T[r][q] (the step length,
+ *                the same division as Step 2) is at most eps_p: a step the
+ *                pivot tolerance does not tell from no step (the objective
+ *                does not improve, up to round-off);
+ *   Bland, Step 1  the lowest column j (below the bar) with
+ *                T[0][j] < -eps_d; the non-finite checks and the optimality
+ *                test are those of Step 1;
+ *   Bland, Step 2  among the eligible rows with the smallest ratio, the one
+ *                whose basic variable has the lowest index; the non-finite
+ *                checks are those of Step 2.
+ * Bland's rule cannot cycle, and every stretch of degenerate pivots longer
+ * than k runs under it, so the solve terminates. In the general form the
+ * count starts at 0 in each phase and the drive-out pivots leave it alone.
+ */
+
+/* Step 1 under Bland's rule over the columns j < limit. */
+static int choose_entering_bland(const oracle_lp *o, int limit)
+{
+    int q = -1;
+    double best = INFINITY;
+    for (int j = 0; j < limit; ++j) {
+        double v = TAB(o, 0, j);
+        if (isnan(v)) return -2;
+        if (v < best) best = v;
+        if (q < 0 && v < -o->eps_d) q = j;
+    }
+    if (best == -INFINITY) return -2;
+    return q; /* -1: optimal */
+}
+
+/* Step 2 under Bland's rule; rows whose basic column is >= bar never leave. */
+static int choose_leaving_bland(const oracle_lp *o, int q, int bar)
+{
+    const int W = o->W;
+    int r = -1;
+    double best = 0.0;
+    for (int i = 1; i <= o->m; ++i) {
+        double a = TAB(o, i, q);
+        double rhs = TAB(o, i, W - 1);
+        if (!isfinite(a) || isnan(rhs)) return -2;
+        if (a > o->eps_p && o->basis[i - 1] < bar) {
+            double ratio = rhs / a;
+            if (r < 0 || ratio < best || (ratio == best && o->basis[i - 1] < o->basis[r - 1])) {
+                best = ratio;
+                r = i;
+            }
+        }
+    }
+    return r;
+}
+
+/* Before pivot (r, q): counts it as degenerate or resets the count. */
+static void count_degenerate(oracle_lp *o, int r, int q)
+{
+    const double theta = TAB(o, r, o->W - 1) / TAB(o, r, q);
+    o->degen_run = theta <= o->eps_p ? o->degen_run + 1 : 0;
+}
+
+/* Sets k (0 = off); call before the first step. */
+void oracle_set_bland(oracle_lp *o, int bland_after)
+{
+    o->bland_after = bland_after > 0 ? bland_after : 0;
+    o->degen_run = 0;
 }

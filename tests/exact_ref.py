@@ -60,6 +60,8 @@ class ExactTableau:
             if a != b:
                 gap = abs(b - a) / max(abs(a), abs(b), Fraction(1))
                 self.near_ties.append(float(gap))
+            else:
+                self.exact_ties += 1  # broken by the lower index; binary64 may see a rounding apart
         return q
 
     def leaving(self, q):
@@ -75,7 +77,14 @@ class ExactTableau:
         if len(cand) > 1 and cand[0][0] != cand[1][0]:
             a, b = cand[0][0], cand[1][0]
             self.near_ties.append(float(abs(b - a) / max(abs(a), abs(b), Fraction(1))))
+        elif len(cand) > 1 and cand[0][0] != 0:
+            # an exact tie of two nonzero ratios, broken by the lower row;
+            # binary64 may see them a rounding apart (a zero ratio, 0 / a,
+            # is exact on both sides)
+            self.exact_ties += 1
         return cand[0][1]
+
+    exact_ties = 0
 
     def pivot(self, r, q):
         T, W = self.T, self.W
@@ -90,27 +99,72 @@ class ExactTableau:
         self.basis[r - 1] = q
         self.log.append((r, q))
 
+    # The anti-cycling fallback: after `bland_after` degenerate pivots in a
+    # row (ratio <= 0), Bland's rule (lowest eligible column; among the rows
+    # with the smallest ratio, the lowest basic variable) until a pivot that
+    # is not degenerate.
+    bland_after = 0
+    degen_run = 0
+
+    def bland(self):
+        return self.bland_after > 0 and self.degen_run >= self.bland_after
+
+    def entering_bland(self, limit):
+        for j in range(limit):
+            if self.T[0][j] < -self.eps_d:
+                return j
+        return None
+
+    def leaving_bland(self, q, bar):
+        W = self.W
+        cand = [(self.T[i][W - 1] / self.T[i][q], self.basis[i - 1], i) for i in range(1, self.m + 1)
+                if self.T[i][q] > self.eps_p and self.basis[i - 1] < bar]
+        if not cand:
+            return None
+        best = min(cand)
+        if sum(1 for v in cand if v[0] == best[0]) > 1 and best[0] != 0:
+            # an exact tie that Bland's rule breaks by the basic variable;
+            # binary64 may see the two ratios a rounding apart
+            self.exact_ties += 1
+        return best[2]
+
+    def step_rules(self, limit, bar):
+        """(q, r) of the next pivot under the rule in force; None parts end."""
+        if self.bland():
+            q = self.entering_bland(limit)
+            return q, (None if q is None else self.leaving_bland(q, bar))
+        q = self.entering()
+        return q, (None if q is None else self.leaving(q))
+
+    def count(self, r, q):
+        theta = self.T[r][self.W - 1] / self.T[r][q]
+        if self.bland_after and theta != 0 and abs(theta - self.eps_p) <= Fraction(1, 10**6) * self.eps_p:
+            self.near_ties.append(float(abs(theta - self.eps_p) / self.eps_p))  # at the degeneracy threshold
+        self.degen_run = self.degen_run + 1 if theta <= self.eps_p else 0
+
     def solve(self, max_pivots=10_000):
         while True:
-            q = self.entering()
+            q, r = self.step_rules(self.n + self.m, self.n + self.m)
             if q is None:
                 self.status = "OPTIMAL"
                 return self
-            r = self.leaving(q)
             if r is None:
                 self.status = "UNBOUNDED"
                 return self
             if len(self.log) >= max_pivots:
                 self.status = "ITER_LIMIT"
                 return self
+            self.count(r, q)
             self.pivot(r, q)
 
     def objective(self):
         return self.T[0][self.W - 1]
 
 
-def exact_simplex(A, b, c, eps_d=0.0, eps_p=0.0, max_pivots=10_000):
-    return ExactTableau(A, b, c, eps_d, eps_p).solve(max_pivots)
+def exact_simplex(A, b, c, eps_d=0.0, eps_p=0.0, max_pivots=10_000, bland_after=0):
+    t = ExactTableau(A, b, c, eps_d, eps_p)
+    t.bland_after = bland_after
+    return t.solve(max_pivots)
 
 
 def _solve_exact(M, rhs):
@@ -236,6 +290,8 @@ class ExactGeneral(ExactTableau):
         if len(order) > 1 and row0[order[0]] != row0[order[1]]:
             a, b = row0[order[0]], row0[order[1]]
             self.near_ties.append(float(abs(b - a) / max(abs(a), abs(b), Fraction(1))))
+        elif len(order) > 1:
+            self.exact_ties += 1  # broken by the lower index; binary64 may see a rounding apart
         return q
 
     def leaving(self, q):
@@ -251,15 +307,16 @@ class ExactGeneral(ExactTableau):
         return cand[0][1]
 
     def _phase(self, max_pivots):
+        self.degen_run = 0
         while True:
-            q = self.entering()
+            q, r = self.step_rules(self.bar, self.bar)
             if q is None:
                 return "OPTIMAL"
-            r = self.leaving(q)
             if r is None:
                 return "UNBOUNDED"
             if len(self.log) >= max_pivots:
                 return "ITER_LIMIT"
+            self.count(r, q)
             self.pivot(r, q)
 
     def solve(self, max_pivots=10_000):
@@ -301,8 +358,10 @@ class ExactGeneral(ExactTableau):
         return y
 
 
-def exact_general(A, b, c, sense, eps_d=0.0, eps_p=0.0, max_pivots=10_000):
-    return ExactGeneral(A, b, c, sense, eps_d, eps_p).solve(max_pivots)
+def exact_general(A, b, c, sense, eps_d=0.0, eps_p=0.0, max_pivots=10_000, bland_after=0):
+    t = ExactGeneral(A, b, c, sense, eps_d, eps_p)
+    t.bland_after = bland_after
+    return t.solve(max_pivots)
 
 
 def brute_force_general(A, b, c, sense):
