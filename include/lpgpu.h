@@ -51,15 +51,20 @@ enum {
     LP_ITER_LIMIT = 2, /* max_pivots pivots done, another one needed */
     LP_NUMERICAL = 3,  /* Step 1 or Step 2 met a non-finite value (see the contract above) */
     LP_RUNNING = 4,    /* not finished (lp_step budget ran out, or not solved yet) */
-    LP_STALLED = 5     /* a wait of the one-launch decision kernel timed out (its workgroups
+    LP_STALLED = 5,    /* a wait of the one-launch decision kernel timed out (its workgroups
                           were not all resident); the solve was abandoned */
+    LP_INFEASIBLE = 6  /* general form: Phase I ended with artificial variables above zero */
 };
+
+/* Row senses of the general form (lp_create_general). */
+enum { LP_LE = 0, LP_GE = 1, LP_EQ = 2 };
 
 /* Return codes. */
 enum {
     LP_OK = 0,
     LP_E_INVAL = -1,   /* NULL pointer, m or n < 1, non-finite input, bad option */
-    LP_E_NEG_RHS = -2, /* some b_i < 0: the slack basis is infeasible (no Phase I) */
+    LP_E_NEG_RHS = -2, /* some b_i < 0: the slack basis is infeasible (the standard-form
+                          entry points have no Phase I; lp_create_general has) */
     LP_E_NOMEM = -3,   /* device or host allocation failed */
     LP_E_DEVICE = -4,  /* a HIP call failed; lp_last_error() has the text */
     LP_E_STATE = -5,   /* call out of order (e.g. solution before solve) */
@@ -148,6 +153,17 @@ typedef struct {
                                outlive the context                            (default NULL) */
     size_t device_buffer_bytes;
     int32_t device;         /* HIP device ordinal                             (default 0) */
+    int32_t bland_after;    /* anti-cycling fallback (not in the paper): 0 = off, the paper's rule
+                               throughout (default); k > 0 = once k pivots in a row were
+                               degenerate (ratio T[r][W-1] / T[r][q] <= eps_pivot), Bland's
+                               rule (Step 1: the lowest column with T[0][j] < -eps_dual; Step
+                               2: among the rows with the smallest ratio, the one whose basic
+                               variable has the lowest index) until a pivot that is not
+                               degenerate, so the solve cannot cycle. In the general form the
+                               count restarts with each phase; drive-out pivots do not count.
+                               Needs one pivot per pass (fuse_pivots 0 or 1, which it then
+                               implies, and select_workgroups <= 1); the batched form and the
+                               server take 0 only. */
     const lp_tuning *tuning; /* execution choices, read during the call; NULL = defaults */
 } lp_options;
 
@@ -295,6 +311,35 @@ int lp_get_timing(const lp_ctx *h, lp_timing *t);
 
 /* Frees the context and its device memory (not a caller's device_buffer). NULL-safe. */
 void lp_destroy(lp_ctx *h);
+
+/*
+ * General form (not in the paper, whose Initialization Step starts from a
+ * feasible basis): maximise c^T x subject to A_i x <= b_i, >= b_i or = b_i
+ * per sense[i] (LP_LE, LP_GE, LP_EQ), x >= 0, b of any sign, by the
+ * two-phase method on the one-pivot kernels (fuse_pivots must be 0 or 1):
+ *   - rows with b_i < 0 are negated (<= and >= swap); the tableau's rows are
+ *     the <= rows, then the >= rows, then the = rows, each in the caller's
+ *     order; row m+1 carries the caller's objective through Phase I;
+ *   - columns: x (n), one surplus per >= row, one identity column per row
+ *     (slack of a <= row, artificial of a >= or = row) and one for row m+1,
+ *     the RHS: the context has lp_get_info m = m+1 and n = n + #>= rows;
+ *   - Phase I maximises minus the sum of the artificial variables with
+ *     Steps 1-3 (row 0 priced out by subtracting the artificial rows in
+ *     order); LP_INFEASIBLE when its optimum is below -1e-9 * max(1, sum of
+ *     those rows' b);
+ *   - artificial variables still basic are driven out by a pivot on the
+ *     lowest non-artificial column with |entry| > eps_pivot (none: the row
+ *     is redundant and stays, never leaving);
+ *   - Phase II on the carried objective, artificial columns barred.
+ * One pivot count, cap and log cover both phases (log rows are tableau rows).
+ * lp_solve runs both phases; lp_get_solution gives x (n), y (m, the caller's
+ * row order, the duals of its rows: >= 0 on <= rows, <= 0 on >= rows) and
+ * the objective, meaningful when the status is LP_OPTIMAL. lp_step and
+ * lp_reload_device return LP_E_INVAL on such a context. Host inputs are
+ * copied; errors as lp_create (LP_E_INVAL also for a bad sense).
+ */
+int lp_create_general(lp_ctx **out, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+                      const int32_t *sense, const lp_options *opt);
 
 /*
  * For callers that cannot allocate device memory (serving loops or harnesses

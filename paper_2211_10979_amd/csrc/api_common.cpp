@@ -29,6 +29,7 @@ Options resolve_options(const lp_options *opt) {
     r.device_buffer = o.device_buffer;
     r.device_buffer_bytes = o.device_buffer_bytes;
     r.device = o.device;
+    r.bland_after = o.bland_after;
     return r;
 }
 
@@ -64,6 +65,7 @@ int lp_options_default(lp_options *o) {
     o->device_buffer = nullptr;
     o->device_buffer_bytes = 0;
     o->device = 0;
+    o->bland_after = 0;
     o->tuning = nullptr;
     return LP_OK;
 }

@@ -294,6 +294,7 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     *out = nullptr;
     if (count < 1 || !m || !n || !A || !bv || !cv) return set_error(LP_E_INVAL, "bad batch arguments");
     const Options o = resolve_options(opt_in);
+    if (o.bland_after != 0) return set_error(LP_E_INVAL, "the batched form takes bland_after 0 only");
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
     int ndev = 0;

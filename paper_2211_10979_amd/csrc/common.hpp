@@ -33,6 +33,19 @@ struct DevState {
     int32_t nparts;      // number of pricing partials written by the update kernel
     int32_t leave;       // column leaving the basis at the current pivot
     int32_t pq;          // position of the entering column in the rewrite list
+    // General form (two-phase method; the one-pivot kernels only): columns
+    // >= bar never enter, and rows whose basic column is >= bar never leave.
+    // n + m (no effect) for the standard form.
+    int32_t bar;
+    // >= 0: the next select takes pivot (force_r, force_q) without Steps 1-2
+    // (the drive-out of an artificial variable after Phase I), then clears it.
+    int32_t force_r, force_q;
+    // Anti-cycling fallback (the one-pivot kernels only): with bland_after =
+    // k > 0, Bland's rule decides while the last k or more pivots were all
+    // degenerate (a ratio <= eps_p); degen counts them.
+    int32_t bland_after;
+    int32_t degen;
+    int32_t pad_;
 };
 
 // (value, index) pair of the two-stage argmin.
@@ -103,6 +116,7 @@ struct Options : lp_tuning {
     void *device_buffer;
     size_t device_buffer_bytes;
     int32_t device;
+    int32_t bland_after;
 };
 Options resolve_options(const lp_options *opt);
 

@@ -163,6 +163,16 @@ struct lp_ctx {
     int32_t status_host = LP_RUNNING;
     bool ran = false;
     double last_ms = -1.0;
+    // General form (lp_create_general): the caller's sizes, the tableau's row
+    // order and signs, and the phase reached (1: Phase I to run, 3: done).
+    bool general = false;
+    int32_t m_in = 0, n_in = 0, n_le = 0;
+    std::vector<int32_t> perm;
+    std::vector<double> sgn;
+    double feas_scale = 1.0;
+    int gphase = 0;
+    int32_t *gpick = nullptr;  // device: the drive-out column found
+    int32_t bland_after = 0;   // anti-cycling fallback (one pivot per pass)
 };
 
 namespace {
@@ -247,8 +257,13 @@ int configure_ctx(lp_ctx *h, int32_t m, int32_t n, const Options &o) {
     h->log_cap = o.record_pivots ? h->max_pivots : 0;
     // Pivot fusion: the given K, or kAutoFuse unless an option asks for a
     // form that only the one-pivot kernels have.
+    if (o.bland_after < 0) return set_error(LP_E_INVAL, "bland_after must be >= 0");
+    if (o.bland_after > 0 && (o.fuse_pivots > 1 || o.select_workgroups > 1))
+        return set_error(LP_E_INVAL, "bland_after > 0 needs one pivot per pass: fuse_pivots 0 or 1 and "
+                                     "select_workgroups <= 1");
     const bool one_pivot_form = o.update_grid_stride > 0 || o.update_hints != 0 || o.select_workgroups > 1 ||
-                                o.rows_per_thread > 1 || o.cols_per_block > 8 || o.update_block > 256;
+                                o.rows_per_thread > 1 || o.cols_per_block > 8 || o.update_block > 256 ||
+                                o.bland_after > 0;
     // Groups above kMaxFuseSplit pivots need the one-launch decision kernel
     // (at most kMaxDecideWgs workgroups over the rows and the list).
     const int32_t dblock = o.decide_block > 0 ? o.decide_block : 256;
@@ -317,6 +332,7 @@ int configure_ctx(lp_ctx *h, int32_t m, int32_t n, const Options &o) {
     h->use_graph = o.plain_launches == 0;
     h->timing = o.time_kernels != 0;
     h->eager_build = o.eager_build != 0;
+    h->bland_after = o.bland_after;
     if (o.status_readback == 2 && h->fuse <= 1)
         return set_error(LP_E_INVAL, "status_readback 2 needs pivot fusion (fuse_pivots > 1)");
     if (h->fuse > 1) {
@@ -374,6 +390,7 @@ size_t carve_aux(lp_ctx *h, unsigned char *base) {
     take(&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t));
     take(&h->pos, ((size_t)n + m) * sizeof(int32_t));
     take(&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double));
+    take(&h->gpick, 4 * sizeof(int32_t));
     if (h->fuse > 1) {
         take(&h->gs, sizeof(GroupState));
         take(&h->D, (size_t)h->Lg * sizeof(double));
@@ -515,6 +532,10 @@ int enqueue_build(lp_ctx *h, const double *dA, const double *db, const double *d
     init.eps_p = h->eps_p;
     init.fresh = 1;
     init.nparts = h->nparts;
+    init.bar = n + m;
+    init.force_r = init.force_q = -1;
+    init.bland_after = h->bland_after;
+    init.degen = 0;
     if (h->fuse > 1) {
         const int32_t kf = fused_update_kf(h->fuse);
         const int64_t ninit = std::max<int64_t>(std::max<int64_t>((int64_t)n + m, (int64_t)kf * ld), h->Lg + kMaxFuse);
@@ -970,6 +991,80 @@ int run_noalloc(lp_ctx *h, DevState *fin) {
     return LP_OK;
 }
 
+// The relative tolerance of the infeasibility test after Phase I.
+constexpr double kFeasTol = 1e-9;
+
+// Ends a general-form solve with `status` (set on the device and in the
+// host's copy of the final state).
+int general_finish(lp_ctx *h, int32_t status) {
+    hipLaunchKernelGGL(k_set_status, dim3(1), dim3(1), 0, h->stream, h->st, status);
+    LP_HIP_CHECK(hipGetLastError());
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    h->host_st[2].status = status;
+    h->status_host = status;
+    h->gphase = 3;
+    return LP_OK;
+}
+
+// Both phases of a general-form LP: Phase I with Steps 1-3 (columns and rows
+// of the carried objective barred), the infeasibility test, the drive-out of
+// the artificial variables still basic (forced pivots), then rows 0 and m
+// trade places and Phase II runs with the artificial columns barred.
+int run_general(lp_ctx *h) {
+    if (h->gphase != 1) return LP_OK;  // solved already
+    DeviceGuard g(h->device);
+    const int32_t M = h->m, np = h->n, m = h->m_in;
+    const int64_t ld = h->ld, W = h->W;
+    if (int rc = run_until(h, INT64_MAX)) return rc;
+    if (h->host_st[2].status != LP_OPTIMAL) {
+        h->gphase = 3;
+        return LP_OK;
+    }
+    double w = 0.0;
+    LP_HIP_CHECK(hipMemcpy(&w, h->T + (W - 1) * ld, sizeof(double), hipMemcpyDeviceToHost));
+    if (w != w) return general_finish(h, LP_NUMERICAL);
+    if (w < -kFeasTol * h->feas_scale) return general_finish(h, LP_INFEASIBLE);
+    // drive-out: rows 1..m in order whose basic variable is artificial
+    const int32_t allowed = np + h->n_le;
+    std::vector<int32_t> basis((size_t)M);
+    LP_HIP_CHECK(hipMemcpy(basis.data(), h->basis, (size_t)M * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int32_t t = 1; t <= m; ++t) {
+        if (basis[t - 1] < allowed) continue;
+        int32_t j = -1;
+        hipLaunchKernelGGL(k_find_driveout, dim3(1), dim3(256), 0, h->stream, h->T, ld, t, allowed, h->eps_p, h->gpick);
+        LP_HIP_CHECK(hipGetLastError());
+        LP_HIP_CHECK(hipMemcpyAsync(&j, h->gpick, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        if (j < 0) continue;  // a redundant row: its artificial variable stays basic
+        hipLaunchKernelGGL(k_set_force, dim3(1), dim3(1), 0, h->stream, h->st, t, j);
+        hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, h->stream, h->T, ld, M, np, h->parts, h->st, h->F,
+                           h->basis, h->log_r, h->log_q, h->pos);
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)(((int64_t)np + 2 + 255) / 256)), dim3(256), 0, h->stream, h->T,
+                           ld, M, np, h->st, h->cols, h->pos, h->Rl, h->cols_done);
+        launch_update(h);
+        LP_HIP_CHECK(hipGetLastError());
+        DevState s;
+        LP_HIP_CHECK(hipMemcpyAsync(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+        LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        h->pivots_host = s.pivots;
+        if (s.status != LP_RUNNING) {  // the cap
+            h->host_st[2] = s;
+            h->status_host = s.status;
+            h->solution_cached = false;
+            h->counters_cached = false;
+            h->gphase = 3;
+            return LP_OK;
+        }
+    }
+    // Phase II: the carried objective becomes row 0
+    hipLaunchKernelGGL(k_swap_rows, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, h->stream, h->T, ld, W, 0, M);
+    hipLaunchKernelGGL(k_set_bar, dim3(1), dim3(1), 0, h->stream, h->st, allowed);
+    LP_HIP_CHECK(hipGetLastError());
+    if (int rc = run_until(h, INT64_MAX)) return rc;
+    h->gphase = 3;
+    return LP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1007,7 +1102,8 @@ int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double 
     if (!all_finite(A, (int64_t)m * n) || !all_finite(b, m) || !all_finite(c, n))
         return set_error(LP_E_INVAL, "non-finite input");
     for (int32_t i = 0; i < m; ++i)
-        if (b[i] < 0.0) return set_error(LP_E_NEG_RHS, "b has a negative entry: the slack basis is infeasible");
+        if (b[i] < 0.0) return set_error(LP_E_NEG_RHS, "b has a negative entry: the slack basis is infeasible "
+                                                   "(lp_create_general takes any sign of b)");
     lp_ctx *h = nullptr;
     if (int rc = alloc_ctx(&h, m, n, opt)) return rc;
     DeviceGuard g(h->device);
@@ -1036,19 +1132,130 @@ int lp_create(lp_ctx **out, int32_t m, int32_t n, const double *A, const double 
     return LP_OK;
 }
 
+int lp_create_general(lp_ctx **out, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+                      const int32_t *sense, const lp_options *opt) {
+    if (!out) return set_error(LP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < 1 || !A || !b || !c || !sense)
+        return set_error(LP_E_INVAL, "m, n must be >= 1 and inputs non-NULL");
+    if (!all_finite(A, (int64_t)m * n) || !all_finite(b, m) || !all_finite(c, n))
+        return set_error(LP_E_INVAL, "non-finite input");
+    for (int32_t i = 0; i < m; ++i)
+        if (sense[i] < LP_LE || sense[i] > LP_EQ) return set_error(LP_E_INVAL, "sense must be LP_LE, LP_GE or LP_EQ");
+    const Options ro = resolve_options(opt);
+    if (ro.fuse_pivots > 1 || ro.select_workgroups > 1 || ro.update_grid_stride > 0)
+        return set_error(LP_E_INVAL, "the general form runs one pivot per pass: fuse_pivots must be 0 or 1, "
+                                     "select_workgroups <= 1 and update_grid_stride 0");
+    // normalised senses and the tableau order: <= rows, then >=, then =
+    std::vector<int32_t> kind((size_t)m), perm, surplus;
+    int32_t n_le = 0, n_ge = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t k = sense[i];
+        if (b[i] < 0.0 && k != LP_EQ) k = LP_LE + LP_GE - k;
+        kind[i] = k;
+        n_le += k == LP_LE;
+        n_ge += k == LP_GE;
+    }
+    std::vector<double> sgn;
+    for (int32_t want : {LP_LE, LP_GE, LP_EQ})
+        for (int32_t i = 0; i < m; ++i)
+            if (kind[i] == want) {
+                perm.push_back(i);
+                sgn.push_back(b[i] < 0.0 ? -1.0 : 1.0);
+            }
+    // the >= rows are tableau rows n_le+1 .. n_le+n_ge; their surplus columns n ..
+    surplus.assign((size_t)m, -1);
+    for (int32_t t = n_le; t < n_le + n_ge; ++t) surplus[t] = n + (t - n_le);
+    const int32_t np = n + n_ge, M = m + 1;
+    lp_options o = opt ? *opt : lp_options{};
+    if (!opt) lp_options_default(&o);
+    lp_tuning tun;
+    if (o.tuning)
+        tun = *o.tuning;
+    else
+        lp_tuning_default(&tun);
+    tun.fuse_pivots = 1;
+    o.tuning = &tun;
+    lp_ctx *h = nullptr;
+    if (int rc = alloc_ctx(&h, M, np, &o)) return rc;
+    DeviceGuard g(h->device);
+    h->general = true;
+    h->m_in = m;
+    h->n_in = n;
+    h->n_le = n_le;
+    h->perm = perm;
+    h->sgn = sgn;
+    h->gphase = 1;
+    // inputs to the device: A, b, c, the signs; then the order and surplus maps
+    const size_t nd = (size_t)m * n + m + n + m;
+    void *stage = nullptr;
+    hipError_t e = hipMalloc(&stage, nd * sizeof(double) + 2 * (size_t)m * sizeof(int32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_ctx(h);
+        return set_error(LP_E_NOMEM, "hipMalloc (input staging) failed");
+    }
+    double *dA = (double *)stage, *db = dA + (size_t)m * n, *dc = db + m, *dsg = dc + n;
+    int32_t *dperm = (int32_t *)(dsg + m), *dsur = dperm + m;
+    int rc = LP_OK;
+    const int64_t ld = h->ld, W = h->W;
+    if (hipMemcpyAsync(dA, A, (size_t)m * n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(db, b, (size_t)m * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(dc, c, (size_t)n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(dsg, sgn.data(), (size_t)m * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(dperm, perm.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(dsur, surplus.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
+        rc = set_error(LP_E_DEVICE, "input copy failed");
+    if (!rc) {
+        const int64_t total = ld * W;
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_build_general, dim3((unsigned)blocks), dim3(256), 0, h->stream, h->T, ld, M, np, n, dA,
+                           db, dc, dperm, dsg, dsur);
+        hipLaunchKernelGGL(k_phase1_row0, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, h->stream, h->T, ld, W,
+                           n_le + 1, m + 1, np + n_le, np + m);
+        if (hipGetLastError() != hipSuccess) rc = set_error(LP_E_DEVICE, "build launch failed");
+    }
+    if (!rc) rc = enqueue_build(h, nullptr, nullptr, nullptr, false);  // the state for a built tableau
+    if (!rc) {
+        hipLaunchKernelGGL(k_set_bar, dim3(1), dim3(1), 0, h->stream, h->st, np + m);  // Phase I
+        if (hipGetLastError() != hipSuccess) rc = set_error(LP_E_DEVICE, "launch failed");
+    }
+    double w0 = 0.0;
+    if (!rc && (hipMemcpyAsync(&w0, h->T + (W - 1) * ld, sizeof(double), hipMemcpyDeviceToHost, h->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess))
+        rc = set_error(LP_E_DEVICE, "build failed");
+    (void)hipFree(stage);
+    // Phase I's objective starts at minus the artificial rows' b summed in row
+    // order, so its negation is that sum exactly: the scale of the test
+    h->feas_scale = std::max(1.0, -w0);
+    if (!rc) rc = capture_graphs(h);
+    if (rc) {
+        free_ctx(h);
+        return rc;
+    }
+    *out = h;
+    return LP_OK;
+}
+
 int lp_reload_device(lp_ctx *h, const double *dA, const double *db, const double *dc) {
     if (!h || !dA || !db || !dc) return set_error(LP_E_INVAL, "NULL argument");
+    if (h->general) return set_error(LP_E_INVAL, "lp_reload_device takes standard-form contexts only");
     DeviceGuard g(h->device);
     return enqueue_build(h, dA, db, dc, true);
 }
 
 int lp_solve(lp_ctx *h) {
     if (!h) return set_error(LP_E_INVAL, "NULL context");
+    if (h->general) return run_general(h);
     return run_until(h, INT64_MAX);
 }
 
 int lp_step(lp_ctx *h, int64_t pivots) {
     if (!h || pivots < 0) return set_error(LP_E_INVAL, "NULL context or negative pivot budget");
+    if (h->general) return set_error(LP_E_INVAL, "lp_step takes standard-form contexts only (use lp_solve)");
     DeviceGuard g(h->device);
     if (h->ran || h->pivots_host > 0) {
         DevState s;
@@ -1075,8 +1282,17 @@ int lp_get_solution(const lp_ctx *hc, lp_result *res, double *x, double *y) {
         LP_HIP_CHECK(hipStreamSynchronize(h->stream));
         s = h->host_st[0];
     }
-    if (x) std::memcpy(x, buf, (size_t)h->n * sizeof(double));
-    if (y) std::memcpy(y, buf + h->n, (size_t)h->m * sizeof(double));
+    if (h->general) {  // the caller's variables, and its rows' duals with their signs
+        if (x) std::memcpy(x, buf, (size_t)h->n_in * sizeof(double));
+        if (y)
+            for (int32_t t = 0; t < h->m_in; ++t) {
+                const double v = buf[(size_t)h->n + t];
+                y[h->perm[t]] = h->sgn[t] == 1.0 ? v : -v;
+            }
+    } else {
+        if (x) std::memcpy(x, buf, (size_t)h->n * sizeof(double));
+        if (y) std::memcpy(y, buf + h->n, (size_t)h->m * sizeof(double));
+    }
     if (res) {
         res->status = s.status;
         res->reserved = 0;

@@ -116,6 +116,40 @@ static __global__ __launch_bounds__(256) void k_zero_words(uint64_t *__restrict_
         p[i] = 0;
 }
 
+// A forced pivot (r, q) = (st->force_r, st->force_q): column q copied to F,
+// then the decision recorded as after Steps 1-2 (the cap still applies);
+// the force is cleared. Used only by the general form's drive-out, whose host
+// loop picks (r, q) with |T[r][q]| > eps_p.
+__device__ __forceinline__ void select_forced(const double *__restrict__ T, int64_t ld, int32_t m, const DevState &s,
+                                              DevState *__restrict__ st, double *__restrict__ F,
+                                              int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
+                                              int32_t *__restrict__ log_q, const int32_t *__restrict__ pos, int tid,
+                                              int nt) {
+    const int32_t q = s.force_q, r = s.force_r;
+    const double *colq = T + (int64_t)q * ld;
+    for (int32_t i = tid; i <= m; i += nt) F[i] = colq[i];
+    if (tid != 0) return;
+    st->force_q = -1;
+    st->force_r = -1;
+    if (s.pivots >= s.max_pivots) {
+        st->status = LP_ITER_LIMIT;
+        st->go = 0;
+        return;
+    }
+    st->r = r;
+    st->q = q;
+    st->p = colq[r];
+    st->leave = basis[r - 1];
+    st->pq = pos[q];
+    basis[r - 1] = q;
+    if (s.pivots < s.log_cap) {
+        log_r[s.pivots] = r;
+        log_q[s.pivots] = q;
+    }
+    st->pivots = s.pivots + 1;
+    st->go = 1;
+}
+
 // Steps 1 and 2 for the next pivot; one workgroup of 1024 threads.
 //   Step 1   final stage of the argmin over the update's per-group partials
 //            (a scan of row 0 before the first pivot);
@@ -138,17 +172,28 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         return;
     }
     const int64_t W = (int64_t)n + m + 1;
+    if (s.force_q >= 0) {  // a forced pivot: no Steps 1-2
+        select_forced(T, ld, m, s, st, F, basis, log_r, log_q, pos, tid, nt);
+        return;
+    }
+    const int32_t bar = s.bar;
+    // the anti-cycling fallback: Bland's rule after bland_after degenerate pivots in a row
+    const bool bland = s.bland_after > 0 && s.degen >= s.bland_after;
 
-    // Step 1: most negative objective-row entry, lowest column on ties.
+    // Step 1: most negative objective-row entry, lowest column on ties (under
+    // Bland's rule the scan also finds the lowest column below -eps_d; the
+    // minimum still decides optimality and the non-finite stop).
     double v = __builtin_inf();
     int32_t q = kNoIndex;
-    if (s.fresh) {
-        for (int32_t j = tid; j < n + m; j += nt) {
+    int32_t qb = kNoIndex;
+    if (s.fresh || bland) {
+        for (int32_t j = tid; j < bar; j += nt) {
             const double t = T[(int64_t)j * ld];
             if (lex_less(t, j, v, q)) {
                 v = t;
                 q = j;
             }
+            if (t < -s.eps_d && j < qb) qb = j;
         }
     } else {
         for (int32_t k = tid; k < s.nparts; k += nt) {
@@ -167,8 +212,14 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         }
         return;
     }
+    if (bland) {  // the lowest eligible column
+        double zb = qb == kNoIndex ? __builtin_inf() : 0.0;
+        block_argmin(zb, qb, sv, si);
+        q = qb;
+    }
 
-    // Step 2: minimum ratio over rows with T[i][q] > eps_p, lowest row on ties.
+    // Step 2: minimum ratio over rows with T[i][q] > eps_p, lowest row on ties
+    // (under Bland's rule, the row whose basic variable has the lowest index).
     // The pivot column is also copied to F on the way (used only if a pivot
     // follows).
     const double *colq = T + (int64_t)q * ld;
@@ -177,22 +228,32 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
     double rv = __builtin_inf();
     int32_t r = kNoIndex;
     int bad = 0;
+    const bool barred_rows = bar < n + m;  // the general form: some rows may not leave
     if (tid == 0) F[0] = colq[0];
     for (int32_t i = 1 + tid; i <= m; i += nt) {
         const double a = colq[i], bb = rhs[i];
         F[i] = a;
         if (step2_bad(a, bb)) {
             bad = 1;
-        } else if (a > s.eps_p) {
+        } else if (a > s.eps_p && (!barred_rows || basis[i - 1] < bar)) {
             const double ratio = bb / a;
-            if (lex_less(ratio, i, rv, r)) {
+            const int32_t key = bland ? basis[i - 1] : i;
+            if (lex_less(ratio, key, rv, r)) {
                 rv = ratio;
-                r = i;
+                r = key;
             }
         }
     }
     bad = __syncthreads_or(bad);
     block_argmin(rv, r, sv, si);
+    if (bland && !bad && r != kNoIndex) {  // the row of the winning basic variable
+        __shared__ int32_t s_row;
+        const int32_t kb = r;
+        for (int32_t i = 1 + tid; i <= m; i += nt)
+            if (basis[i - 1] == kb) s_row = i;
+        __syncthreads();
+        r = s_row;
+    }
     if (bad || r == kNoIndex || s.pivots >= s.max_pivots) {
         if (tid == 0) {
             st->status = bad ? LP_NUMERICAL : (r == kNoIndex ? LP_UNBOUNDED : LP_ITER_LIMIT);
@@ -216,6 +277,7 @@ static __global__ __launch_bounds__(1024) void k_select(const double *__restrict
         }
         st->pivots = s.pivots + 1;
         st->fresh = 0;
+        st->degen = rv <= s.eps_p ? s.degen + 1 : 0;  // the step of this pivot
         st->go = 1;
     }
 }
@@ -413,6 +475,7 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
                                               const DevState *__restrict__ st, ArgMin *__restrict__ parts) {
     if (!st->go) return;
     const int32_t r = st->r;
+    const int32_t bar = st->bar;  // columns >= bar (the RHS among them) are no Step 1 candidates
     const int32_t ncols = n + 2;
     const int32_t rc = (int32_t)(blockIdx.x % (uint32_t)rowchunks);
     const int32_t g = (int32_t)(blockIdx.x / (uint32_t)rowchunks);
@@ -457,7 +520,7 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
             for (int c = 0; c < C; ++c) {
                 const int32_t j = cols[c0 + c];
                 const double y0 = fma(-f[0].x, Rj[c], x[c][0].x);
-                if (j != n + m && lex_less(y0, j, val, idx)) {
+                if (j < bar && lex_less(y0, j, val, idx)) {
                     val = y0;
                     idx = j;
                 }
@@ -484,7 +547,7 @@ __global__ __launch_bounds__(B) void k_update(double *__restrict__ T, int64_t ld
                 y.x = (2 * v == r) ? R : fma(-f.x, R, xx.x);
                 y.y = (2 * v + 1 == r) ? R : fma(-f.y, R, xx.y);
                 cp[v] = y;
-                if (row0 && k == 0 && j != n + m && lex_less(y.x, j, val, idx)) {
+                if (row0 && k == 0 && j < bar && lex_less(y.x, j, val, idx)) {
                     val = y.x;
                     idx = j;
                 }
@@ -509,7 +572,7 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
     const int32_t nvec = (m + 2) / 2;
     const int64_t tiles = (int64_t)rowchunks * (n + 2);
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
-    const int32_t rhs = n + m;
+    const int32_t bar = st->bar;  // columns >= bar (the RHS among them) are no Step 1 candidates
     for (int64_t t0 = blockIdx.x; t0 < tiles; t0 += (int64_t)gridDim.x * U) {
         double2 x[U], f[U];
         double2 *addr[U];
@@ -544,7 +607,7 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
                 const int64_t t = t0 + (int64_t)u * gridDim.x;
                 const int32_t g = (int32_t)(t / rowchunks);
                 const int32_t j = cols[g];
-                parts[g] = ArgMin{j != rhs ? y.x : __builtin_inf(), j != rhs ? j : kNoIndex};
+                parts[g] = ArgMin{j < bar ? y.x : __builtin_inf(), j < bar ? j : kNoIndex};
             }
         }
     }
@@ -588,6 +651,115 @@ static __global__ __launch_bounds__(256) void k_store_basic(double *__restrict__
     y.x = (2 * v == r) ? 1.0 : 0.0;
     y.y = (2 * v + 1 == r) ? 1.0 : 0.0;
     reinterpret_cast<double2 *>(T + col * ld)[v] = y;
+}
+
+// ---- general form (two-phase method) -------------------------------------
+// Tableau of the general form, kernel sizes m = m_in + 1 rows (row m is the
+// caller's objective, carried through Phase I) and n = n' = n_in + surplus
+// columns. Row t (1..m_in) is the caller's row perm[t-1] times sgn[t-1], its
+// surplus column surplus[t-1] (or -1) holds -1, and its identity column is
+// n'+t-1; row m holds -c, then zeros, and its own identity column n'+m_in.
+// Row 0 is left 0 here (k_phase1_row0 writes it). One thread per entry,
+// column-major order.
+static __global__ __launch_bounds__(256) void k_build_general(double *__restrict__ T, int64_t ld, int32_t m,
+                                                              int32_t n, int32_t n_in, const double *__restrict__ A,
+                                                              const double *__restrict__ b,
+                                                              const double *__restrict__ c,
+                                                              const int32_t *__restrict__ perm,
+                                                              const double *__restrict__ sgn,
+                                                              const int32_t *__restrict__ surplus) {
+    const int64_t W = (int64_t)n + m + 1;
+    const int64_t total = ld * W;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx / ld;
+        const int32_t i = (int32_t)(idx - j * ld);
+        double v = 0.0;
+        if (i >= 1 && i < m) {  // a constraint row
+            const int32_t k = perm[i - 1];
+            const bool neg = sgn[i - 1] != 1.0;
+            if (j < n_in) {
+                const double a = A[(int64_t)k * n_in + j];
+                v = neg ? -a : a;
+            } else if (j < n) {
+                v = surplus[i - 1] == j ? -1.0 : 0.0;
+            } else if (j < W - 1) {
+                v = j == (int64_t)n + i - 1 ? 1.0 : 0.0;
+            } else {
+                v = neg ? -b[k] : b[k];
+            }
+        } else if (i == m) {  // the carried objective row
+            if (j < n_in)
+                v = -c[j];
+            else if (j == (int64_t)n + m - 1)
+                v = 1.0;
+        }
+        T[idx] = v;
+    }
+}
+
+// Row 0 of Phase I, one thread per column: 1 under each artificial column
+// [art_c0, art_c1), 0 elsewhere, minus the artificial rows [art_r0, art_r1)
+// one by one in row order.
+static __global__ __launch_bounds__(256) void k_phase1_row0(double *__restrict__ T, int64_t ld, int64_t W,
+                                                            int32_t art_r0, int32_t art_r1, int32_t art_c0,
+                                                            int32_t art_c1) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    const double *col = T + j * ld;
+    double v = (j >= art_c0 && j < art_c1) ? 1.0 : 0.0;
+    for (int32_t t = art_r0; t < art_r1; ++t) v = v - col[t];
+    T[j * ld] = v;
+}
+
+// Swaps rows r1 and r2 over all W columns (Phase II takes the carried
+// objective as row 0).
+static __global__ __launch_bounds__(256) void k_swap_rows(double *__restrict__ T, int64_t ld, int64_t W, int32_t r1,
+                                                          int32_t r2) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= W) return;
+    double *col = T + j * ld;
+    const double a = col[r1];
+    col[r1] = col[r2];
+    col[r2] = a;
+}
+
+// The lowest column j < limit with |T[row][j]| > eps (or -1), one workgroup:
+// the column of an artificial variable's drive-out.
+static __global__ __launch_bounds__(256) void k_find_driveout(const double *__restrict__ T, int64_t ld, int32_t row,
+                                                              int32_t limit, double eps, int32_t *__restrict__ out) {
+    __shared__ int32_t s_min[4];
+    int32_t best = kNoIndex;
+    for (int32_t j = threadIdx.x; j < limit; j += blockDim.x)
+        if (fabs(T[(int64_t)j * ld + row]) > eps) {
+            best = j;
+            break;  // later j of this thread are larger
+        }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off, 64));
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t b0 = s_min[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b0 = min(b0, s_min[w]);
+        *out = b0 == kNoIndex ? -1 : b0;
+    }
+}
+
+// Solver-state edits of the general form's host loop.
+static __global__ void k_set_force(DevState *st, int32_t r, int32_t q) {
+    st->force_r = r;
+    st->force_q = q;
+    st->status = LP_RUNNING;
+}
+static __global__ void k_set_status(DevState *st, int32_t status) { st->status = status; }
+// Sets the columns and rows barred from now on and rescans row 0 at the next
+// select (the start of a phase).
+static __global__ void k_set_bar(DevState *st, int32_t bar) {
+    st->bar = bar;
+    st->fresh = 1;
+    st->degen = 0;  // the anti-cycling count restarts with each phase
+    st->status = LP_RUNNING;
 }
 
 }  // namespace lpgpu

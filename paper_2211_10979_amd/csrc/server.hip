@@ -589,6 +589,7 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
     *out = nullptr;
     if (hbm_budget_bytes < ((size_t)1 << 20)) return set_error(LP_E_INVAL, "budget below 1 MiB");
     const Options o = resolve_options(opt_in);
+    if (o.bland_after != 0) return set_error(LP_E_INVAL, "the server takes bland_after 0 only");
     if (!(o.eps_dual >= 0.0) || !(o.eps_pivot >= 0.0) || !std::isfinite(o.eps_dual) || !std::isfinite(o.eps_pivot))
         return set_error(LP_E_INVAL, "eps_dual and eps_pivot must be finite and >= 0");
     int ndev = 0;

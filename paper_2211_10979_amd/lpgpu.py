@@ -24,8 +24,10 @@ except Exception:  # pragma: no cover - torch is optional
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblpgpu.so")
 
-LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL, LP_RUNNING, LP_STALLED = 0, 1, 2, 3, 4, 5
-STATUS_NAMES = {0: "OPTIMAL", 1: "UNBOUNDED", 2: "ITER_LIMIT", 3: "NUMERICAL", 4: "RUNNING", 5: "STALLED"}
+LP_OPTIMAL, LP_UNBOUNDED, LP_ITER_LIMIT, LP_NUMERICAL, LP_RUNNING, LP_STALLED, LP_INFEASIBLE = 0, 1, 2, 3, 4, 5, 6
+STATUS_NAMES = {0: "OPTIMAL", 1: "UNBOUNDED", 2: "ITER_LIMIT", 3: "NUMERICAL", 4: "RUNNING", 5: "STALLED",
+                6: "INFEASIBLE"}
+LP_LE, LP_GE, LP_EQ = 0, 1, 2  # row senses of the general form
 LP_OK, LP_E_INVAL, LP_E_NEG_RHS, LP_E_NOMEM, LP_E_DEVICE, LP_E_STATE, LP_E_PENDING, LP_E_BUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 
 
@@ -72,6 +74,7 @@ class lp_options(ctypes.Structure):
         ("device_buffer", ctypes.c_void_p),
         ("device_buffer_bytes", ctypes.c_size_t),
         ("device", ctypes.c_int32),
+        ("bland_after", ctypes.c_int32),
         ("tuning", ctypes.POINTER(lp_tuning)),
     ]
 
@@ -154,6 +157,7 @@ SIGNATURES = {
     "lp_tableau_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "lp_create": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _OPT]),
     "lp_create_device": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _OPT]),
+    "lp_create_general": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _I32, _OPT]),
     "lp_reload_device": (ctypes.c_int, [_P, _P, _P, _P]),
     "lp_solve": (ctypes.c_int, [_P]),
     "lp_step": (ctypes.c_int, [_P, _I64]),
@@ -292,6 +296,19 @@ def lp_create(A, b, c, options: lp_options | None = None, **kw):
     return h
 
 
+def lp_create_general(A, b, c, sense, options: lp_options | None = None, **kw):
+    """Creates a general-form context (rows <=, >= or = per `sense`: LP_LE,
+    LP_GE, LP_EQ; any sign of b) from host arrays; returns the handle."""
+    A, b, c = _f64(A), _f64(b), _f64(c)
+    sense = np.ascontiguousarray(sense, dtype=np.int32)
+    m, n = A.shape
+    o = _opts(options, kw)
+    h = ctypes.c_void_p()
+    _check(library().lp_create_general(ctypes.byref(h), m, n, _dp(A), _dp(b), _dp(c), _ip(sense), ctypes.byref(o)),
+           "lp_create_general")
+    return h
+
+
 def lp_create_device(m, n, dA, db, dc, options: lp_options | None = None, **kw):
     """Creates a context from device pointers (ints or torch tensors)."""
     ptr = lambda t: t.data_ptr() if hasattr(t, "data_ptr") else int(t)
@@ -327,11 +344,12 @@ def lp_get_timing(h) -> dict:
     return {name: getattr(t, name) for name, _ in lp_timing._fields_}
 
 
-def lp_get_solution(h, want_x=True, want_y=True):
-    """Returns (result dict, x or None, y or None)."""
+def lp_get_solution(h, want_x=True, want_y=True, m=None, n=None):
+    """Returns (result dict, x or None, y or None). For a general-form
+    context pass the caller's m and n (lp_get_info reports the tableau's)."""
     info = lp_get_info(h)
-    x = np.empty(info.n, dtype=np.float64) if want_x else None
-    y = np.empty(info.m, dtype=np.float64) if want_y else None
+    x = np.empty(info.n if n is None else n, dtype=np.float64) if want_x else None
+    y = np.empty(info.m if m is None else m, dtype=np.float64) if want_y else None
     res = lp_result()
     _check(library().lp_get_solution(h, ctypes.byref(res), _dp(x) if want_x else None, _dp(y) if want_y else None),
            "lp_get_solution")
@@ -560,6 +578,21 @@ def solve(A, b, c, **kw):
     try:
         lp_solve(h)
         res, x, y = lp_get_solution(h)
+        rows, cols = lp_get_pivots(h)
+        res.update(x=x, y=y, rows=rows, cols=cols)
+        return res
+    finally:
+        lp_destroy(h)
+
+
+def solve_general(A, b, c, sense, **kw):
+    """One general-form LP, both phases: returns a dict with status, pivots,
+    objective, x, y (the caller's rows), rows, cols and solve_ms."""
+    m, n = np.shape(A)
+    h = lp_create_general(A, b, c, sense, **kw)
+    try:
+        lp_solve(h)
+        res, x, y = lp_get_solution(h, m=m, n=n)
         rows, cols = lp_get_pivots(h)
         res.update(x=x, y=y, rows=rows, cols=cols)
         return res

@@ -55,7 +55,7 @@ def test_boundary_names_and_option_order():
     assert [n for n in BOUNDARY_CALLS if n not in names] == []
     fields = struct_fields("lp_options")
     assert fields[:len(BOUNDARY_OPTIONS)] == BOUNDARY_OPTIONS
-    assert fields[len(BOUNDARY_OPTIONS):] == ["device", "tuning"]
+    assert fields[len(BOUNDARY_OPTIONS):] == ["device", "bland_after", "tuning"]
 
 
 def test_binding_layout_matches_the_header(lpgpu):
