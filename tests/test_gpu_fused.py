@@ -106,6 +106,19 @@ def test_degenerate_battery(K, decide):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
+@pytest.mark.parametrize("K", range(1, 33))
+def test_every_group_size(K):
+    """Every group size from 1 to 32 with the one-launch decisions, and 1 to
+    16 with two launches per pivot: 16 degenerate LPs each, log, tableau, x
+    and y equal to the oracle's."""
+    say(f"fused K={K}: 16 degenerate LPs")
+    for seed in range(16):
+        A, b, c = degenerate_lp(500 + seed, seed % 4)
+        solve_and_compare(A, b, c, fuse_pivots=K)
+        if K <= 16:
+            solve_and_compare(A, b, c, fuse_pivots=K, decide_kernel=1)
+
+
 @pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (24, 0), (31, 0), (7, 1),
                                      (16, 1)])
 def test_group_boundaries_by_stepping(K, decide):
