@@ -8,13 +8,22 @@ pivot with Steps 1-3 until optimal, and extract x, y and the objective.
 
 Reported:
   value           pivots/s over the timed steps (inputs already in HBM);
-  roofline        the Step 3 update kernel (the dominant one): algorithmic
+  roofline        the Step 3 update pass (the HBM-bound kernel): algorithmic
                   bytes per launch / its average duration from HIP events
                   recorded around it on its own stream during the timed
                   steps, against 8 TB/s;
-  cpu_baseline    the CPU oracle on the host cores, on full solves of the
-                  same LP (generation excluded);
-  batched/serving the batched and the served forms, when built.
+  cpu_baseline    the CPU oracle on the host cores (generation excluded):
+                  full solves of the same LP on all cores (value) and its
+                  first pivots on one, the 200 x 200 and 2000 x 2000 LPs,
+                  the batch of 512 serially and one LP per thread, an
+                  estimate for the serving trace from its first 200 LPs,
+                  and a STREAM-style triad of the host;
+  small           the 200 x 200 and 2000 x 2000 LPs on the GPU;
+  batched         the 512-LP batch against one-at-a-time solves;
+  serving         the 10,000-LP Poisson trace through the server against
+                  one-at-a-time solves of the same trace (arrivals at 1.5x
+                  the one-at-a-time rate; all at once; all at once under a
+                  tight budget).
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
@@ -285,17 +294,65 @@ def bench_batch(args, lpgpu, lpgen, torch):
                 identical_to_single_lp_solver=bool(same), certificates_ok=bool(cert_ok))
 
 
+class Prefetch:
+    """Trace LPs generated in trace order on a pool of threads, at most
+    `ahead` in flight; iterating yields (k, lp). The draws run in C with the
+    interpreter lock released, so the pool keeps pace with the GPU."""
+
+    def __init__(self, lpgen, sizes, workers, ahead, start=0, stop=None):
+        from concurrent.futures import ThreadPoolExecutor
+
+        self.lpgen, self.sizes = lpgen, sizes
+        self.start, self.stop = start, len(sizes) if stop is None else stop
+        self.pool = ThreadPoolExecutor(max_workers=workers)
+        self.ahead = ahead
+
+    def _gen(self, k):
+        m, n = self.sizes[k]
+        return self.lpgen.dense_lp(self.lpgen.TRACE_SEED, m, n, k=k)
+
+    def __iter__(self):
+        from collections import deque
+
+        futs = deque()
+        nxt = self.start
+        while nxt < self.stop and len(futs) < self.ahead:
+            futs.append((nxt, self.pool.submit(self._gen, nxt)))
+            nxt += 1
+        while futs:
+            k, f = futs.popleft()
+            lp = f.result()
+            if nxt < self.stop:
+                futs.append((nxt, self.pool.submit(self._gen, nxt)))
+                nxt += 1
+            yield k, lp
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
+def host_workers():
+    """Worker threads for host-side generation: the CPU share of the box (at
+    most 16), whatever the affinity mask shows."""
+    return max(1, min(16, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16") or 16)))
+
+
 def bench_serve(args, lpgpu, lpgen):
-    """A Poisson arrival stream of dense LPs (m, n log-uniform on [64, 4096])
-    through the server, against one-at-a-time solves of the same trace."""
+    """The Poisson arrival stream of dense LPs (m, n log-uniform on [64,
+    4096]) through the server, against one-at-a-time solves of the same
+    trace. Every LP is generated from its index when it is needed and dropped
+    after it has been handed over, so the host holds only a window of the
+    trace."""
+    import queue
+    import resource
     import threading
 
     from paper_2211_10979_amd.certify import certify
 
     count = args.serve_lps
     sizes, gaps = lpgen.trace_sizes(lpgen.TRACE_SEED, count)
-    log(f"serving: generating {count} LPs")
-    lps = [lpgen.dense_lp(lpgen.TRACE_SEED, m, n, k=k) for k, (m, n) in enumerate(sizes)]
+    workers = host_workers()
+    tab_gb = sum(lpgpu.lp_tableau_bytes(m, n) for m, n in sizes) / (1 << 30)
 
     def solo(lp):
         t0 = time.perf_counter()
@@ -303,102 +360,295 @@ def bench_serve(args, lpgpu, lpgen):
         lpgpu.lp_solve(h)
         res, x, y = lpgpu.lp_get_solution(h)
         lpgpu.lp_destroy(h)
-        return time.perf_counter() - t0, res, x
+        return time.perf_counter() - t0, res, x, y
 
-    # calibrate the one-at-a-time rate on a sample, then set the arrival rate
-    sample = lps[: min(len(lps), 100)]
-    for lp in sample[:5]:
+    # one at a time over the whole trace: service times measured back to back
+    log(f"serving: one-at-a-time baseline over {count} LPs ({workers} generator threads)")
+    warm = Prefetch(lpgen, sizes, workers, 8, stop=min(count, 5))
+    for _, lp in warm:
         solo(lp)
-    t_sample = sum(solo(lp)[0] for lp in sample)
-    c_seq = len(sample) / t_sample
+    warm.close()
+    service = np.empty(count)
+    solo_piv = np.empty(count, dtype=np.int64)
+    solo_status = np.empty(count, dtype=np.int64)
+    solo_x = [None] * count
+    cert_ok = True
+    pf = Prefetch(lpgen, sizes, workers, 4 * workers)
+    for k, lp in pf:
+        dt, res, x, y = solo(lp)
+        service[k] = dt
+        solo_piv[k] = res["pivots"]
+        solo_status[k] = res["status"]
+        solo_x[k] = x
+        if k < 200:
+            cert_ok &= bool(certify(lp.A, lp.b, lp.c, x, y, res["objective"])[0])
+        if k % 2000 == 1999:
+            log(f"serving: one-at-a-time {k + 1}/{count}")
+    pf.close()
+    c_seq = count / float(service.sum())
     lam = args.serve_load * c_seq
     arrivals = np.cumsum(gaps) / lam
-
-    # one at a time on the same trace: service times measured back to back,
-    # each LP starts at max(its arrival, previous finish)
-    log("serving: one-at-a-time baseline")
+    arrivals -= arrivals[0]
+    # the same trace, one at a time: each LP starts at max(its arrival, the
+    # previous finish)
     finish = 0.0
-    lat = []
-    solo_res = []
-    for lp, arr in zip(lps, arrivals):
-        dt, res, x = solo(lp)
-        start = max(arr, finish)
-        finish = start + dt
-        lat.append(finish - arr)
-        solo_res.append((res, x))
-    solo_makespan = finish - arrivals[0]
+    lat = np.empty(count)
+    for k in range(count):
+        finish = max(arrivals[k], finish) + service[k]
+        lat[k] = finish - arrivals[k]
+    solo_makespan = finish
 
-    def serve(arr_times):
-        s = lpgpu.lp_server_create(int(args.serve_budget_gb * (1 << 30)), args.serve_slots)
-        tickets = [None] * count
+    def serve(arr_times, submitters, slots, budget_gb=None):
+        """Submits the trace at the given times (submitter threads take LPs
+        from one generator in trace order) and collects every result."""
+        budget_gb = args.serve_budget_gb if budget_gb is None else budget_gb
+        s = lpgpu.lp_server_create(int(budget_gb * (1 << 30)), slots)
+        tickets = queue.Queue()
+        mismatches = [0]
+        failures = []
         try:
+            pf = Prefetch(lpgen, sizes, workers, 4 * workers)
+            it = iter(pf)
+            lock = threading.Lock()
             t0 = time.perf_counter()
 
             def submitter():
-                for k, (lp, arr) in enumerate(zip(lps, arr_times)):
-                    wait = arr - (time.perf_counter() - t0)
-                    if wait > 0:
-                        time.sleep(wait)
-                    tickets[k] = lpgpu.lp_server_submit(s, lp.A, lp.b, lp.c)
+                try:
+                    while True:
+                        with lock:
+                            try:
+                                k, lp = next(it)
+                            except StopIteration:
+                                return
+                        wait = arr_times[k] - (time.perf_counter() - t0)
+                        if wait > 0:
+                            time.sleep(wait)
+                        tickets.put((k, lpgpu.lp_server_submit(s, lp.A, lp.b, lp.c)))
+                except Exception as e:  # reported after the run
+                    failures.append(e)
+                    tickets.put((-1, None))
 
-            th = threading.Thread(target=submitter)
-            th.start()
-            th.join()
-            out = [lpgpu.lp_server_wait(s, tickets[k], lp.m, lp.n) for k, lp in enumerate(lps)]
+            ths = [threading.Thread(target=submitter) for _ in range(submitters)]
+            for th in ths:
+                th.start()
+            for done in range(count):
+                k, t = tickets.get()
+                if k < 0:
+                    raise failures[0]
+                m, n = sizes[k]
+                res, x, _ = lpgpu.lp_server_wait(s, t, m, n)
+                if res["pivots"] != solo_piv[k] or res["status"] != solo_status[k] or not np.array_equal(x, solo_x[k]):
+                    mismatches[0] += 1
+                if done % 2000 == 1999:
+                    log(f"serving: {done + 1}/{count} results")
             span = time.perf_counter() - t0
-            st = lpgpu.lp_server_get_stats(s)
+            for th in ths:
+                th.join()
+            pf.close()
+            st = lpgpu.lp_server_stats(s)
         finally:
             lpgpu.lp_server_destroy(s)
-        return out, span, st
+        return span, st, mismatches[0]
 
-    log("serving: server, Poisson arrivals")
-    served, makespan, st = serve(arrivals - arrivals[0])
+    log(f"serving: server, Poisson arrivals at {lam:.1f}/s")
+    makespan, st, bad = serve(arrivals, 1, args.serve_slots)
     log("serving: server, all requests at once")
-    burst, burst_span, burst_st = serve(np.zeros(count))
-    same = all(sr[0]["pivots"] == so[0]["pivots"] and np.array_equal(sr[1], so[1])
-               for sr, so in zip(served, solo_res))
-    cert = all(certify(lp.A, lp.b, lp.c, x, y, r["objective"])[0] for (r, x, y), lp in zip(served[:200], lps))
+    burst_span, burst_st, burst_bad = serve(np.zeros(count), workers, max(args.serve_slots, count))
+    log(f"serving: server, all requests at once under a {args.serve_tight_gb} GB budget")
+    tight_span, tight_st, tight_bad = serve(np.zeros(count), workers, max(args.serve_slots, count),
+                                            budget_gb=args.serve_tight_gb)
+    peak_rss_gb = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / (1 << 20)
     return dict(workload=f"{count} dense LPs of the Poisson trace (m, n log-uniform on [64, 4096], seed "
-                         f"{lpgen.TRACE_SEED}), arrival rate {args.serve_load} x the one-at-a-time rate",
+                         f"{lpgen.TRACE_SEED}, {tab_gb:.1f} GB of tableaux in all), arrival rate "
+                         f"{args.serve_load} x the one-at-a-time rate",
                 lps=count, arrival_rate_per_s=round(lam, 1), budget_gb=args.serve_budget_gb,
                 max_slots=args.serve_slots, solves_per_s=round(count / makespan, 1),
                 p50_ms=round(st["p50_ms"], 3), p99_ms=round(st["p99_ms"], 3),
                 peak_resident_gb=round(st["peak_bytes"] / (1 << 30), 3), ticks=st["ticks"],
                 one_at_a_time_solves_per_s=round(count / solo_makespan, 1),
+                one_at_a_time_service_solves_per_s=round(c_seq, 1),
                 one_at_a_time_p50_ms=round(1e3 * float(np.percentile(lat, 50)), 3),
                 one_at_a_time_p99_ms=round(1e3 * float(np.percentile(lat, 99)), 3),
+                speedup_vs_one_at_a_time=round(solo_makespan / makespan, 3),
                 saturated_solves_per_s=round(count / burst_span, 1),
+                saturated_speedup_vs_one_at_a_time=round((count / burst_span) / c_seq, 3),
                 saturated_p50_ms=round(burst_st["p50_ms"], 3), saturated_p99_ms=round(burst_st["p99_ms"], 3),
+                saturated_max_slots=max(args.serve_slots, count),
                 saturated_peak_resident_gb=round(burst_st["peak_bytes"] / (1 << 30), 3),
-                identical_to_one_at_a_time=bool(same and all(
-                    b[0]["pivots"] == so[0]["pivots"] and np.array_equal(b[1], so[1]) for b, so in zip(burst, solo_res))),
-                certificates_ok_first_200=bool(cert))
+                tight_budget_gb=args.serve_tight_gb, tight_solves_per_s=round(count / tight_span, 1),
+                tight_p50_ms=round(tight_st["p50_ms"], 3), tight_p99_ms=round(tight_st["p99_ms"], 3),
+                tight_peak_resident_gb=round(tight_st["peak_bytes"] / (1 << 30), 3),
+                identical_to_one_at_a_time=bool(bad == 0 and burst_bad == 0 and tight_bad == 0),
+                mismatches=bad + burst_bad + tight_bad, certificates_ok_first_200=bool(cert_ok),
+                peak_host_rss_gb=round(peak_rss_gb, 2), generator_threads=workers)
 
 
-def cpu_baseline(args, lp, gpu_log):
+# ---------------------------------------------------------------- CPU legs
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def stream_triad(threads, n=1 << 26, reps=5):
+    """STREAM-style triad a = b + s * c over three arrays of n doubles, split
+    over `threads` threads (numpy releases the interpreter lock). Each chunk
+    goes through a small cache-resident temporary, so memory traffic is the
+    triad's 24 bytes per element. Best of `reps`, in GB/s."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    a = np.zeros(n)
+    b = np.ones(n)
+    c = np.full(n, 2.0)
+    step = 1 << 19
+    bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+
+    def part(t):
+        tmp = np.empty(step)
+        for lo in range(bounds[t], bounds[t + 1], step):
+            hi = min(lo + step, bounds[t + 1])
+            w = tmp[: hi - lo]
+            np.multiply(c[lo:hi], 3.0, out=w)
+            np.add(b[lo:hi], w, out=a[lo:hi])
+
+    best = 0.0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(part, range(threads)))
+            best = max(best, 24.0 * n / (time.perf_counter() - t0) / 1e9)
+    return round(best, 1)
+
+
+def cpu_leg_omp(args):
+    """The CPU oracle's OpenMP legs, in a child process that never touches
+    the GPU, run with OMP_PROC_BIND=close: the benchmark LP with all cores
+    and with one, and the two small single LPs; input generation excluded."""
     import oracle
+    from paper_2211_10979_amd import lpgen
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    budget = args.cpu_seconds
-    t_total = 0.0
-    pivots = 0
-    solves = 0
-    match = None
-    while solves == 0 or t_total < budget:
-        o = oracle.OracleLP(lp.A, lp.b, lp.c, threads=threads)
+    threads = host_workers()
+    out = dict(cpu_model=cpu_model(), nproc=len(os.sched_getaffinity(0)), threads=threads,
+               omp_proc_bind=os.environ.get("OMP_PROC_BIND"))
+
+    def timed_solves(lp, nthreads, budget):
+        """Full solves until `budget` seconds have passed (at least one)."""
+        t_total, piv, solves, log0 = 0.0, 0, 0, None
+        while solves == 0 or t_total < budget:
+            o = oracle.OracleLP(lp.A, lp.b, lp.c, threads=nthreads)
+            t0 = time.perf_counter()
+            o.step(-1)
+            t_total += time.perf_counter() - t0
+            piv += o.pivots
+            solves += 1
+            if log0 is None:
+                log0 = o.log()
+            o.close()
+        return t_total, piv, solves, log0
+
+    lp = lpgen.workload(args.workload)
+    t_all, piv, solves, olog = timed_solves(lp, threads, args.cpu_seconds)
+    gpu = np.load(args.gpu_log)
+    match = olog[0].tolist() == gpu["rows"].tolist() and olog[1].tolist() == gpu["cols"].tolist()
+    out["value"] = piv / t_all
+    out["sample"] = (f"{solves} full solve(s) of {args.workload} ({piv // solves} pivots each) on {threads} threads, "
+                     f"{t_all:.1f} s, input generation excluded")
+    out["solves_per_s"] = solves / t_all
+    out["oracle_log_matches_gpu"] = bool(match)
+    # one thread: the first pivots of the same LP, timed pivot by pivot
+    o = oracle.OracleLP(lp.A, lp.b, lp.c, threads=1)
+    t1 = 0.0
+    while t1 < args.cpu_seconds / 3 and o.status == oracle.RUNNING:
         t0 = time.perf_counter()
-        o.step(-1)
-        t_total += time.perf_counter() - t0
-        pivots += o.pivots
-        solves += 1
-        if match is None:
-            r, q = o.log()
-            match = r.tolist() == gpu_log[0].tolist() and q.tolist() == gpu_log[1].tolist()
-        o.close()
-    return dict(value=pivots / t_total, unit="pivots/s", cores=threads, kind="oracle",
-                sample=f"{solves} full solve(s) of {args.workload} ({pivots // solves} pivots each), "
-                       f"{t_total:.1f} s of CPU time, input generation excluded",
-                solves_per_s=solves / t_total, oracle_log_matches_gpu=bool(match))
+        o.step(1)
+        t1 += time.perf_counter() - t0
+    k1 = o.pivots
+    o.close()
+    out["one_thread"] = dict(value=k1 / t1, unit="pivots/s", sample=f"first {k1} pivots of {args.workload}, 1 thread")
+    for name in ("dense_200x200", "dense_2000x2000"):
+        small = lpgen.workload(name)
+        t, p, sv, _ = timed_solves(small, threads, 1.0)
+        out[name] = dict(pivots_per_s=p / t, solves_per_s=sv / t, solves=sv, threads=threads)
+    return out
+
+
+def cpu_leg_lp(args):
+    """The CPU oracle one LP per thread (single-threaded oracle, no OpenMP
+    binding, so the threads spread over the cores), in a child process that
+    never touches the GPU: the batch of 512 serially and in parallel, and a
+    sample of the serving trace; plus the host's STREAM-style triad."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_2211_10979_amd import lpgen
+
+    threads = host_workers()
+    out = dict(triad_gbs_1_thread=stream_triad(1), triad_gbs_all=stream_triad(threads))
+    bsizes = lpgen.batch_sizes(lpgen.BATCH_SEED, 512)
+    blps = [lpgen.dense_lp(lpgen.BATCH_SEED, m, n, k=k) for k, (m, n) in enumerate(bsizes)]
+
+    def one(lp1):
+        o1 = oracle.OracleLP(lp1.A, lp1.b, lp1.c, threads=1)
+        o1.step(-1)
+        p1 = o1.pivots
+        o1.close()
+        return p1
+
+    t0 = time.perf_counter()
+    bp = sum(one(x) for x in blps)
+    t_serial = time.perf_counter() - t0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        t0 = time.perf_counter()
+        bp2 = sum(ex.map(one, blps))
+        t_par = time.perf_counter() - t0
+    out["batch_512"] = dict(serial_solves_per_s=512 / t_serial, lp_parallel_solves_per_s=512 / t_par,
+                            pivots=bp, same_pivots=bool(bp == bp2), threads=threads)
+    # the serving trace: its first LPs (the order is random, so the prefix is a
+    # random sample) one per thread, until 200 LPs or the time budget
+    tsizes, _ = lpgen.trace_sizes(lpgen.TRACE_SEED, 10000)
+    done, t_sample = 0, 0.0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        while done < 200 and t_sample < args.cpu_seconds:
+            chunk = [lpgen.dense_lp(lpgen.TRACE_SEED, m, n, k=done + i)
+                     for i, (m, n) in enumerate(tsizes[done: min(200, done + threads)])]
+            t0 = time.perf_counter()
+            list(ex.map(one, chunk))
+            t_sample += time.perf_counter() - t0
+            done += len(chunk)
+    rate = done / t_sample
+    out["trace_estimate"] = dict(estimate=True, sample_lps=done, sample_seconds=round(t_sample, 2),
+                                 solves_per_s=rate, est_seconds_for_10000=10000 / rate, threads=threads,
+                                 how="the trace's first LPs, one per thread; 10,000 / their rate")
+    return out
+
+
+def cpu_baseline(args, gpu_log):
+    """Runs the CPU legs in child processes (no GPU): the OpenMP legs with
+    OMP_PROC_BIND=close, the one-LP-per-thread legs without binding."""
+    import subprocess
+    import tempfile
+
+    out = {}
+    with tempfile.TemporaryDirectory() as d:
+        lpath = os.path.join(d, "log.npz")
+        np.savez(lpath, rows=gpu_log[0], cols=gpu_log[1])
+        for part, bind in (("omp", "close"), ("lp", "false")):
+            opath = os.path.join(d, f"{part}.json")
+            env = dict(os.environ, OMP_PROC_BIND=bind, OMP_NUM_THREADS=str(host_workers()))
+            cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", part, "--cpu-out", opath, "--gpu-log",
+                   lpath, "--workload", args.workload, "--cpu-seconds", str(args.cpu_seconds)]
+            subprocess.run(cmd, env=env, check=True)
+            with open(opath) as f:
+                out.update(json.load(f))
+    threads = out.pop("threads")
+    return dict(value=out.pop("value"), unit="pivots/s", cores=threads, kind="oracle", sample=out.pop("sample"),
+                **out)
 
 
 def main():
@@ -417,15 +667,28 @@ def main():
     ap.add_argument("--batch-lps", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-lps", type=int, default=1000,
+    ap.add_argument("--serve-lps", type=int, default=10000,
                     help="LPs of the arrival trace served (the full trace has 10000)")
     ap.add_argument("--serve-load", type=float, default=1.5, help="arrival rate / one-at-a-time solve rate")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-tight-gb", type=float, default=0.5,
+                    help="budget of a second saturated leg in which the budget binds")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--small-steps", type=int, default=20, help="timed steps of the 200 x 200 and 2000 x 2000 legs")
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--cpu-leg", default=None, choices=("omp", "lp"), help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-out", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--gpu-log", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run the plain copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.cpu_leg:  # a child process of cpu_baseline: CPU only
+        out = cpu_leg_omp(args) if args.cpu_leg == "omp" else cpu_leg_lp(args)
+        with open(args.cpu_out, "w") as f:
+            json.dump(out, f)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -473,6 +736,19 @@ def main():
         roofline=roof,
         plain=plain,
     )
+    if not args.no_small:
+        line["small"] = {}
+        for name in ("dense_200x200", "dense_2000x2000"):
+            log(f"plain solve: {name}")
+            sargs = argparse.Namespace(**{**vars(args), "workload": name, "steps": args.small_steps})
+            r = bench_plain(sargs, lpgpu, lpgen, torch)
+            r.pop("lp"), r.pop("log")
+            rf = r.pop("roofline", None)
+            line["small"][name] = dict(pivots_per_s=round(r["value"], 1), solves_per_s=round(r["solves_per_s"], 1),
+                                       ms_per_step=round(r["ms_per_step"], 4), pivots_per_solve=r["pivots_per_solve"],
+                                       status=r["status"], certificates_ok=r["certificates_ok"],
+                                       update_kernel=None if rf is None else rf["kernel"],
+                                       update_avg_launch_us=None if rf is None else rf["avg_launch_us"])
     if not args.no_batch:
         log(f"batched: {args.batch_lps} LPs")
         line["batched"] = bench_batch(args, lpgpu, lpgen, torch)
@@ -480,7 +756,7 @@ def main():
         line["serving"] = bench_serve(args, lpgpu, lpgen)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle")
-        line["cpu_baseline"] = cpu_baseline(args, lp, gpu_log)
+        line["cpu_baseline"] = cpu_baseline(args, gpu_log)
     print(json.dumps(line), flush=True)
 
 
