@@ -655,55 +655,112 @@ __device__ __forceinline__ void block_argmin_dpp(double &v, int32_t &i, int32_t 
 //   the decision (every workgroup reduces all Step 2 partials, so all agree;
 //     workgroup 0 records it) and the Step 3 inputs of its slots -> one
 //     Step 1 partial per workgroup;                       barrier.
-// The barrier is a counter of arrivals; a workgroup waits for G arrivals per
-// barrier passed. The wait is bounded (spin_limit polls): if some workgroup
-// never arrives (the G workgroups were not all resident), the waiting ones
-// set LP_STALLED and leave, so every wave exits. The last workgroup to exit
-// resets the counter for the next launch.
+// A barrier carries the partials it waits for: each workgroup publishes its
+// partial as a record of 64-bit words in a line of its own, each word 32 bits
+// of the partial with the launch's flag in the upper half (an aligned 64-bit
+// store is single-copy atomic, so a word with the current flag holds current
+// data), and waits by reading every workgroup's record until all words carry
+// the flag: the partials arrive with the wait, with no counter and no second
+// read. Every barrier of a launch has records of its own and every launch a
+// flag of its own (epoch + 1, the epoch advanced by the last workgroup to
+// leave), so no record is reused within a launch and an old record never
+// passes for a new one. The wait is bounded (spin_limit polls): if some
+// workgroup never arrives (the G workgroups were not all resident), the
+// waiting ones set LP_STALLED and leave, so every wave exits.
+constexpr int kXchWords = 16;  // words per record: one 128-byte line
+constexpr int kMaxDecideBarriers = 2 * kMaxFuse + 2;
+constexpr int kMaxDecideWgsXch = 128;  // records per barrier (the decision kernel's workgroup limit)
 struct GridSync {
-    uint32_t count;  // barrier arrivals in this launch
-    uint32_t exits;  // workgroups that have left
+    uint32_t count;  // (unused by the data-carrying barrier)
+    uint32_t exits;  // workgroups that have left this launch
+    uint32_t epoch;  // launches completed
+    uint32_t pad_[29];
+    uint64_t xch[kMaxDecideBarriers][kMaxDecideWgsXch][kXchWords];
 };
 
-// Thread 0 arrives with a release increment (the workgroup's writes, which
-// the workgroup barrier orders before it, become visible with the arrival),
-// polls the counter with relaxed loads, and after the wait issues one acquire
-// fence: the relaxed load that sees the target reads from the release
-// sequence of every arrival, so the fence makes all their writes visible
-// (fence synchronisation). An acquire on every poll would invalidate the
-// cache on every poll.
-//
-// A wait that gives up marks the solve LP_STALLED and the group as stalled.
-// Arrivals of workgroups that gave up still count, so a late workgroup can
-// pass a barrier that the others abandoned: every workgroup therefore
-// re-reads the status after each wait and leaves if the solve has stalled,
-// and the final status is written only over LP_RUNNING (finish_status), so
-// LP_STALLED is never overwritten.
-__device__ __forceinline__ bool grid_barrier(GridSync *gsync, uint32_t target, uint32_t spin_limit,
-                                             DevState *st, GroupState *gs, int32_t *s_ok) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&gsync->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Publishes this workgroup's record for a barrier: one thread, after a
+// workgroup barrier that follows the workgroup's writes, so that the release
+// fence makes them visible with the record (fence synchronisation with the
+// waiters' acquire fence).
+template <int N>
+__device__ __forceinline__ void xch_publish(uint64_t *rec, const uint32_t (&d)[N], uint32_t flag) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        __hip_atomic_store(rec + k, ((uint64_t)flag << 32) | d[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits for the records of all G workgroups (N words each) at `recs`: wave 0
+// polls (lane l reads record l and record l + 64) and copies the data words
+// to LDS (xs[w][k]), then the workgroup passes its barrier. A wait that gives
+// up marks the solve LP_STALLED and the group as stalled. A workgroup that
+// arrives late can still find every record of a barrier that others abandoned
+// (those who gave up had published theirs), so the poll also reads the status
+// and a stalled solve fails the wait: the final status is written only over
+// LP_RUNNING (finish_status), so LP_STALLED is never overwritten.
+template <int N>
+__device__ __forceinline__ bool xch_wait(const uint64_t (*recs)[kXchWords], int G, uint32_t flag, uint32_t spin_limit,
+                                         DevState *st, GroupState *gs, uint32_t (*xs)[N], int32_t *s_ok) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        uint64_t a[N], b[N];
         uint32_t it = 0;
-        bool ok = true;
-        while (__hip_atomic_load(&gsync->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++it > spin_limit) {
-                ok = false;
+        bool ok = false;
+        for (;;) {
+            bool mine = true;
+            if (lane < G) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    a[k] = __hip_atomic_load(&recs[lane][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mine &= (uint32_t)(a[k] >> 32) == flag;
+                }
+            }
+            if (lane + 64 < G) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    b[k] = __hip_atomic_load(&recs[lane + 64][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mine &= (uint32_t)(b[k] >> 32) == flag;
+                }
+            }
+            const int32_t stv =
+                lane == 0 ? __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+            const bool stalled = __builtin_amdgcn_readfirstlane(stv) == LP_STALLED;
+            const bool all = __ballot(!mine) == 0;
+            if (stalled) break;
+            if (all) {
+                ok = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            if (++it > spin_limit) {
+                if (lane == 0) {
+                    atomicExch(&st->status, (int32_t)LP_STALLED);
+                    atomicExch(&gs->stalled, 1);
+                }
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
-        if (!ok) {
-            atomicExch(&st->status, (int32_t)LP_STALLED);
-            atomicExch(&gs->stalled, 1);
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane < G) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) xs[lane][k] = (uint32_t)a[k];
+            }
+            if (lane + 64 < G) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) xs[lane + 64][k] = (uint32_t)b[k];
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (ok && __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == LP_STALLED)
-            ok = false;
-        *s_ok = ok;
+        if (lane == 0) *s_ok = ok;
     }
     __syncthreads();
     return *s_ok != 0;
+}
+
+__device__ __forceinline__ uint32_t lo32(double v) { return (uint32_t)__double_as_longlong(v); }
+__device__ __forceinline__ uint32_t hi32(double v) { return (uint32_t)((uint64_t)__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // The status that ends the solve, written only while it is LP_RUNNING.
@@ -762,12 +819,18 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     __shared__ double sv_r[BD / 64], sv_s[BD / 64], sv_0[BD / 64];
     __shared__ int32_t si_r[BD / 64], si_s[BD / 64], si_0[BD / 64];
     __shared__ int32_t sl_r[BD / 64], sl_s[BD / 64], sl_0[BD / 64];
+    (void)rparts;  // (the Step 2 partials travel with the barrier here)
     __shared__ int32_t s_ok;
+    // the partials the barriers carry: Step 1 (value, column, slot) and Step 2
+    // (ratio, row, leaving column, in-list flag, pivot value, RHS entry)
+    __shared__ uint32_t xs_s[kMaxDecideWgsXch][4];
+    __shared__ uint32_t xs_r[kMaxDecideWgsXch][9];
     const int tid = threadIdx.x;
     const int G = gridDim.x, w = blockIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
     const int64_t W = (int64_t)n + m + 1;
-    uint32_t nbar = 0;
+    uint32_t nbar = 0;                             // barriers passed in this launch
+    const uint32_t flag = gsync->epoch + 1u;       // this launch's record flag
 
     const DevState s0 = *st;
     const int32_t t = w * BD + tid;
@@ -870,8 +933,12 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             ds = t;
         }
         block_argmin_dpp<BD>(dv, di, ds, sv_0, si_0, sl_0);
-        if (tid == 0) sparts[w] = SPart{dv, di, ds};
-        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
+        if (tid == 0) {
+            const uint32_t d[4] = {lo32(dv), hi32(dv), (uint32_t)di, (uint32_t)ds};
+            xch_publish<4>(gsync->xch[nbar][w], d, flag);
+        }
+        if (!xch_wait<4>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_s, &s_ok)) return;
+        ++nbar;
     }
     double frow[KM], rslot[KM];
     int32_t rk[KM];
@@ -892,8 +959,20 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         double v = __builtin_inf();
         int32_t q = kNoIndex, tq = -1;
         if (!budget) {
-            SPart a = lane < G ? sparts[lane] : SPart{__builtin_inf(), kNoIndex, -1};
-            const SPart b = lane + 64 < G ? sparts[lane + 64] : SPart{__builtin_inf(), kNoIndex, -1};
+            // the partials of the last barrier, or at a group's first pivot
+            // those the previous group's last staging left
+            const SPart none{__builtin_inf(), kNoIndex, -1};
+            SPart a = none, b = none;
+            if (j == 0 && !s0.fresh) {
+                if (lane < G) a = sparts[lane];
+                if (lane + 64 < G) b = sparts[lane + 64];
+            } else {
+                if (lane < G) a = SPart{as_f64(xs_s[lane][0], xs_s[lane][1]), (int32_t)xs_s[lane][2],
+                                        (int32_t)xs_s[lane][3]};
+                if (lane + 64 < G)
+                    b = SPart{as_f64(xs_s[lane + 64][0], xs_s[lane + 64][1]), (int32_t)xs_s[lane + 64][2],
+                              (int32_t)xs_s[lane + 64][3]};
+            }
             if (lex_less(b.v, b.i, a.v, a.i)) a = b;
             v = a.v;
             q = a.i;
@@ -912,7 +991,13 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         if (stop) {
             if (j == 0) {  // the close is stored once every workgroup has read the list
-                if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
+                __syncthreads();  // every wave has read the Step 1 partials (wave 0 rewrites them)
+                if (tid == 0) {
+                    const uint32_t d[4] = {0u, 0u, 0u, 0u};
+                    xch_publish<4>(gsync->xch[nbar][w], d, flag);
+                }
+                if (!xch_wait<4>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_s, &s_ok)) return;
+                ++nbar;
                 if (w == 0 && tid < 64) store_close();
             }
             break;
@@ -956,11 +1041,16 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // the workgroup's Step 2 partial, written by the thread that owns
         // row r (by thread 0 when no row qualifies); lpos carries "the
         // leaving column has a slot" here
-        if (r != kNoIndex && r_mine == r)
-            rparts[w] = GRatio{rv, r, rv != rv, a, basis_i, (int32_t)inlist_i, bb};
-        else if (r == kNoIndex && tid == 0)
-            rparts[w] = GRatio{rv, r, 0, 0.0, -1, 0, 0.0};
-        if (!grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
+        if (r != kNoIndex && r_mine == r) {
+            const uint32_t d[9] = {lo32(rv), hi32(rv), (uint32_t)r, (uint32_t)basis_i, (uint32_t)inlist_i,
+                                   lo32(a), hi32(a), lo32(bb), hi32(bb)};
+            xch_publish<9>(gsync->xch[nbar][w], d, flag);
+        } else if (r == kNoIndex && tid == 0) {
+            const uint32_t d[9] = {lo32(rv), hi32(rv), (uint32_t)kNoIndex, 0xffffffffu, 0u, 0u, 0u, 0u, 0u};
+            xch_publish<9>(gsync->xch[nbar][w], d, flag);
+        }
+        if (!xch_wait<9>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_r, &s_ok)) return;
+        ++nbar;
         if (j == 0 && w == 0) {  // every workgroup has read the list
             if (tid < 64) store_close();
             __syncthreads();  // before the decision record below
@@ -973,8 +1063,12 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         int32_t leave, inl;
         {
             const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0, 0.0};
-            GRatio pa = lane < G ? rparts[lane] : none;
-            const GRatio pb = lane + 64 < G ? rparts[lane + 64] : none;
+            auto rec = [&](int u) {
+                return GRatio{as_f64(xs_r[u][0], xs_r[u][1]), (int32_t)xs_r[u][2], 0, as_f64(xs_r[u][5], xs_r[u][6]),
+                              (int32_t)xs_r[u][3], (int32_t)xs_r[u][4], as_f64(xs_r[u][7], xs_r[u][8])};
+            };
+            GRatio pa = lane < G ? rec(lane) : none;
+            const GRatio pb = lane + 64 < G ? rec(lane + 64) : none;
             if (lex_less(pb.v, pb.r, pa.v, pa.r)) pa = pb;
             rv = pa.v;
             r = pa.r;
@@ -1065,8 +1159,17 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             ds = t;
         }
         block_argmin_dpp<BD>(dv, di, ds, sv_s, si_s, sl_s);
+        // (also stored plainly: the next group's first pricing reads them,
+        // whichever pivot of this group is the last)
         if (tid == 0) sparts[w] = SPart{dv, di, ds};
-        if (j + 1 < K && !grid_barrier(gsync, (uint32_t)G * ++nbar, spin_limit, st, gs, &s_ok)) return;
+        if (j + 1 < K) {
+            if (tid == 0) {
+                const uint32_t d[4] = {lo32(dv), hi32(dv), (uint32_t)di, (uint32_t)ds};
+                xch_publish<4>(gsync->xch[nbar][w], d, flag);
+            }
+            if (!xch_wait<4>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_s, &s_ok)) return;
+            ++nbar;
+        }
     }
 
     // The pivot rows after the group, for every slot: the row of pivot a
@@ -1137,13 +1240,14 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  uint32_t spin_limit, double *__restrict__ PV) {
     decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r,
                                log_q, rparts, gsync, spin_limit, PV);
-    // every workgroup leaves through here; the last one resets the barrier
+    // every workgroup leaves through here; the last one advances the epoch,
+    // so the next launch's records carry a new flag
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&gsync->exits, 1u) == (uint32_t)gridDim.x - 1) {
-            gsync->count = 0;
             gsync->exits = 0;
+            gsync->epoch = gsync->epoch + 1u;
             __threadfence();
         }
     }
