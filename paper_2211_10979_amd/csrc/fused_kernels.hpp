@@ -55,13 +55,21 @@ namespace lpgpu {
 
 constexpr int kMaxFuse = 32;       // pivots per group with the one-launch decision kernel
 constexpr int kMaxFuseSplit = 16;  // with the two launches per pivot (k_gselect, k_gstage)
+// How a launch of the one-launch decision kernel gave up (GroupState::stalled):
+// a grid-barrier wait after the check-in ran out of polls (the group's state
+// may be half written: the solve ends with LP_STALLED), or the check-in gate
+// closed before every workgroup was resident (the launch wrote nothing: the
+// host goes on with the barrier-free kernels).
+constexpr int32_t kStallBarrier = 1;
+constexpr int32_t kStallGate = 2;
 
 // Decisions of the current group, resident in device memory.
 struct GroupState {
     int32_t kdone;  // pivots decided in this group
     int32_t napp;   // leaving columns appended to the list (slots n+1 ..)
-    int32_t stalled;  // 1: a grid-barrier wait of the decision kernel gave up; the update
-                      // passes then apply nothing (the group's inputs are incomplete)
+    int32_t stalled;  // kStallBarrier or kStallGate: the decision kernel gave up on its
+                      // launch; the update passes then apply nothing (the group's inputs are
+                      // incomplete)
     int32_t pad_;
     int32_t r[kMaxFuse];
     int32_t q[kMaxFuse];
@@ -106,24 +114,24 @@ static __global__ void k_ginit(DevState *st, DevState init, GroupState *gs, int3
 // issued in one batch and the pairing is done in registers (fully unrolled
 // loops, no local arrays indexed at run time), so the close costs about two
 // memory round trips.
-static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, int32_t *__restrict__ pos,
-                                   int32_t n) {
+template <int N>
+__device__ void close_group_n(GroupState *gs, int32_t *__restrict__ cols, int32_t *__restrict__ pos, int32_t n) {
     const int kd = gs->kdone;
     if (kd == 0) return;
     const int na = gs->napp;
     // loads without per-entry conditions (every index is in bounds: the
-    // group record has kMaxFuseSplit entries, the list kMaxFuseSplit padding slots),
+    // group record and the list's padding slots have at least N entries),
     // then the entries past the group masked out, so that no load waits for
     // another
-    int32_t qk[kMaxFuseSplit], lk[kMaxFuseSplit], app[kMaxFuseSplit], pq[kMaxFuseSplit];
+    int32_t qk[N], lk[N], app[N], pq[N];
 #pragma unroll
-    for (int k = 0; k < kMaxFuseSplit; ++k) {
+    for (int k = 0; k < N; ++k) {
         qk[k] = gs->q[k];
         lk[k] = gs->l[k];
         app[k] = cols[n + 1 + k];
     }
 #pragma unroll
-    for (int k = 0; k < kMaxFuseSplit; ++k) {
+    for (int k = 0; k < N; ++k) {
         const bool in = k < kd && qk[k] >= 0;
         pq[k] = pos[in ? qk[k] : 0];
         if (!in) {
@@ -134,12 +142,12 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
         if (k >= na) app[k] = -1;
     }
     // the last event of the group decides: entered -> basic, left -> nonbasic
-    bool qb[kMaxFuseSplit], ab[kMaxFuseSplit];  // entered column k / appended column s basic at the end
+    bool qb[N], ab[N];  // entered column k / appended column s basic at the end
 #pragma unroll
-    for (int k = 0; k < kMaxFuseSplit; ++k) {
+    for (int k = 0; k < N; ++k) {
         bool bq = false, ba = false;
 #pragma unroll
-        for (int e = 0; e < kMaxFuseSplit; ++e) {
+        for (int e = 0; e < N; ++e) {
             if (qk[e] == qk[k]) bq = true;
             if (lk[e] == qk[k]) bq = false;
             if (qk[e] == app[k]) ba = true;
@@ -148,19 +156,19 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
         qb[k] = bq;
         ab[k] = ba;
     }
-    bool free_k[kMaxFuseSplit];  // entered column k still basic and holding a slot below n
+    bool free_k[N];  // entered column k still basic and holding a slot below n
 #pragma unroll
-    for (int k = 0; k < kMaxFuseSplit; ++k) {
+    for (int k = 0; k < N; ++k) {
         bool first = true;  // a column entered twice holds its slot once
 #pragma unroll
         for (int e = 0; e < k; ++e) first &= qk[e] != qk[k];
         free_k[k] = k < kd && first && pq[k] >= 0 && pq[k] < n && qb[k];
     }
 #pragma unroll
-    for (int k = 0; k < kMaxFuseSplit; ++k)
+    for (int k = 0; k < N; ++k)
         if (k < kd && qb[k] && pq[k] >= 0) pos[qk[k]] = -1;
 #pragma unroll
-    for (int s = 0; s < kMaxFuseSplit; ++s) {
+    for (int s = 0; s < N; ++s) {
         if (s < na) {
             const int32_t c = app[s];
             if (ab[s]) {
@@ -168,7 +176,7 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
             } else {
                 int32_t t = -1;
 #pragma unroll
-                for (int k = 0; k < kMaxFuseSplit; ++k)
+                for (int k = 0; k < N; ++k)
                     if (t < 0 && free_k[k]) {
                         t = pq[k];
                         free_k[k] = false;
@@ -183,6 +191,11 @@ static __device__ void close_group(GroupState *gs, int32_t *__restrict__ cols, i
     }
     gs->kdone = 0;
     gs->napp = 0;
+}
+// groups of the two-launch path (at most kMaxFuseSplit pivots)
+static __device__ __forceinline__ void close_group(GroupState *gs, int32_t *__restrict__ cols,
+                                                   int32_t *__restrict__ pos, int32_t n) {
+    close_group_n<kMaxFuseSplit>(gs, cols, pos, n);
 }
 
 // Step 1 partial of the staging kernel: the best (row-0 value, column) of a
@@ -671,12 +684,59 @@ constexpr int kXchWords = 16;  // words per record: one 128-byte line
 constexpr int kMaxDecideBarriers = 2 * kMaxFuse + 2;
 constexpr int kMaxDecideWgsXch = 128;  // records per barrier (the decision kernel's workgroup limit)
 struct GridSync {
-    uint32_t count;  // (unused by the data-carrying barrier)
+    uint32_t count;  // check-in gate: workgroups arrived, kGateClosed once closed
     uint32_t exits;  // workgroups that have left this launch
     uint32_t epoch;  // launches completed
     uint32_t pad_[29];
     uint64_t xch[kMaxDecideBarriers][kMaxDecideWgsXch][kXchWords];
 };
+
+// The check-in gate at the start of a launch: the barriers below wait for
+// all G workgroups, so they must all be resident at once, which nothing
+// guarantees when other work shares the device. Each workgroup adds one to
+// the gate and waits until it reads G. One that has polled spin_limit times
+// closes the gate with a compare-and-swap of the count it last read, which
+// fails if another workgroup arrived meanwhile (it then reads again): the
+// count reaches G or the gate closes, never both, so either every workgroup
+// passes or none does. Workgroups that find the gate closed leave at once;
+// nothing before the gate writes to memory, so a closed gate leaves the
+// solve as it was (the group is marked kStallGate and the status LP_STALLED,
+// from which the host resumes on the barrier-free kernels). The last
+// workgroup to leave the launch reopens the gate.
+constexpr uint32_t kGateClosed = 0x80000000u;
+
+__device__ __forceinline__ bool gate_pass(GridSync *gsync, int G, uint32_t spin_limit, DevState *st, GroupState *gs,
+                                          int32_t *s_ok) {
+    if (threadIdx.x == 0) {
+        uint32_t v = atomicAdd(&gsync->count, 1u) + 1u;
+        uint32_t it = 0;
+        bool ok = false;
+        for (;;) {
+            if (v & kGateClosed) break;
+            if (v == (uint32_t)G) {
+                ok = true;
+                break;
+            }
+            if (++it > spin_limit) {
+                const uint32_t old = atomicCAS(&gsync->count, v, v | kGateClosed);
+                if (old == v) break;  // closed
+                v = old;
+                continue;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            v = __hip_atomic_load(&gsync->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ok) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        } else {  // (every workgroup that finds the gate closed: the same marks)
+            atomicExch(&gs->stalled, kStallGate);
+            atomicCAS(&st->status, (int32_t)LP_RUNNING, (int32_t)LP_STALLED);
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
 
 // Publishes this workgroup's record for a barrier: one thread, after a
 // workgroup barrier that follows the workgroup's writes, so that the release
@@ -707,6 +767,9 @@ __device__ __forceinline__ bool xch_wait(const uint64_t (*recs)[kXchWords], int 
         uint32_t it = 0;
         bool ok = false;
         for (;;) {
+            // the status first, by every lane (one request): issued with the
+            // record loads, not after them
+            const int32_t stv = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             bool mine = true;
             if (lane < G) {
 #pragma unroll
@@ -722,8 +785,6 @@ __device__ __forceinline__ bool xch_wait(const uint64_t (*recs)[kXchWords], int 
                     mine &= (uint32_t)(b[k] >> 32) == flag;
                 }
             }
-            const int32_t stv =
-                lane == 0 ? __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
             const bool stalled = __builtin_amdgcn_readfirstlane(stv) == LP_STALLED;
             const bool all = __ballot(!mine) == 0;
             if (stalled) break;
@@ -734,7 +795,7 @@ __device__ __forceinline__ bool xch_wait(const uint64_t (*recs)[kXchWords], int 
             if (++it > spin_limit) {
                 if (lane == 0) {
                     atomicExch(&st->status, (int32_t)LP_STALLED);
-                    atomicExch(&gs->stalled, 1);
+                    atomicExch(&gs->stalled, kStallBarrier);
                 }
                 break;
             }
@@ -814,7 +875,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
                                             int32_t *__restrict__ basis, int32_t *__restrict__ log_r,
                                             int32_t *__restrict__ log_q, GRatio *__restrict__ rparts,
                                             GridSync *__restrict__ gsync, uint32_t spin_limit,
-                                            double *__restrict__ PV) {
+                                            uint32_t gate_spin, double *__restrict__ PV) {
     // one set of reduction slots per call site (ratio test, staging, start)
     __shared__ double sv_r[BD / 64], sv_s[BD / 64], sv_0[BD / 64];
     __shared__ int32_t si_r[BD / 64], si_s[BD / 64], si_0[BD / 64];
@@ -831,6 +892,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     const int64_t W = (int64_t)n + m + 1;
     uint32_t nbar = 0;                             // barriers passed in this launch
     const uint32_t flag = gsync->epoch + 1u;       // this launch's record flag
+    if (!gate_pass(gsync, G, gate_spin, st, gs, &s_ok)) return;
 
     const DevState s0 = *st;
     const int32_t t = w * BD + tid;
@@ -1237,20 +1299,40 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  int32_t *__restrict__ pos, int32_t *__restrict__ basis,
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
-                                                 uint32_t spin_limit, double *__restrict__ PV) {
+                                                 uint32_t spin_limit, uint32_t gate_spin, double *__restrict__ PV) {
     decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r,
-                               log_q, rparts, gsync, spin_limit, PV);
+                               log_q, rparts, gsync, spin_limit, gate_spin, PV);
     // every workgroup leaves through here; the last one advances the epoch,
-    // so the next launch's records carry a new flag
+    // so the next launch's records carry a new flag, and reopens the gate
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&gsync->exits, 1u) == (uint32_t)gridDim.x - 1) {
             gsync->exits = 0;
+            gsync->count = 0;  // the gate opens for the next launch
             gsync->epoch = gsync->epoch + 1u;
             __threadfence();
         }
     }
+}
+
+// Closes the gate of the next decision launch (kGateClosed): its workgroups
+// then find it closed, as they would when they could not all be resident
+// (a host-forced test of the fallback).
+static __global__ void k_gate_close(GridSync *gsync) { gsync->count = kGateClosed; }
+
+// Resumes a solve whose decision launch closed its gate (kStallGate; nothing
+// of that launch was written): the open group is closed (groups of up to
+// kMaxFuse pivots), the status returns to LP_RUNNING and the next Step 1
+// scans row 0 (the pure update pass leaves no partials for the barrier-free
+// kernels). One thread.
+static __global__ void k_grecover(DevState *st, GroupState *gs, int32_t *__restrict__ cols, int32_t *__restrict__ pos,
+                                  int32_t n) {
+    if (gs->stalled != kStallGate) return;
+    close_group_n<kMaxFuse>(gs, cols, pos, n);
+    gs->stalled = 0;
+    if (st->status == LP_STALLED) st->status = LP_RUNNING;
+    st->fresh = 1;
 }
 
 // Step 3 for the whole group in one pass over (row chunk, slot group) tiles:

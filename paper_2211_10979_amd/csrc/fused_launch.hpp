@@ -35,6 +35,7 @@ struct FusedArgs {
     int32_t decide_block;  // its threads per workgroup (256 or 512)
     GridSync *gsync;     // its barrier counters, zero between launches
     uint32_t decide_spin;
+    uint32_t gate_spin;  // polls before its check-in gate closes
     double *dump;       // a zero column the pure update pass writes for slots past the list
     double *PV;         // the group's pivot rows after the group, K rows of n + 1 + K doubles
 };

@@ -130,6 +130,8 @@ struct lp_ctx {
     int decide_wgs = 0;                       // K > 1: > 0 = one-launch decision kernel, its workgroups
     int decide_block = 256;                   // K > 1: its threads per workgroup
     uint32_t decide_spin = kDefaultDecideSpin;
+    bool force_gate_close = false;            // decide_spin -1: close the first decision launch's gate
+    int32_t stall_fallbacks = 0;              // decision launches whose gate closed (then barrier-free)
     int nsparts = 0;
     bool use_graph = true;
     bool timing = false;
@@ -224,7 +226,7 @@ int validate_opts(const Options &o) {
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
     if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 32]");
     if (o.decide_kernel < 0 || o.decide_kernel > 1) return set_error(LP_E_INVAL, "decide_kernel must be 0 or 1");
-    if (o.decide_spin < 0) return set_error(LP_E_INVAL, "decide_spin must be >= 0");
+    if (o.decide_spin < -1) return set_error(LP_E_INVAL, "decide_spin must be >= -1");
     if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
         return set_error(LP_E_INVAL, "decide_block must be 0 (auto), 256 or 512");
     if (o.eager_build < 0 || o.eager_build > 1) return set_error(LP_E_INVAL, "eager_build must be 0 or 1");
@@ -340,6 +342,7 @@ int configure_ctx(lp_ctx *h, int32_t m, int32_t n, const Options &o) {
         const int32_t g = decide_workgroups_for(m, h->Lg, h->decide_block);
         h->decide_wgs = one_launch(h->fuse) ? g : 0;
         h->decide_spin = o.decide_spin > 0 ? (uint32_t)o.decide_spin : kDefaultDecideSpin;
+        h->force_gate_close = o.decide_spin == -1 && h->decide_wgs > 0;
         const bool can_early = h->decide_wgs > 0 && h->chunk == 1;
         if (o.status_readback == 2 && !can_early)
             return set_error(LP_E_INVAL,
@@ -650,6 +653,7 @@ FusedArgs fused_args(lp_ctx *h) {
     a.decide_block = h->decide_block;
     a.gsync = h->gsync;
     a.decide_spin = h->decide_spin;
+    a.gate_spin = std::max(h->decide_spin, kDefaultDecideSpin);
     return a;
 }
 
@@ -859,13 +863,7 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
 // Runs pivots until the status leaves RUNNING or `stop_at` pivots are done.
 // Chunks are pipelined two deep: chunk k+1 is queued before the status of
 // chunk k is read back, so the device never waits for the host.
-int run_until(lp_ctx *h, int64_t stop_at) {
-    DeviceGuard g(h->device);
-    h->update_ms = 0.0;
-    h->update_launches = 0;
-    h->update_ms_applied = 0.0;
-    h->applied_launches = 0;
-    h->first_ms = 0.0;
+int run_until_once(lp_ctx *h, int64_t stop_at) {
     h->counters_cached = false;
     h->solution_cached = false;
     if (h->early_status) return run_until_early(h, stop_at);
@@ -919,6 +917,83 @@ int run_until(lp_ctx *h, int64_t stop_at) {
     return LP_OK;
 }
 
+// Closes the gate of the first decision launch when the options ask for it
+// (decide_spin -1, a host-forced test of the fallback below).
+void maybe_close_gate(lp_ctx *h) {
+    if (!h->force_gate_close || h->fuse <= 1 || h->decide_wgs <= 0) return;
+    hipLaunchKernelGGL(k_gate_close, dim3(1), dim3(1), 0, h->stream, h->gsync);
+    h->force_gate_close = false;
+}
+
+// The fallback after a decision launch whose check-in gate closed (its
+// workgroups were not all resident at once, e.g. while other streams held
+// the compute units): that launch wrote nothing and the update pass queued
+// after it applied nothing, so the tableau is the one after the last whole
+// group. The open group is closed, the basic columns a deferred build left
+// unstored are stored (the barrier-free kernels read every column they
+// select), and the solve goes on with two launches per pivot (no grid
+// barrier) in groups of at most kMaxFuseSplit pivots: the same pivots and
+// bits. *resumed is false (and the solve stays LP_STALLED) when the stall
+// came from a wait after the gate, or when no barrier-free kernels exist for
+// the context's update shape.
+int recover_stall(lp_ctx *h, bool *resumed) {
+    *resumed = false;
+    if (h->fuse <= 1 || h->decide_wgs <= 0 || h->status_host != LP_STALLED) return LP_OK;
+    int32_t how = 0;
+    LP_HIP_CHECK(hipMemcpy(&how, &h->gs->stalled, sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int K2 = std::min(h->fuse, kMaxFuseSplit);
+    const UpdateConfig &u = h->ucfg;
+    if (how != kStallGate || !fused_update_supported(u.block, u.cols, u.rv, K2, false)) return LP_OK;
+    if (h->lazy) {
+        const int64_t nb = (int64_t)h->m * (h->ld / 2);
+        hipLaunchKernelGGL(k_store_basic, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
+                           h->m, (const int32_t *)h->basis);
+        h->lazy = false;
+    }
+    hipLaunchKernelGGL(k_grecover, dim3(1), dim3(1), 0, h->stream, h->st, h->gs, h->cols, h->pos, h->n);
+    LP_HIP_CHECK(hipGetLastError());
+    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    h->decide_wgs = 0;
+    h->early_status = false;
+    h->fuse = K2;
+    h->Lg = (int64_t)h->n + 1 + K2;
+    h->nparts = (int)((h->Lg + h->ucfg.cols - 1) / h->ucfg.cols);
+    h->nsparts = (int)((h->Lg + 255) / 256);
+    for (int k = 0; k < 2; ++k) {
+        if (h->gexec[k]) (void)hipGraphExecDestroy(h->gexec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        h->gexec[k] = nullptr;
+        h->graph[k] = nullptr;
+    }
+    if (int rc = capture_graphs(h)) return rc;
+    h->status_host = LP_RUNNING;
+    if (h->host_st) h->host_st[2].status = LP_RUNNING;  // (the solve that allocates nothing has no pinned state)
+    h->stall_fallbacks += 1;
+    *resumed = true;
+    return LP_OK;
+}
+
+// run_until_once, resumed on the barrier-free kernels after a closed gate.
+int run_until(lp_ctx *h, int64_t stop_at) {
+    DeviceGuard g(h->device);
+    h->update_ms = 0.0;
+    h->update_launches = 0;
+    h->update_ms_applied = 0.0;
+    h->applied_launches = 0;
+    h->first_ms = 0.0;
+    maybe_close_gate(h);
+    double ms = 0.0;
+    for (;;) {
+        if (int rc = run_until_once(h, stop_at)) return rc;
+        ms += h->last_ms;
+        bool resumed = false;
+        if (int rc = recover_stall(h, &resumed)) return rc;
+        if (!resumed) break;
+    }
+    h->last_ms = ms;
+    return LP_OK;
+}
+
 bool all_finite(const double *p, int64_t k) {
     for (int64_t i = 0; i < k; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -959,6 +1034,7 @@ int noalloc_block(int device, unsigned char **out) {
 // so nothing is queued after the end; otherwise after each chunk.
 int run_noalloc(lp_ctx *h, DevState *fin) {
     DevState s{};
+    maybe_close_gate(h);
     for (;;) {
         if (h->fuse > 1 && h->decide_wgs > 0) {
             const FusedArgs a = fused_args(h);
@@ -984,6 +1060,12 @@ int run_noalloc(lp_ctx *h, DevState *fin) {
             if (int rc = enqueue_chunk(h, 0)) return rc;
             LP_HIP_CHECK(hipMemcpyAsync(&s, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
             LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+        }
+        if (s.status == LP_STALLED) {  // a closed gate: on with the barrier-free kernels
+            h->status_host = s.status;
+            bool resumed = false;
+            if (int rc = recover_stall(h, &resumed)) return rc;
+            if (resumed) continue;
         }
         if (s.status != LP_RUNNING) break;
     }

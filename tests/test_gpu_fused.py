@@ -296,6 +296,89 @@ def test_decision_kernel_gives_up_instead_of_hanging():
     solve_and_compare(A, b, c, fuse_pivots=12)
 
 
+def check_against_oracle(h, o, lp):
+    res, x, y = lpgpu.lp_get_solution(h)
+    rows, cols = lpgpu.lp_get_pivots(h)
+    orow, ocol = o.log()
+    assert res["status"] == o.status and res["pivots"] == o.pivots
+    assert rows.tolist() == orow.tolist() and cols.tolist() == ocol.tolist()
+    assert np.array_equal(lpgpu.lp_get_tableau(h), o.tableau())
+    assert lpgpu.lp_get_basis(h).tolist() == o.basis().tolist()
+    ox, oy, _ = o.extract()
+    assert np.array_equal(x, ox) and np.array_equal(y, oy)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(fuse_pivots=12), dict(fuse_pivots=32), dict(plain_launches=1),
+                                  dict(time_kernels=1), dict(status_readback=2)])
+def test_closed_gate_resumes_without_barriers(opts):
+    """decide_spin -1 closes the check-in gate of the first one-launch
+    decision, as when its workgroups cannot all be resident: that launch
+    writes nothing and the solve goes on with the barrier-free decision
+    kernels (groups of at most 16 pivots), with the oracle's pivots, tableau,
+    basis and solution."""
+    lp = lpgen.workload("dense_2000x2000")
+    say(f"fused: closed gate, fallback {opts}")
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    o.step(-1)
+    h = lpgpu.lp_create(lp.A, lp.b, lp.c, decide_spin=-1, **opts)
+    try:
+        info = lpgpu.lp_get_info(h)
+        K = info.update_fuse
+        assert info.decide_workgroups > 0
+        lpgpu.lp_solve(h)
+        check_against_oracle(h, o, lp)
+        info = lpgpu.lp_get_info(h)
+        assert info.decide_workgroups == 0 and info.update_fuse == min(K, 16)
+    finally:
+        lpgpu.lp_destroy(h)
+        o.close()
+
+
+def test_closed_gate_on_a_deferred_build_and_stepping():
+    """The gate of the first group after a deferred build closes: that
+    group's pass builds the structural columns alone, the unstored slack
+    columns are stored, and lp_step goes on barrier-free; the tableau matches
+    the oracle's after every step."""
+    import torch
+
+    lp = lpgen.workload("dense_200x200")
+    say("fused: closed gate on a deferred build, stepping")
+    dev = torch.device("cuda", 0)
+    dA, db, dc = (torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (lp.A, lp.b, lp.c))
+    h = lpgpu.lp_create_device(lp.m, lp.n, dA, db, dc, decide_spin=-1)
+    o = oracle.OracleLP(lp.A, lp.b, lp.c)
+    try:
+        lpgpu.lp_reload_device(h, dA, db, dc)
+        while True:
+            lpgpu.lp_step(h, 7)
+            st = o.step(7)
+            res, _, _ = lpgpu.lp_get_solution(h)
+            assert res["pivots"] == o.pivots
+            assert np.array_equal(lpgpu.lp_get_tableau(h), o.tableau()), f"after pivot {o.pivots}"
+            if st != oracle.RUNNING:
+                break
+        check_against_oracle(h, o, lp)
+        assert lpgpu.lp_get_info(h).decide_workgroups == 0
+    finally:
+        lpgpu.lp_destroy(h)
+        o.close()
+
+
+def test_closed_gate_in_the_solve_that_allocates_nothing():
+    import torch
+
+    lp = lpgen.workload("dense_2000x2000")
+    say("fused: closed gate in lp_solve_noalloc")
+    dev = torch.device("cuda", 0)
+    dA, db, dc = (torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (lp.A, lp.b, lp.c))
+    buf = torch.empty(lpgpu.lp_tableau_bytes(lp.m, lp.n) // 8, dtype=torch.float64, device=dev)
+    o = oracle.solve(lp.A, lp.b, lp.c)
+    res, x, y, rows, cols, count = lpgpu.lp_solve_noalloc(lp.m, lp.n, dA, db, dc, buf, decide_spin=-1)
+    assert res["status"] == o["status"] and count == o["pivots"]
+    assert rows.tolist() == o["rows"].tolist() and cols.tolist() == o["cols"].tolist()
+    assert np.array_equal(x, o["x"]) and np.array_equal(y, o["y"])
+
+
 @pytest.mark.parametrize("block", [256, 512])
 def test_decision_kernel_block_sizes(block):
     """The decision kernel's workgroup size changes no result."""
