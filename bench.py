@@ -331,6 +331,42 @@ class Prefetch:
         self.pool.shutdown(wait=True)
 
 
+def bench_hybrid(args, lpgpu, lpgen):
+    """The paper's CPU + GPU column split (Section IV; Tables VI-VII sweep the
+    GPU's share theta) on the timed workload: one solve per theta after a
+    warm-up, with the one-pivot single-GPU solve (the hybrid's GPU side runs
+    the same update kernel) and theta = 1 as references."""
+    lp = lpgen.workload(args.workload)
+    m, n = lp.m, lp.n
+    threads = host_workers()
+    thetas = [float(t) for t in args.hybrid_thetas.split(",") if t]
+    one = lpgpu.solve(lp.A, lp.b, lp.c, fuse_pivots=1)
+    out = dict(workload=args.workload, host_threads=threads, one_pivot_single_gpu=dict(
+        pivots_per_s=round(one["pivots"] / (one["solve_ms"] * 1e-3), 1), solve_ms=round(one["solve_ms"], 3)),
+        sweep=[])
+    for k, theta in enumerate([thetas[0]] + thetas):
+        h = lpgpu.lp_hybrid_create(lp.A, lp.b, lp.c, theta, threads)
+        try:
+            lpgpu.lp_hybrid_solve(h)
+            res, _, _ = lpgpu.lp_hybrid_get_solution(h, m, n)
+            rows, cols = lpgpu.lp_hybrid_get_pivots(h)
+            info = lpgpu.lp_hybrid_info(h)
+        finally:
+            lpgpu.lp_hybrid_destroy(h)
+        if k == 0:
+            continue  # warm-up
+        same = rows.tolist() == one["rows"].tolist() and cols.tolist() == one["cols"].tolist()
+        piv = max(res["pivots"], 1)
+        out["sweep"].append(dict(theta=theta, pivots_per_s=round(res["pivots"] / (res["solve_ms"] * 1e-3), 1),
+                                 solve_ms=round(res["solve_ms"], 3), host_columns=info["host_columns"],
+                                 host_ms_per_pivot=round(info["host_ms"] / piv, 4),
+                                 status=lpgpu.STATUS_NAMES[res["status"]], same_pivots=same))
+        log(f"hybrid theta {theta}: {out['sweep'][-1]}")
+    best = max(out["sweep"], key=lambda r: r["pivots_per_s"])
+    out["best_theta"] = best["theta"]
+    return out
+
+
 def host_workers():
     """Worker threads for host-side generation: the CPU share of the box (at
     most 16), whatever the affinity mask shows."""
@@ -675,6 +711,9 @@ def main():
     ap.add_argument("--serve-tight-gb", type=float, default=0.5,
                     help="budget of a second saturated leg in which the budget binds")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--hybrid-thetas", default="1.0,0.99,0.98,0.97,0.96,0.95,0.9",
+                    help="GPU shares of the CPU + GPU split to time")
+    ap.add_argument("--no-hybrid", action="store_true")
     ap.add_argument("--small-steps", type=int, default=20, help="timed steps of the 200 x 200 and 2000 x 2000 legs")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--cpu-leg", default=None, choices=("omp", "lp"), help=argparse.SUPPRESS)
@@ -754,6 +793,9 @@ def main():
         line["batched"] = bench_batch(args, lpgpu, lpgen, torch)
     if not args.no_serve:
         line["serving"] = bench_serve(args, lpgpu, lpgen)
+    if not args.no_hybrid:
+        log(f"hybrid: {args.workload}, theta {args.hybrid_thetas}")
+        line["hybrid"] = bench_hybrid(args, lpgpu, lpgen)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle")
         line["cpu_baseline"] = cpu_baseline(args, gpu_log)

@@ -51,8 +51,14 @@ enum {
     LP_ITER_LIMIT = 2, /* max_pivots pivots done, another one needed */
     LP_NUMERICAL = 3,  /* Step 1 or Step 2 met a non-finite value (see the contract above) */
     LP_RUNNING = 4,    /* not finished (lp_step budget ran out, or not solved yet) */
-    LP_STALLED = 5,    /* a wait of the one-launch decision kernel timed out (its workgroups
-                          were not all resident); the solve was abandoned */
+    LP_STALLED = 5,    /* a grid-barrier wait of the one-launch decision kernel timed out
+                          after all its workgroups had checked in (only with a decide_spin far
+                          below the default); the solve was abandoned. A launch whose
+                          workgroups cannot all be resident at once (other work holding the
+                          compute units) closes its check-in gate instead, writes nothing,
+                          and the solve goes on with the barrier-free decision kernels (two
+                          launches per pivot, groups of at most 16 pivots): no status, the
+                          same pivots and bits; lp_get_info then reports decide_workgroups 0 */
     LP_INFEASIBLE = 6  /* general form: Phase I ended with artificial variables above zero */
 };
 
@@ -75,6 +81,7 @@ enum {
 typedef struct lp_ctx lp_ctx;
 typedef struct lp_batch lp_batch;
 typedef struct lp_server lp_server;
+typedef struct lp_hybrid lp_hybrid;
 
 /*
  * Execution and kernel-shape choices. None of them changes a result: every
@@ -121,7 +128,10 @@ typedef struct {
                                128 workgroups, else two launches per pivot); 1 = two launches
                                per pivot */
     int32_t decide_spin;    /* polls before a grid-barrier wait of the decision kernel gives up
-                               with LP_STALLED (0 = default, about 0.2 s) */
+                               with LP_STALLED (0 = default, about 0.2 s); its check-in gate
+                               waits at least the default. -1: the first decision launch finds
+                               its gate closed, as when its workgroups cannot all be resident
+                               (a test of the barrier-free fallback) */
     int32_t decide_block;   /* threads per workgroup of the decision kernel (256 or 512; 0 = auto:
                                256); 512 holds groups of at most 16 pivots */
     int32_t eager_build;    /* 0 = auto: with the one-launch decision kernel, lp_reload_device
@@ -439,6 +449,65 @@ int lp_batch_get_shape(const lp_batch *bt, int32_t *block, int32_t *unroll, int3
 int lp_batch_autotune(lp_batch *bt, const char *cache_path, int32_t trials, double *best_ms);
 
 void lp_batch_destroy(lp_batch *bt);
+
+/* ------------------------------------------------------------------ hybrid
+ * The paper's CPU + GPU split of the tableau's columns (Section IV, Setup,
+ * Initialization and Steps 1-4; Tables VI-VIII sweep the share), on one GPU
+ * and the host's cores: the GPU keeps the first round(theta n) of the n
+ * structural columns and the first round(theta m) of the m slack columns
+ * (halves round up), the host the others, so that each side starts with its
+ * share of the nonbasic columns; both keep a copy of the right-hand side.
+ * Each side rewrites only its nonbasic columns, the leaving column and its
+ * right-hand side, as lp_solve does.
+ * Each pivot combines the two sides' Step 1 minima, runs Step 2 on the side
+ * that owns the entering column, sends its pivot column to the other side
+ * over PCIe, then both sides update their own columns at the same time (the
+ * host on host_threads threads). The pivots, x, y and objective are those of
+ * lp_create + lp_solve with fuse_pivots = 1 (the same roundings, Dantzig's
+ * rule and tie-breaks).
+ */
+
+/*
+ * A, b, c: host inputs as lp_create (standard form, b >= 0), copied.
+ * theta: the GPU's share of the columns, in [0, 1] (1: every column on the
+ *   GPU, 0: only the right-hand side's copy there).
+ * host_threads: threads updating the host's share (<= 0: the host's
+ *   hardware threads, at most 16); they spin between pivots while a solve
+ *   runs and exit when it ends.
+ * opt: eps_dual, eps_pivot, max_pivots, record_pivots and device are used;
+ *   bland_after must be 0; the rest is ignored (the GPU share is updated by
+ *   the one-pivot update kernel on a stream of the handle's own).
+ * Errors as lp_create (LP_E_INVAL also for theta outside [0, 1]).
+ */
+int lp_hybrid_create(lp_hybrid **out, int32_t m, int32_t n, const double *A, const double *b, const double *c,
+                     double theta, int32_t host_threads, const lp_options *opt);
+
+/* Runs Steps 1-3 to the end (a second call does nothing). Blocks. */
+int lp_hybrid_solve(lp_hybrid *h);
+
+/* As lp_get_solution; LP_E_STATE before a solve. */
+int lp_hybrid_get_solution(const lp_hybrid *h, lp_result *res, double *x, double *y);
+
+/* As lp_get_pivots (entries beyond the log's capacity are not kept). */
+int lp_hybrid_get_pivots(const lp_hybrid *h, int32_t *rows, int32_t *cols, int64_t cap, int64_t *count);
+
+/*
+ * The tableau into the host array out, column-major, (m+1) rows by n+m+1
+ * columns (the RHS last): columns [0, J) and the RHS from the GPU's copy, the
+ * rest from the host's. Any time after create.
+ */
+int lp_hybrid_get_tableau(const lp_hybrid *h, double *out);
+
+/*
+ * The split (device_columns and host_columns, summing to n+m), the host thread count
+ * and the host's time in its Step 3 share summed over the solve (ms, after a
+ * solve). Each pointer may be NULL.
+ */
+int lp_hybrid_info(const lp_hybrid *h, int32_t *device_columns, int32_t *host_columns, int32_t *host_threads,
+                   double *host_ms);
+
+/* Frees the handle. NULL-safe. */
+void lp_hybrid_destroy(lp_hybrid *h);
 
 /* ------------------------------------------------------------------ serving
  * A request loop that keeps each admitted LP's tableau resident in device

@@ -191,6 +191,14 @@ SIGNATURES = {
     "lp_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(lp_server_stats_t)]),
     "lp_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lp_server_stats_t)]),
     "lp_server_destroy": (None, [_P]),
+    "lp_hybrid_create": (ctypes.c_int, [_PP, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, ctypes.c_double,
+                                        ctypes.c_int32, _OPT]),
+    "lp_hybrid_solve": (ctypes.c_int, [_P]),
+    "lp_hybrid_get_solution": (ctypes.c_int, [_P, _RES, _D, _D]),
+    "lp_hybrid_get_pivots": (ctypes.c_int, [_P, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_int64)]),
+    "lp_hybrid_get_tableau": (ctypes.c_int, [_P, _D]),
+    "lp_hybrid_info": (ctypes.c_int, [_P, _I32, _I32, _I32, _D]),
+    "lp_hybrid_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -568,6 +576,64 @@ def lp_server_destroy(h):
         library().lp_server_destroy(h)
 
 
+# ------------------------------------------------------------------ hybrid
+
+
+def lp_hybrid_create(A, b, c, theta, host_threads=0, options: lp_options | None = None, **kw):
+    """CPU + GPU column split: the GPU holds a share `theta` of the n+m
+    columns, the host the rest (updated on `host_threads` threads)."""
+    A, b, c = _f64(A), _f64(b), _f64(c)
+    m, n = A.shape
+    o = _opts(options, kw)
+    h = ctypes.c_void_p()
+    _check(library().lp_hybrid_create(ctypes.byref(h), m, n, _dp(A), _dp(b), _dp(c), float(theta), int(host_threads),
+                                      ctypes.byref(o)), "lp_hybrid_create")
+    return h
+
+
+def lp_hybrid_solve(h):
+    return _check(library().lp_hybrid_solve(h), "lp_hybrid_solve")
+
+
+def lp_hybrid_info(h) -> dict:
+    dc, hc, ht = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(library().lp_hybrid_info(h, ctypes.byref(dc), ctypes.byref(hc), ctypes.byref(ht), ctypes.byref(ms)),
+           "lp_hybrid_info")
+    return dict(device_columns=dc.value, host_columns=hc.value, host_threads=ht.value, host_ms=ms.value)
+
+
+def lp_hybrid_get_solution(h, m, n):
+    """Returns (result dict, x, y) of a solved hybrid handle."""
+    x = np.empty(n, dtype=np.float64)
+    y = np.empty(m, dtype=np.float64)
+    res = lp_result()
+    _check(library().lp_hybrid_get_solution(h, ctypes.byref(res), _dp(x), _dp(y)), "lp_hybrid_get_solution")
+    return _res_dict(res), x, y
+
+
+def lp_hybrid_get_pivots(h, cap=None):
+    count = ctypes.c_int64()
+    _check(library().lp_hybrid_get_pivots(h, None, None, 0, ctypes.byref(count)), "lp_hybrid_get_pivots")
+    k = count.value if cap is None else min(cap, count.value)
+    rows = np.empty(max(k, 1), dtype=np.int32)
+    cols = np.empty(max(k, 1), dtype=np.int32)
+    _check(library().lp_hybrid_get_pivots(h, _ip(rows), _ip(cols), k, ctypes.byref(count)), "lp_hybrid_get_pivots")
+    return rows[:k].copy(), cols[:k].copy()
+
+
+def lp_hybrid_get_tableau(h, m, n):
+    """The tableau as a row-major (m+1) x (n+m+1) array (a transposed view)."""
+    out = np.empty((n + m + 1, m + 1), dtype=np.float64)
+    _check(library().lp_hybrid_get_tableau(h, _dp(out)), "lp_hybrid_get_tableau")
+    return out.T
+
+
+def lp_hybrid_destroy(h):
+    if h:
+        library().lp_hybrid_destroy(h)
+
+
 # ------------------------------------------------------------------ convenience
 
 
@@ -583,6 +649,20 @@ def solve(A, b, c, **kw):
         return res
     finally:
         lp_destroy(h)
+
+
+def solve_hybrid(A, b, c, theta, host_threads=0, **kw):
+    """One LP on the CPU + GPU split: as solve, plus the split's info."""
+    m, n = np.shape(A)
+    h = lp_hybrid_create(A, b, c, theta, host_threads, **kw)
+    try:
+        lp_hybrid_solve(h)
+        res, x, y = lp_hybrid_get_solution(h, m, n)
+        rows, cols = lp_hybrid_get_pivots(h)
+        res.update(x=x, y=y, rows=rows, cols=cols, **lp_hybrid_info(h))
+        return res
+    finally:
+        lp_hybrid_destroy(h)
 
 
 def solve_general(A, b, c, sense, **kw):
