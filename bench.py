@@ -159,10 +159,13 @@ def bench_plain(args, lpgpu, lpgen, torch):
         info = lpgpu.lp_get_info(h)
         fuse = info.update_fuse
         readback = info.status_readback
-        if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24 or 32 pivots
-            kf = next(k for k in (2, 4, 8, 12, 16, 24, 32) if k >= fuse)
-            name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"
-            kernel = f"{name}<{info.update_block}, {info.update_cols}, {kf}>"
+        if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24, 32 or 48 pivots
+            kf = next(k for k in (2, 4, 8, 12, 16, 24, 32, 48) if k >= fuse)
+            if info.decide_workgroups > 0 and kf >= 48:  # row-lane tiles
+                kernel = f"k_gpure_rl<{kf}>"
+            else:
+                name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"
+                kernel = f"{name}<{info.update_block}, {info.update_cols}, {kf}>""
         else:
             kernel = (f"k_update<{info.update_block}, {info.update_cols}, {info.update_rows}, "
                       f"{info.update_hints & 1}, {info.update_hints >> 1}>")
@@ -217,7 +220,7 @@ def bench_plain(args, lpgpu, lpgen, torch):
                                pivots=upd_piv, alg_bytes_per_pivot=alg / max(upd_piv, 1),
                                columns_per_pivot=upd_cols / max(upd_piv, 1))
     if first_launches:
-        out["first_pass"] = dict(kernel=f"k_gfirst<{kf}>", launches=first_launches,
+        out["first_pass"] = dict(kernel=f"k_gfirst_rl<{kf}>" if kf >= 32 else f"k_gfirst<{kf}>", launches=first_launches,
                                  avg_launch_us=round(first_ms / first_launches * 1e3, 2),
                                  alg_bytes_per_launch=first_alg / first_launches,
                                  achieved_gbs=round(first_alg / max(first_ms, 1e-9) / 1e6, 1),

@@ -109,7 +109,7 @@ typedef struct {
                                compute unit (block 64..512), one column per tile (default 0) */
     int32_t update_unroll;  /* grid-stride update kernel: tiles in flight per thread (1, 2, 4, 8) */
     int32_t select_workgroups; /* Steps 1-2 kernel: workgroups (1..64; 0 = 1) */
-    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..32; 0 = auto: 24, or 16
+    int32_t fuse_pivots;    /* pivots applied per pass over the tableau (1..48; 0 = auto: 24, or 16
                                where 24 has no kernels (two launches per pivot, cols_per_block
                                1 or 2), unless an option above asks for a form only K = 1 has). With K > 1 the
                                solver decides K pivots one after the other, each from row 0,

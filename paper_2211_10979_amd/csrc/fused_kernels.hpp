@@ -53,7 +53,7 @@
 
 namespace lpgpu {
 
-constexpr int kMaxFuse = 32;       // pivots per group with the one-launch decision kernel
+constexpr int kMaxFuse = 48;       // pivots per group with the one-launch decision kernel
 constexpr int kMaxFuseSplit = 16;  // with the two launches per pivot (k_gselect, k_gstage)
 // How a launch of the one-launch decision kernel gave up (GroupState::stalled):
 // a grid-barrier wait after the check-in ran out of polls (the group's state
@@ -832,24 +832,35 @@ __device__ __forceinline__ void finish_status(DevState *st, int32_t status) {
 // Steps k < j of a chain (rows: x <- R_k if the row is r_k, else
 // fma(-F_k, R_k, x)), unrolled over the first N of the KM entries (N >= j;
 // the steps k >= j are masked out). Tiers of N keep the work near j.
-template <int N, int KM>
-__device__ __forceinline__ double chain_steps(double x, int j, int32_t row, const int32_t (&rk)[KM],
-                                              const double (&F)[KM], const double (&R)[KM]) {
+// The chain of the group's pivots 0 .. j-1 on one entry (row `row`): at each
+// pivot k, the entry becomes R_k if `row` is the pivot row r_k, else
+// fma(-F_k, R_k, entry). One factor is the entry's own (per thread, in
+// registers: OWN_F selects which), the other and the pivot rows are the same
+// for every thread and live one per lane of the wave (lane k holds pivot k's,
+// read with readlane), so that no register array grows with the group size
+// beyond the thread's own history.
+template <int N, int KM, bool OWN_F>
+__device__ __forceinline__ double chain_steps(double x, int j, int32_t row, int32_t rk_l, const double (&own)[KM],
+                                              double sh_l) {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const double nx = (row == rk[k]) ? R[k] : fma(-F[k], R[k], x);
+        const int32_t rk = __builtin_amdgcn_readlane(rk_l, k);
+        const double sh = readlane_f64(sh_l, k);
+        const double F = OWN_F ? own[k] : sh, R = OWN_F ? sh : own[k];
+        const double nx = (row == rk) ? R : fma(-F, R, x);
         x = k < j ? nx : x;
     }
     return x;
 }
 
-template <int KM>
-__device__ __forceinline__ double chain_tiered(double x, int j, int32_t row, const int32_t (&rk)[KM],
-                                               const double (&F)[KM], const double (&R)[KM]) {
-    constexpr int N1 = KM < 8 ? KM : 8, N2 = KM < 16 ? KM : 16;
-    if (j <= N1) return chain_steps<N1, KM>(x, j, row, rk, F, R);
-    if (j <= N2) return chain_steps<N2, KM>(x, j, row, rk, F, R);
-    return chain_steps<KM, KM>(x, j, row, rk, F, R);
+template <int KM, bool OWN_F>
+__device__ __forceinline__ double chain_tiered(double x, int j, int32_t row, int32_t rk_l, const double (&own)[KM],
+                                               double sh_l) {
+    constexpr int N1 = KM < 8 ? KM : 8, N2 = KM < 16 ? KM : 16, N3 = KM < 32 ? KM : 32;
+    if (j <= N1) return chain_steps<N1, KM, OWN_F>(x, j, row, rk_l, own, sh_l);
+    if (j <= N2) return chain_steps<N2, KM, OWN_F>(x, j, row, rk_l, own, sh_l);
+    if (j <= N3) return chain_steps<N3, KM, OWN_F>(x, j, row, rk_l, own, sh_l);
+    return chain_steps<KM, KM, OWN_F>(x, j, row, rk_l, own, sh_l);
 }
 
 // Entry (row, col) of the tableau at the start of the group. The first group
@@ -1003,12 +1014,11 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         ++nbar;
     }
     double frow[KM], rslot[KM];
-    int32_t rk[KM];
+    int32_t rk_l = -1;  // lane k: the pivot row of pivot k
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         frow[k] = 0.0;
         rslot[k] = 0.0;
-        rk[k] = -1;
     }
     int32_t napp = 0;
     int kd = 0;  // pivots decided in this group
@@ -1067,15 +1077,14 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
 
         // Step 2 on this thread's row of column q and the RHS after the j
         // earlier pivots; the row's entry of column q is kept as F_j[i]. The
-        // coefficients of all KM steps are loaded in one batch (index
-        // clamped into the buffer) and the steps k >= j are masked out by
-        // selects, so that no load waits behind another. The RHS entry is
-        // carried from pivot to pivot (bcur) with the same operations.
+        // R entries of slot tq are loaded one per lane (lane k: R_k, index
+        // clamped into the buffer), in the same batch as the entry, and the
+        // steps k >= j are masked out by selects. The RHS entry is carried
+        // from pivot to pivot (bcur) with the same operations.
         const int32_t tqs = tq < 0 ? 0 : tq;
-        double Rq[KM];
-#pragma unroll
-        for (int k = 0; k < KM; ++k) Rq[k] = Rk[(int64_t)(k < K ? k : K - 1) * Lg + tqs];
-        const double a = chain_tiered<KM>(start_entry<First>(T, ld, n, A, cv, q, is), j, i, rk, frow, Rq);
+        const double rq_l = Rk[(int64_t)(lane < K ? lane : K - 1) * Lg + tqs];
+        const double a =
+            chain_tiered<KM, true>(start_entry<First>(T, ld, n, A, cv, q, is), j, i, rk_l, frow, rq_l);
         const double bb = bcur;
 #pragma unroll
         for (int k = 0; k < KM; ++k)
@@ -1176,9 +1185,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             const double Rn = rb / p;
             bcur = (i == r) ? Rn : fma(-a, Rn, bcur);
         }
-#pragma unroll
-        for (int k = 0; k < KM; ++k)
-            if (k == j) rk[k] = r;
+        if (lane == j) rk_l = r;
         if (i == r) {
             basis_i = q;
             inlist_i = true;
@@ -1196,18 +1203,21 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // j earlier pivots, R_j[t] = that / p, and the row-0 entry after
         // pivot j (R = 0 for a slot not filled yet: its column is a unit
         // vector that no pivot of the group has changed)
-        double Fr[KM];  // F_k[r], one batch as above
-#pragma unroll
-        for (int k = 0; k < KM; ++k) Fr[k] = Fk[(int64_t)(k < K ? k : K - 1) * ld + r];
+        const double fr_l = Fk[(int64_t)(lane < K ? lane : K - 1) * ld + r];  // lane k: F_k[r]
         const double F0 = Fk[(int64_t)j * ld];
         double R = 0.0;
-        if (c_t >= 0) {
+        {
             // (the slot just appended holds e_r, whose entry in row r is 1:
-            // taken as is, since the store above may not be visible yet)
-            const double y0 = t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r);
-            const double y = chain_tiered<KM>(y0, j, r, rk, Fr, rslot);
-            R = y / p;
-            D_t = fma(-F0, R, D_t);
+            // taken as is, since the store above may not be visible yet).
+            // The chain runs with every lane active: it reads the shared
+            // factors from lanes 0 .. j-1, which must hold them
+            const bool live = c_t >= 0;
+            const double y0 = !live ? 0.0 : (t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r));
+            const double y = chain_tiered<KM, false>(y0, j, r, rk_l, rslot, fr_l);
+            if (live) {
+                R = y / p;
+                D_t = fma(-F0, R, D_t);
+            }
         }
 #pragma unroll
         for (int k = 0; k < KM; ++k)
@@ -1244,7 +1254,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         // thread b < kd loads F_b at the earlier pivot rows (one batch)
 #pragma unroll
         for (int a = 0; a < KM; ++a)
-            if (tid > a && tid < kd) sM[tid][a] = Fk[(int64_t)tid * ld + rk[a]];
+            if (tid > a && tid < kd) sM[tid][a] = Fk[(int64_t)tid * ld + __builtin_amdgcn_readlane(rk_l, a)];
         __syncthreads();
         if (has_slot) {
             // every earlier pivot row updated by pivot b, b in order: for each
@@ -1258,7 +1268,9 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
                 if (b < kd) {
 #pragma unroll
                     for (int a = 0; a < b; ++a)
-                        pv[a] = (rk[a] == rk[b]) ? rslot[b] : fma(-sM[b][a], rslot[b], pv[a]);
+                        pv[a] = (__builtin_amdgcn_readlane(rk_l, a) == __builtin_amdgcn_readlane(rk_l, b))
+                                    ? rslot[b]
+                                    : fma(-sM[b][a], rslot[b], pv[a]);
                 }
             }
 #pragma unroll
@@ -1681,6 +1693,153 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
             }
             if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
         }
+    }
+}
+
+// Row-lane tiles of the update pass (the form for groups of kRlFromKF
+// pivots and more): a workgroup of 256 threads takes 128 rows by 64 list
+// slots, wave w the slots 16w .. 16w+15 and lane l the row pair i0 + 2l,
+// i0 + 2l + 1, so each load or store of a slot's column covers 128
+// consecutive rows (1 KB, 16 bytes per lane) and each thread keeps 2 x 16
+// entries. Per pivot k it reads F_k of its two rows (one 16-byte LDS read)
+// and R_k of its 16 slots (scalar loads: the addresses are the same across the
+// wave) for 32 fmas, so F and R stay out of the registers and the register
+// count does not grow with KF. Rows past m are not stored (they hold zeros
+// that no pivot changes). The chain runs without the pivot-row select
+// (k_gfix stores the pivot rows): the same operations in the same order as
+// pure_tile and k_gfirst.
+constexpr int kRlRows = 128;  // rows per tile: a row pair per lane
+constexpr int kRlSlots = 64;  // slots per tile: 16 per wave
+constexpr int kRlPer = 16;    // slots per thread
+constexpr int kRlFromKF = 32;  // groups of this many pivots and more take the row-lane tiles
+
+template <int KF>
+__device__ __forceinline__ void rl_stage(double2 (*sF)[kRlRows / 2], const double *__restrict__ Fk, int64_t ld,
+                                         int64_t i0) {
+    const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
+    const int64_t ldv = ld / 2;  // (ld and i0 are even)
+    for (int t = threadIdx.x; t < KF * (kRlRows / 2); t += 256) {
+        const int k = t / (kRlRows / 2), v = t % (kRlRows / 2);
+        const int64_t i = i0 + 2 * v;
+        sF[k][v] = i < ld ? F2[(int64_t)k * ldv + i / 2] : double2{0.0, 0.0};
+    }
+}
+
+// The chain over the wave's 16 slots for the lane's row pair: R_k of those
+// slots through scalar loads (Rw points at R_0 of the wave's first slot;
+// slots past the list read entries that are never stored), F_k from LDS.
+template <int KF>
+__device__ __forceinline__ void rl_chain(double2 (&x)[kRlPer], const double2 (*sF)[kRlRows / 2], const double *Rw,
+                                         int64_t Lg, int lane) {
+#pragma unroll 2
+    for (int k = 0; k < KF; ++k) {
+        const double2 f = sF[k][lane];
+        const double *Rr = Rw + (int64_t)k * Lg;
+#pragma unroll
+        for (int u = 0; u < kRlPer; ++u) {
+            const double R = Rr[u];
+            x[u].x = fma(-f.x, R, x[u].x);
+            x[u].y = fma(-f.y, R, x[u].y);
+        }
+    }
+}
+
+// The pure pass in row-lane tiles over slots slot0 .. n+napp.
+template <int KF>
+__global__ __launch_bounds__(256) void k_gpure_rl(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                  int64_t Lg, int32_t nrt, const int32_t *__restrict__ cols,
+                                                  const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                                  const GroupState *__restrict__ gs, int32_t slot0) {
+    if (gs->kdone == 0 || gs->stalled) return;
+    const int32_t Lv = n + 1 + gs->napp;
+    const int32_t rt = (int32_t)(blockIdx.x % (uint32_t)nrt), ct = (int32_t)(blockIdx.x / (uint32_t)nrt);
+    const int32_t s0 = slot0 + ct * kRlSlots;
+    if (s0 >= Lv) return;
+    __shared__ double2 sF[KF][kRlRows / 2];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = (int64_t)rt * kRlRows, i = i0 + 2 * lane;  // the lane's first row
+    const bool row_ok = i <= m;  // (then i + 1 < ld: ld is even)
+    const int32_t sw = s0 + kRlPer * w;  // this wave's first slot
+    // the wave's 16 columns: one load by lanes 0..15, then read from those
+    // lanes (wave-uniform); every load address is valid (the row clamped into
+    // the column, an unused slot reading column 0), the stores are masked
+    const int32_t cl = lane < kRlPer && sw + lane < Lv ? cols[sw + lane] : -1;
+    int32_t jc[kRlPer];
+    double2 x[kRlPer];
+    const int64_t ic = row_ok ? i : 0;
+#pragma unroll
+    for (int u = 0; u < kRlPer; ++u) {
+        jc[u] = __builtin_amdgcn_readlane(cl, u);
+        x[u] = *reinterpret_cast<const double2 *>(T + (int64_t)(jc[u] >= 0 ? jc[u] : 0) * ld + ic);
+    }
+    rl_stage<KF>(sF, Fk, ld, i0);
+    __syncthreads();
+    rl_chain<KF>(x, sF, Rk + sw, Lg, lane);
+    if (row_ok) {
+#pragma unroll
+        for (int u = 0; u < kRlPer; ++u)
+            if (jc[u] >= 0) *reinterpret_cast<double2 *>(T + (int64_t)jc[u] * ld + i) = x[u];
+    }
+}
+
+// The first pass after a deferred build in row-lane tiles: slot j < n holds
+// structural column j during the first group, so lane l reads rows i, i+1 of
+// A (16 consecutive entries of each, row 0: -c; rows past m: zeros) and
+// writes the entries after the group's pivots to the tableau, padding rows
+// included. A group of no pivots writes the build alone. The slots from n on
+// take the pure pass (slot0 = n).
+template <int KF>
+__global__ __launch_bounds__(256) void k_gfirst_rl(double *__restrict__ T, int64_t ld, int32_t m, int32_t n,
+                                                   int64_t Lg, int32_t nrt, const double *__restrict__ A,
+                                                   const double *__restrict__ cv, const double *__restrict__ Rk,
+                                                   const double *__restrict__ Fk, const GroupState *__restrict__ gs) {
+    const int32_t kd = gs->stalled ? 0 : gs->kdone;  // a stalled group: the build alone
+    const int32_t rt = (int32_t)(blockIdx.x % (uint32_t)nrt), ct = (int32_t)(blockIdx.x / (uint32_t)nrt);
+    const int32_t s0 = ct * kRlSlots;
+    __shared__ double2 sF[KF][kRlRows / 2];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = (int64_t)rt * kRlRows, i = i0 + 2 * lane;
+    const int32_t sw = s0 + kRlPer * w;  // this wave's first structural column
+    // 16-byte loads need an even n and a 16-byte aligned A (then every row
+    // and every wave's first column are 16-byte aligned)
+    const bool vec = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 && sw + kRlPer <= n;
+    double e[2][kRlPer];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t r = i + h;
+        if (r == 0) {
+#pragma unroll
+            for (int u = 0; u < kRlPer; ++u) e[h][u] = sw + u < n ? -cv[sw + u] : 0.0;
+        } else if (r <= m) {
+            const double *a = A + (r - 1) * (int64_t)n + sw;
+            if (vec) {
+#pragma unroll
+                for (int u = 0; u < kRlPer / 2; ++u) {
+                    const double2 v = reinterpret_cast<const double2 *>(a)[u];
+                    e[h][2 * u] = v.x;
+                    e[h][2 * u + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kRlPer; ++u) e[h][u] = sw + u < n ? a[u] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kRlPer; ++u) e[h][u] = 0.0;
+        }
+    }
+    double2 x[kRlPer];
+#pragma unroll
+    for (int u = 0; u < kRlPer; ++u) x[u] = double2{e[0][u], e[1][u]};
+    if (kd > 0) {
+        rl_stage<KF>(sF, Fk, ld, i0);
+        __syncthreads();
+        rl_chain<KF>(x, sF, Rk + sw, Lg, lane);
+    }
+    if (i < ld) {
+#pragma unroll
+        for (int u = 0; u < kRlPer; ++u)
+            if (sw + u < n) *reinterpret_cast<double2 *>(T + (int64_t)(sw + u) * ld + i) = x[u];
     }
 }
 

@@ -52,6 +52,27 @@ void update_pure(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hip
                            (const GroupState *)a.gs, a.dump, 0);
 }
 
+// The pure pass in row-lane tiles (k_gpure_rl) over slots slot0 .. n+K.
+template <int KF>
+void launch_pure_rl(const FusedArgs &a, int32_t slot0, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int32_t nrt = (a.m + kRlRows) / kRlRows;  // tiles of rows 0..m
+    const unsigned grid = (unsigned)((int64_t)nrt * ((Lg - slot0 + kRlSlots - 1) / kRlSlots));
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((k_gpure_rl<KF>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg, nrt,
+                              (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                              (const GroupState *)a.gs, slot0);
+    else
+        hipLaunchKernelGGL((k_gpure_rl<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, nrt,
+                           (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, slot0);
+}
+
+template <int B, int C, int KF>
+void update_pure_rl(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    launch_pure_rl<KF>(a, 0, s, e0, e1);
+}
+
 using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <int B, int C>
@@ -64,10 +85,12 @@ UpdateFn pick_pure(int K) {
         case 16: return update_pure<B, C, 16>;
         default: break;
     }
-    if constexpr (C >= 4) {  // groups above 16 pivots: 4 or 8 slots per workgroup
+    if constexpr (C >= 4) {  // groups above 16 pivots: 4 or 8 slots per workgroup; 48 in row-lane tiles
+                             // (F in LDS, R through the scalar cache)
         switch (fused_update_kf(K)) {
             case 24: return update_pure<B, C, 24>;
             case 32: return update_pure<B, C, 32>;
+            case 48: return update_pure_rl<B, C, 48>;
             default: break;
         }
     }
@@ -141,6 +164,7 @@ void decide_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t
         switch (a.KF) {
             case 24: decide_bd<BD, First, 24>(a, A, c, s); break;
             case 32: decide_bd<BD, First, 32>(a, A, c, s); break;
+            case 48: decide_bd<BD, First, 48>(a, A, c, s); break;
             default: break;
         }
     }
@@ -175,6 +199,7 @@ int occupancy_kf(int KF) {
         switch (KF) {
             case 24: return occupancy_pair<BD, 24>();
             case 32: return occupancy_pair<BD, 32>();
+            case 48: return occupancy_pair<BD, 48>();
             default: break;
         }
     }
@@ -212,8 +237,28 @@ void launch_first_decide(const FusedArgs &a, const double *A, const double *c, h
 
 namespace {
 
+// The first pass in row-lane tiles: the structural columns (rows 0 .. ld-1,
+// padding written as zeros), then the pure pass over slots n .. n+K.
+template <int KF>
+void first_kf_rl(const FusedArgs &a, const double *A, const double *c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int32_t nrt = (int32_t)((a.ld + kRlRows - 1) / kRlRows);
+    const unsigned grid = (unsigned)((int64_t)nrt * ((a.n + kRlSlots - 1) / kRlSlots));
+    if (e0)
+        hipExtLaunchKernelGGL((k_gfirst_rl<KF>), dim3(grid), dim3(256), 0, s, e0, nullptr, 0, a.T, a.ld, a.m, a.n, Lg,
+                              nrt, A, c, (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
+    else
+        hipLaunchKernelGGL((k_gfirst_rl<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, nrt, A, c,
+                           (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
+    launch_pure_rl<KF>(a, a.n, s, nullptr, e1);
+}
+
 template <int KF>
 void first_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if constexpr (KF >= kRlFromKF) {
+        first_kf_rl<KF>(a, A, c, s, e0, e1);
+        return;
+    }
     const int64_t Lg = (int64_t)a.n + 1 + a.K;
     const int32_t ntx = (a.n + kFirstTile - 1) / kFirstTile;
     const int32_t nty = (int32_t)((a.ld + kFirstRows - 1) / kFirstRows);
@@ -249,6 +294,7 @@ void launch_first_update(const FusedArgs &a, const double *A, const double *c, h
         case 16: first_kf<16>(a, A, c, s, e0, e1); break;
         case 24: first_kf<24>(a, A, c, s, e0, e1); break;
         case 32: first_kf<32>(a, A, c, s, e0, e1); break;
+        case 48: first_kf<48>(a, A, c, s, e0, e1); break;
         default: break;
     }
     launch_fix(a, s);

@@ -40,10 +40,10 @@ struct FusedArgs {
     double *PV;         // the group's pivot rows after the group, K rows of n + 1 + K doubles
 };
 
-// Update instances exist for groups of up to 2, 4, 8, 12, 16, 24 and 32
-// pivots (above 16 with the one-launch decision kernel only).
+// Update instances exist for groups of up to 2, 4, 8, 12, 16, 24, 32 and
+// 48 pivots (above 16 with the one-launch decision kernel only).
 inline int32_t fused_update_kf(int32_t K) {
-    return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : K <= 16 ? 16 : K <= 24 ? 24 : 32;
+    return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : K <= 16 ? 16 : K <= 24 ? 24 : K <= 32 ? 32 : 48;
 }
 
 // The one-launch decision kernel: G workgroups of `block` threads, one row

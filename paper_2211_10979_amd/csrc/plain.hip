@@ -224,7 +224,7 @@ int validate_opts(const Options &o) {
         o.update_block != 512 && o.update_block != 1024)
         return set_error(LP_E_INVAL, "update_block must be 0 (auto) or one of 64, 128, 256, 512, 1024");
     if (o.chunk_pivots < 0) return set_error(LP_E_INVAL, "chunk_pivots must be >= 0");
-    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 32]");
+    if (o.fuse_pivots < 0 || o.fuse_pivots > kMaxFuse) return set_error(LP_E_INVAL, "fuse_pivots must be in [0, 48]");
     if (o.decide_kernel < 0 || o.decide_kernel > 1) return set_error(LP_E_INVAL, "decide_kernel must be 0 or 1");
     if (o.decide_spin < -1) return set_error(LP_E_INVAL, "decide_spin must be >= -1");
     if (o.decide_block != 0 && o.decide_block != 256 && o.decide_block != 512)
@@ -392,7 +392,7 @@ size_t carve_aux(lp_ctx *h, unsigned char *base) {
     // both are padded past the last slot
     take(&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t));
     take(&h->pos, ((size_t)n + m) * sizeof(int32_t));
-    take(&h->Rl, ((size_t)kf * h->Lg + 16) * sizeof(double));
+    take(&h->Rl, ((size_t)kf * h->Lg + 64) * sizeof(double));  // (row-lane tiles read R of 64 slots past the list)
     take(&h->gpick, 4 * sizeof(int32_t));
     if (h->fuse > 1) {
         take(&h->gs, sizeof(GroupState));

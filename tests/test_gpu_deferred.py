@@ -73,7 +73,7 @@ def compare_final(h, o):
     return orow.tolist(), ocol.tolist()
 
 
-@pytest.mark.parametrize("K", [2, 4, 11, 16, 24, 32])
+@pytest.mark.parametrize("K", [2, 4, 11, 16, 24, 32, 40, 48])
 def test_degenerate_battery_deferred(K):
     """120 small LPs of several shapes through one context each, reloaded;
     the battery has in-group re-entries, so slack columns are stored on

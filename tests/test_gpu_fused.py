@@ -89,7 +89,7 @@ def solve_and_compare(A, b, c, **opts):
         o.close()
 
 
-@pytest.mark.parametrize("K,decide", [(2, 0), (3, 0), (4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (20, 0), (32, 0),
+@pytest.mark.parametrize("K,decide", [(2, 0), (3, 0), (4, 0), (5, 0), (8, 0), (11, 0), (16, 0), (20, 0), (32, 0), (48, 0),
                                      (4, 1), (16, 1)])
 def test_degenerate_battery(K, decide):
     """120 small LPs; the battery contains in-group re-entries of both kinds.
@@ -106,9 +106,9 @@ def test_degenerate_battery(K, decide):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K", range(1, 33))
+@pytest.mark.parametrize("K", range(1, 49))
 def test_every_group_size(K):
-    """Every group size from 1 to 32 with the one-launch decisions, and 1 to
+    """Every group size from 1 to 48 with the one-launch decisions, and 1 to
     16 with two launches per pivot: 16 degenerate LPs each, log, tableau, x
     and y equal to the oracle's."""
     say(f"fused K={K}: 16 degenerate LPs")
@@ -119,7 +119,7 @@ def test_every_group_size(K):
             solve_and_compare(A, b, c, fuse_pivots=K, decide_kernel=1)
 
 
-@pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (24, 0), (31, 0), (7, 1),
+@pytest.mark.parametrize("K,decide", [(2, 0), (4, 0), (7, 0), (8, 0), (13, 0), (16, 0), (24, 0), (31, 0), (41, 0), (7, 1),
                                      (16, 1)])
 def test_group_boundaries_by_stepping(K, decide):
     """lp_step budgets that cut groups short and ones that span several
@@ -150,7 +150,7 @@ def test_group_boundaries_by_stepping(K, decide):
         o.close()
 
 
-@pytest.mark.parametrize("K,decide", [(1, 0), (3, 0), (4, 0), (8, 0), (12, 0), (16, 0), (24, 0), (32, 0), (12, 1)])
+@pytest.mark.parametrize("K,decide", [(1, 0), (3, 0), (4, 0), (8, 0), (12, 0), (16, 0), (24, 0), (32, 0), (48, 0), (12, 1)])
 def test_dense_2000_full_solve(K, decide):
     lp = lpgen.workload("dense_2000x2000")
     say(f"fused K={K} decide_kernel={decide}: dense_2000x2000")
@@ -251,7 +251,7 @@ def test_work_counter_counts_the_union_of_a_group():
 def test_options_are_checked():
     lp = lpgen.dense_lp(2, 600, 200)  # m + 1 > 256: every update option applies
     A, b, c = lp.A, lp.b, lp.c
-    for bad in (dict(fuse_pivots=33), dict(fuse_pivots=17, decide_kernel=1), dict(fuse_pivots=-1),
+    for bad in (dict(fuse_pivots=49), dict(fuse_pivots=17, decide_kernel=1), dict(fuse_pivots=-1),
                 dict(fuse_pivots=4, cols_per_block=16), dict(fuse_pivots=24, cols_per_block=1),
                 dict(fuse_pivots=2, rows_per_thread=4), dict(fuse_pivots=2, rows_per_thread=2),
                 dict(fuse_pivots=2, select_workgroups=2),
