@@ -161,11 +161,11 @@ def bench_plain(args, lpgpu, lpgen, torch):
         readback = info.status_readback
         if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24, 32 or 48 pivots
             kf = next(k for k in (2, 4, 8, 12, 16, 24, 32, 48) if k >= fuse)
-            if info.decide_workgroups > 0 and kf >= 48:  # row-lane tiles
-                kernel = f"k_gpure_rl<{kf}>"
+            if info.decide_workgroups > 0 and kf >= 24:  # on the matrix cores
+                kernel = f"k_gpure_mf<{kf}>"
             else:
                 name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"
-                kernel = f"{name}<{info.update_block}, {info.update_cols}, {kf}>""
+                kernel = f"{name}<{info.update_block}, {info.update_cols}, {kf}>"
         else:
             kernel = (f"k_update<{info.update_block}, {info.update_cols}, {info.update_rows}, "
                       f"{info.update_hints & 1}, {info.update_hints >> 1}>")

@@ -1843,6 +1843,99 @@ __global__ __launch_bounds__(256) void k_gfirst_rl(double *__restrict__ T, int64
     }
 }
 
+// The pure pass on the matrix cores. The pass is a rank-KF update of every
+// listed column, X -= F R (F: the group's pivot columns, R: their
+// normalised pivot rows), each entry a chain of fmas in pivot order. The FP64
+// MFMA v_mfma_f64_16x16x4f64 computes D = A B + C as four fmas per entry in k
+// order, one rounding each (the same bits as the chain, special values
+// included), so four pivots at a time run as one MFMA with A = -R (16 slots by
+// 4 pivots), B = F (4 pivots by 16 rows) and C = the entries (16 slots by 16
+// rows): fma(-R_k, F_k, x) equals fma(-F_k, R_k, x) (one exact product, one
+// rounding). A workgroup takes 64 rows by 64 slots: wave w the slots
+// 16w .. 16w+15 over four tiles of 16 rows. The matrix layout of the
+// instruction: A lane l = A[l % 16][l / 16], B lane l = B[l / 16][l % 16],
+// C/D lane l element e = D[4e + l / 16][l % 16], so element e of a lane is row
+// l % 16 of slot 4e + l / 16: every load and store covers 16 consecutive rows
+// (128 bytes) of four columns. Rows up to the padded length are rewritten
+// (the padding holds zeros that no pivot changes).
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+constexpr int kMfWr = 1;                    // waves stacked along the rows of a tile
+constexpr int kMfRows = 64 * kMfWr;         // rows per tile
+constexpr int kMfSlots = 16 * (4 / kMfWr);  // slots per tile
+
+template <int KF>
+__device__ __forceinline__ void mf_stage(double (*sF)[kMfRows], const double *__restrict__ Fk, int64_t ld, int64_t i0) {
+    for (int t = threadIdx.x; t < KF * kMfRows; t += 256) {
+        const int k = t / kMfRows, l = t % kMfRows;
+        const int64_t i = i0 + l;
+        sF[k][l] = i < ld ? Fk[(int64_t)k * ld + i] : 0.0;
+    }
+}
+
+// acc[rt] (row tile rt of the wave's 64 rows, from tile row r0) after the KF
+// pivots: the A operand (-R of the lane's slot row l % 16, pivot
+// 4s + l / 16) from memory, the B operand (F of row r0 + 16 rt + l % 16,
+// pivot 4s + l / 16) from LDS.
+template <int KF>
+__device__ __forceinline__ void mf_chain(v4d_t (&acc)[4], const double (*sF)[kMfRows], const double *__restrict__ Rk,
+                                         int64_t Lg, int32_t sw, int r0, int lane) {
+    const int kq = lane >> 4, ll = lane & 15;
+#pragma unroll 4
+    for (int s = 0; s < KF / 4; ++s) {
+        const double r = -Rk[(int64_t)(4 * s + kq) * Lg + sw + ll];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const double f = sF[4 * s + kq][r0 + 16 * rt + ll];
+            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(r, f, acc[rt], 0, 0, 0);
+        }
+    }
+}
+
+template <int KF>
+__global__ __launch_bounds__(256) void k_gpure_mf(double *__restrict__ T, int64_t ld, int32_t m, int32_t n, int64_t Lg,
+                                                  int32_t nrt, const int32_t *__restrict__ cols,
+                                                  const double *__restrict__ Rk, const double *__restrict__ Fk,
+                                                  const GroupState *__restrict__ gs, int32_t slot0) {
+    static_assert(KF % 4 == 0, "four pivots per MFMA");
+    if (gs->kdone == 0 || gs->stalled) return;
+    const int32_t Lv = n + 1 + gs->napp;
+    const int32_t rtile = (int32_t)(blockIdx.x % (uint32_t)nrt), ct = (int32_t)(blockIdx.x / (uint32_t)nrt);
+    const int32_t s0 = slot0 + ct * kMfSlots;
+    if (s0 >= Lv) return;
+    __shared__ double sF[KF][kMfRows];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wr = w % kMfWr, ws = w / kMfWr;
+    const int64_t i0 = (int64_t)rtile * kMfRows;
+    const int r0 = 64 * wr;  // the wave's first row in the tile
+    const int32_t sw = s0 + 16 * ws;
+    const int kq = lane >> 4, ll = lane & 15;
+    // element e of the lane: slot sw + 4e + kq; its column (or -1)
+    int32_t jc[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t sl = sw + 4 * e + kq;
+        jc[e] = sl < Lv ? cols[sl] : -1;
+    }
+    v4d_t acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const int64_t row = i0 + r0 + 16 * rt + ll;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            acc[rt][e] = jc[e] >= 0 && row < ld ? T[(int64_t)jc[e] * ld + row] : 0.0;
+    }
+    mf_stage<KF>(sF, Fk, ld, i0);
+    __syncthreads();
+    mf_chain<KF>(acc, sF, Rk, Lg, sw, r0, lane);
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const int64_t row = i0 + r0 + 16 * rt + ll;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (jc[e] >= 0 && row < ld) T[(int64_t)jc[e] * ld + row] = acc[rt][e];
+    }
+}
+
 // The pivot rows of the group's list columns after its update pass: row
 // r_a of the column in slot t takes PV[a][t], its value after the group that
 // the decision kernel computed (the pass applied the chain without the

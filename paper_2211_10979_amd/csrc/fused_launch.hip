@@ -68,9 +68,25 @@ void launch_pure_rl(const FusedArgs &a, int32_t slot0, hipStream_t s, hipEvent_t
                            (const GroupState *)a.gs, slot0);
 }
 
+// The pure pass on the matrix cores (k_gpure_mf) over slots slot0 .. n+K.
+template <int KF>
+void launch_pure_mf(const FusedArgs &a, int32_t slot0, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const int64_t Lg = (int64_t)a.n + 1 + a.K;
+    const int32_t nrt = (int32_t)((a.ld + kMfRows - 1) / kMfRows);
+    const unsigned grid = (unsigned)((int64_t)nrt * ((Lg - slot0 + kMfSlots - 1) / kMfSlots));
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((k_gpure_mf<KF>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg, nrt,
+                              (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                              (const GroupState *)a.gs, slot0);
+    else
+        hipLaunchKernelGGL((k_gpure_mf<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, nrt,
+                           (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
+                           (const GroupState *)a.gs, slot0);
+}
+
 template <int B, int C, int KF>
-void update_pure_rl(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    launch_pure_rl<KF>(a, 0, s, e0, e1);
+void update_pure_mf(const FusedArgs &a, unsigned, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    launch_pure_mf<KF>(a, 0, s, e0, e1);
 }
 
 using UpdateFn = void (*)(const FusedArgs &, unsigned, hipStream_t, hipEvent_t, hipEvent_t);
@@ -85,12 +101,11 @@ UpdateFn pick_pure(int K) {
         case 16: return update_pure<B, C, 16>;
         default: break;
     }
-    if constexpr (C >= 4) {  // groups above 16 pivots: 4 or 8 slots per workgroup; 48 in row-lane tiles
-                             // (F in LDS, R through the scalar cache)
+    if constexpr (C >= 4) {  // groups above 16 pivots: 4 or 8 slots per workgroup; 48 on the matrix cores
         switch (fused_update_kf(K)) {
             case 24: return update_pure<B, C, 24>;
             case 32: return update_pure<B, C, 32>;
-            case 48: return update_pure_rl<B, C, 48>;
+            case 48: return update_pure_mf<B, C, 48>;
             default: break;
         }
     }
