@@ -161,7 +161,7 @@ def bench_plain(args, lpgpu, lpgen, torch):
         readback = info.status_readback
         if fuse > 1:  # the update instance: groups of up to 2, 4, 8, 12, 16, 24, 32 or 48 pivots
             kf = next(k for k in (2, 4, 8, 12, 16, 24, 32, 48) if k >= fuse)
-            if info.decide_workgroups > 0 and kf >= 24:  # on the matrix cores
+            if info.decide_workgroups > 0 and kf >= 48:  # on the matrix cores
                 kernel = f"k_gpure_mf<{kf}>"
             else:
                 name = "k_gupdate_pure" if info.decide_workgroups > 0 else "k_gupdate"

@@ -63,6 +63,20 @@ constexpr int kMaxFuseSplit = 16;  // with the two launches per pivot (k_gselect
 constexpr int32_t kStallBarrier = 1;
 constexpr int32_t kStallGate = 2;
 
+// 16-byte loads and stores with the non-temporal hint, for the passes that
+// stream the tableau (and A) once: they leave the L2 to the group's F and R,
+// which every tile reads again (without them the first pass fetched 1.6
+// times its bytes).
+typedef double v2nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 nt_load2(const void *p) {
+    const v2nt v = __builtin_nontemporal_load(reinterpret_cast<const v2nt *>(p));
+    return double2{v.x, v.y};
+}
+__device__ __forceinline__ void nt_store2(void *p, const double2 &x) {
+    const v2nt v = {x.x, x.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2nt *>(p));
+}
+
 // Decisions of the current group, resident in device memory.
 struct GroupState {
     int32_t kdone;  // pivots decided in this group
@@ -1515,7 +1529,7 @@ __device__ __forceinline__ void pure_tile(double *__restrict__ T, int64_t ld, in
         p[c] = reinterpret_cast<double2 *>(jc >= 0 && c0 + c < Lv ? T + (int64_t)jc * ld : dump) + vs;
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) x[c] = *p[c];
+    for (int c = 0; c < C; ++c) x[c] = nt_load2(p[c]);
     for (int t = threadIdx.x; t < C * KF; t += B) {  // C * KF may exceed B
         const int k = t % KF, c = t / KF;
         sR[c][k] = c0 + c < Lv ? Rk[(int64_t)k * Lg + c0 + c] : 0.0;
@@ -1533,7 +1547,7 @@ __device__ __forceinline__ void pure_tile(double *__restrict__ T, int64_t ld, in
         }
     if (live) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) *p[c] = x[c];
+        for (int c = 0; c < C; ++c) nt_store2(p[c], x[c]);
     }
 }
 
@@ -1616,7 +1630,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
             } else if (i <= m) {
                 const double *a = A + (i - 1) * n + j;
                 if (vec_a && j + 1 < n) {  // j is even
-                    v = *reinterpret_cast<const double2 *>(a);
+                    v = nt_load2(a);
                 } else {
                     if (j < n) v.x = a[0];
                     if (j + 1 < n) v.y = a[1];
@@ -1653,7 +1667,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
         for (int u = 0; u < TC / CG; ++u) {
             const int cl = cg + CG * u;
             const int64_t j = j0 + cl;
-            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = double2{tile[2 * p][cl], tile[2 * p + 1][cl]};
+            if (j < n) nt_store2(T + j * ld + iw, double2{tile[2 * p][cl], tile[2 * p + 1][cl]});
         }
         return;
     }
@@ -1674,7 +1688,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
                 x.x = fma(-f.x, R, x.x);
                 x.y = fma(-f.y, R, x.y);
             }
-            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
+            if (j < n) nt_store2(T + j * ld + iw, x);
         }
     } else {
         double2 f[KF];
@@ -1691,7 +1705,7 @@ __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t 
                 x.x = fma(-f[k].x, R, x.x);
                 x.y = fma(-f[k].y, R, x.y);
             }
-            if (j < n) *reinterpret_cast<double2 *>(T + j * ld + iw) = x;
+            if (j < n) nt_store2(T + j * ld + iw, x);
         }
     }
 }
