@@ -56,10 +56,13 @@ struct ArgMin {
 
 // Lexicographic order: smaller value first, then the lower index. A NaN wins
 // over every number so that it reaches the final stage, which reports it.
+// (Written with bitwise operators and one select, so that it compiles to
+// compares and mask logic without branches.)
 __device__ __forceinline__ bool lex_less(double av, int32_t ai, double bv, int32_t bi) {
-    const bool an = av != av, bn = bv != bv;
-    if (an || bn) return an && (!bn || ai < bi);
-    return av < bv || (av == bv && ai < bi);
+    const bool an = av != av, bn = bv != bv, ilt = ai < bi;
+    const bool lt = (av < bv) | ((av == bv) & ilt);
+    const bool nl = an & (!bn | ilt);
+    return (an | bn) ? nl : lt;
 }
 
 // Non-finite values (the paper does not discuss them; the reading shared with

@@ -594,10 +594,12 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
 // Reductions of the decision kernel. Within a row of 16 lanes the wave
 // argmin exchanges values by DPP (quad permutations, then the half-row and
 // row mirrors: after these four steps every lane holds its row's winner);
-// the last two steps cross rows with shuffles. The argmin is unique under
-// the (value, index) order of lex_less, so the result does not depend on the
-// order of the reduction: every wave that reduces the same candidates gets
-// the same winner.
+// the last two steps cross rows with the lane swaps of gfx950
+// (v_permlane16_swap, v_permlane32_swap: VALU exchanges, no LDS round trip).
+// Every step is compares and selects, without branches. The argmin is unique
+// under the (value, index) order of lex_less, so the result does not depend
+// on the order of the reduction: every wave that reduces the same candidates
+// gets the same winner.
 template <int CTRL>
 __device__ __forceinline__ int32_t dpp_i32(int32_t x) {
     return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
@@ -613,25 +615,40 @@ __device__ __forceinline__ double readlane_f64(double x, int32_t lane) {
                             __builtin_amdgcn_readlane(__double2loint(x), lane));
 }
 
+// Keeps the smaller of (v, i, t) and (ov, oi, ot) under lex_less.
+__device__ __forceinline__ void argmin_take(double &v, int32_t &i, int32_t &t, double ov, int32_t oi, int32_t ot) {
+    const bool take = lex_less(ov, oi, v, i);
+    v = take ? ov : v;
+    i = take ? oi : i;
+    t = take ? ot : t;
+}
+
 template <int CTRL>
 __device__ __forceinline__ void dpp_step(double &v, int32_t &i, int32_t &t) {
-    const double ov = dpp_f64<CTRL>(v);
-    const int32_t oi = dpp_i32<CTRL>(i), ot = dpp_i32<CTRL>(t);
-    if (lex_less(ov, oi, v, i)) {
-        v = ov;
-        i = oi;
-        t = ot;
+    argmin_take(v, i, t, dpp_f64<CTRL>(v), dpp_i32<CTRL>(i), dpp_i32<CTRL>(t));
+}
+
+// x of lane l ^ 16 (W = 16) or l ^ 32 (W = 32), with every lane active: the
+// swap of a register with itself leaves, in the first result, rows 0 and 2
+// (lanes 0-31 for W = 32) in their place and their copies in rows 1 and 3
+// (lanes 32-63), and in the second result rows 1 and 3 (lanes 32-63) with
+// their copies in rows 0 and 2 (lanes 0-31).
+template <int W>
+__device__ __forceinline__ int32_t swap_i32(int32_t x) {
+    const bool hi = (threadIdx.x & W) != 0;
+    if constexpr (W == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return hi ? r[0] : r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return hi ? r[0] : r[1];
     }
 }
 
-__device__ __forceinline__ void xor_step(double &v, int32_t &i, int32_t &t, int off) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int32_t oi = __shfl_xor(i, off, 64), ot = __shfl_xor(t, off, 64);
-    if (lex_less(ov, oi, v, i)) {
-        v = ov;
-        i = oi;
-        t = ot;
-    }
+template <int W>
+__device__ __forceinline__ void swap_step(double &v, int32_t &i, int32_t &t) {
+    const double ov = __hiloint2double(swap_i32<W>(__double2hiint(v)), swap_i32<W>(__double2loint(v)));
+    argmin_take(v, i, t, ov, swap_i32<W>(i), swap_i32<W>(t));
 }
 
 // wave argmin of (v, i) carrying t; every lane gets the winner
@@ -640,8 +657,8 @@ __device__ __forceinline__ void wave_argmin_dpp(double &v, int32_t &i, int32_t &
     dpp_step<0x4E>(v, i, t);   // quad_perm [2,3,0,1]
     dpp_step<0x141>(v, i, t);  // row_half_mirror
     dpp_step<0x140>(v, i, t);  // row_mirror
-    xor_step(v, i, t, 16);
-    xor_step(v, i, t, 32);
+    swap_step<16>(v, i, t);    // rows 0 <-> 1, 2 <-> 3
+    swap_step<32>(v, i, t);    // lanes 0-31 <-> 32-63
 }
 
 // Block argmin with one barrier: `sv`, `si`, `sl` (one entry per wave) must
@@ -658,10 +675,13 @@ __device__ __forceinline__ void block_argmin_dpp(double &v, int32_t &i, int32_t 
         sl[wave] = t;
     }
     __syncthreads();
-    v = lane < BD / 64 ? sv[lane] : __builtin_inf();
-    i = lane < BD / 64 ? si[lane] : kNoIndex;
-    t = lane < BD / 64 ? sl[lane] : -1;
-    wave_argmin_dpp(v, i, t);
+    // the wave winners, read by every lane (one LDS address per read) and
+    // reduced in registers
+    v = sv[0];
+    i = si[0];
+    t = sl[0];
+#pragma unroll
+    for (int u = 1; u < BD / 64; ++u) argmin_take(v, i, t, sv[u], si[u], sl[u]);
 }
 
 // k_gdecide runs the group's Steps 1-2 and the Step 3 inputs (what k_gselect
@@ -908,9 +928,13 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
     (void)rparts;  // (the Step 2 partials travel with the barrier here)
     __shared__ int32_t s_ok;
     // the partials the barriers carry: Step 1 (value, column, slot) and Step 2
-    // (ratio, row, leaving column, in-list flag, pivot value, RHS entry)
+    // (row, leaving column with the in-list flag, pivot value, RHS entry)
     __shared__ uint32_t xs_s[kMaxDecideWgsXch][4];
-    __shared__ uint32_t xs_r[kMaxDecideWgsXch][9];
+    __shared__ uint32_t xs_r[kMaxDecideWgsXch][6];
+    // each row's Step 2 candidate (pivot entry, RHS entry, leaving column and
+    // whether it has a slot), read by thread 0 for the workgroup's winner
+    __shared__ double sc_a[BD], sc_b[BD];
+    __shared__ uint32_t sc_l[BD];
     const int tid = threadIdx.x;
     const int G = gridDim.x, w = blockIdx.x;
     const int64_t Lg = (int64_t)n + 1 + K;
@@ -1118,23 +1142,36 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
                 r = i;
             }
         }
-        const int32_t r_mine = r;
+        if (r != kNoIndex) {
+            sc_a[tid] = a;
+            sc_b[tid] = bb;
+            sc_l[tid] = (uint32_t)basis_i | (inlist_i ? 0x80000000u : 0u);
+        }
         {
             int32_t unused = 0;
             block_argmin_dpp<BD>(rv, r, unused, sv_r, si_r, sl_r);
         }
-        // the workgroup's Step 2 partial, written by the thread that owns
-        // row r (by thread 0 when no row qualifies); lpos carries "the
-        // leaving column has a slot" here
-        if (r != kNoIndex && r_mine == r) {
-            const uint32_t d[9] = {lo32(rv), hi32(rv), (uint32_t)r, (uint32_t)basis_i, (uint32_t)inlist_i,
-                                   lo32(a), hi32(a), lo32(bb), hi32(bb)};
-            xch_publish<9>(gsync->xch[nbar][w], d, flag);
-        } else if (r == kNoIndex && tid == 0) {
-            const uint32_t d[9] = {lo32(rv), hi32(rv), (uint32_t)kNoIndex, 0xffffffffu, 0u, 0u, 0u, 0u, 0u};
-            xch_publish<9>(gsync->xch[nbar][w], d, flag);
+        // the workgroup's Step 2 partial, published by thread 0 (the
+        // argmin's barrier ordered the winner's candidate before the reads):
+        // the row, its leaving column with "has a slot" in bit 31, its pivot
+        // and RHS entries. The ratio itself is not sent: the readers compute
+        // it from the two entries as the rows did (the same division, so the
+        // same bits; a NaN candidate is recognised by step2_bad again).
+        if (tid == 0) {
+            uint32_t d[6] = {(uint32_t)kNoIndex, 0xffffffffu, 0u, 0u, 0u, 0u};
+            if (r != kNoIndex) {
+                const int32_t o = r - w * BD;
+                const double ca = sc_a[o], cb = sc_b[o];
+                d[0] = (uint32_t)r;
+                d[1] = sc_l[o];
+                d[2] = lo32(ca);
+                d[3] = hi32(ca);
+                d[4] = lo32(cb);
+                d[5] = hi32(cb);
+            }
+            xch_publish<6>(gsync->xch[nbar][w], d, flag);
         }
-        if (!xch_wait<9>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_r, &s_ok)) return;
+        if (!xch_wait<6>(gsync->xch[nbar], G, flag, spin_limit, st, gs, xs_r, &s_ok)) return;
         ++nbar;
         if (j == 0 && w == 0) {  // every workgroup has read the list
             if (tid < 64) store_close();
@@ -1149,8 +1186,11 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         {
             const GRatio none{__builtin_inf(), kNoIndex, 0, 0.0, -1, 0, 0.0};
             auto rec = [&](int u) {
-                return GRatio{as_f64(xs_r[u][0], xs_r[u][1]), (int32_t)xs_r[u][2], 0, as_f64(xs_r[u][5], xs_r[u][6]),
-                              (int32_t)xs_r[u][3], (int32_t)xs_r[u][4], as_f64(xs_r[u][7], xs_r[u][8])};
+                const int32_t rr = (int32_t)xs_r[u][0];
+                const uint32_t lw = xs_r[u][1];
+                const double ca = as_f64(xs_r[u][2], xs_r[u][3]), cb = as_f64(xs_r[u][4], xs_r[u][5]);
+                const double cv = rr == kNoIndex ? __builtin_inf() : (step2_bad(ca, cb) ? __builtin_nan("") : cb / ca);
+                return GRatio{cv, rr, 0, ca, (int32_t)(lw & 0x7fffffffu), (int32_t)(lw >> 31), cb};
             };
             GRatio pa = lane < G ? rec(lane) : none;
             const GRatio pb = lane + 64 < G ? rec(lane + 64) : none;
