@@ -1767,12 +1767,22 @@ constexpr int kRlSlots = 64;  // slots per tile: 16 per wave
 constexpr int kRlPer = 16;    // slots per thread
 constexpr int kRlFromKF = 32;  // groups of this many pivots and more take the row-lane tiles
 
+// The pivots a row-lane or matrix-core pass applies: the group's kd rounded
+// up to the chain's step (2 pivots, or 4 on the matrix cores), at most KF.
+// The decision kernel stores the pivots from kd on as exact identities, so
+// stopping there gives the same bits as running all KF.
+template <int KF, int STEP>
+__device__ __forceinline__ int chain_len(int32_t kd) {
+    const int kn = (kd + STEP - 1) / STEP * STEP;
+    return kn < KF ? kn : KF;
+}
+
 template <int KF>
 __device__ __forceinline__ void rl_stage(double2 (*sF)[kRlRows / 2], const double *__restrict__ Fk, int64_t ld,
-                                         int64_t i0) {
+                                         int64_t i0, int kn) {
     const double2 *F2 = reinterpret_cast<const double2 *>(Fk);
     const int64_t ldv = ld / 2;  // (ld and i0 are even)
-    for (int t = threadIdx.x; t < KF * (kRlRows / 2); t += 256) {
+    for (int t = threadIdx.x; t < kn * (kRlRows / 2); t += 256) {
         const int k = t / (kRlRows / 2), v = t % (kRlRows / 2);
         const int64_t i = i0 + 2 * v;
         sF[k][v] = i < ld ? F2[(int64_t)k * ldv + i / 2] : double2{0.0, 0.0};
@@ -1781,12 +1791,13 @@ __device__ __forceinline__ void rl_stage(double2 (*sF)[kRlRows / 2], const doubl
 
 // The chain over the wave's 16 slots for the lane's row pair: R_k of those
 // slots through scalar loads (Rw points at R_0 of the wave's first slot;
-// slots past the list read entries that are never stored), F_k from LDS.
+// slots past the list read entries that are never stored), F_k from LDS;
+// pivots 0 .. kn-1 (kn even).
 template <int KF>
 __device__ __forceinline__ void rl_chain(double2 (&x)[kRlPer], const double2 (*sF)[kRlRows / 2], const double *Rw,
-                                         int64_t Lg, int lane) {
+                                         int64_t Lg, int lane, int kn) {
 #pragma unroll 2
-    for (int k = 0; k < KF; ++k) {
+    for (int k = 0; k < kn; ++k) {
         const double2 f = sF[k][lane];
         const double *Rr = Rw + (int64_t)k * Lg;
 #pragma unroll
@@ -1826,9 +1837,10 @@ __global__ __launch_bounds__(256) void k_gpure_rl(double *__restrict__ T, int64_
         jc[u] = __builtin_amdgcn_readlane(cl, u);
         x[u] = *reinterpret_cast<const double2 *>(T + (int64_t)(jc[u] >= 0 ? jc[u] : 0) * ld + ic);
     }
-    rl_stage<KF>(sF, Fk, ld, i0);
+    const int kn = chain_len<KF, 2>(gs->kdone);
+    rl_stage<KF>(sF, Fk, ld, i0, kn);
     __syncthreads();
-    rl_chain<KF>(x, sF, Rk + sw, Lg, lane);
+    rl_chain<KF>(x, sF, Rk + sw, Lg, lane, kn);
     if (row_ok) {
 #pragma unroll
         for (int u = 0; u < kRlPer; ++u)
@@ -1886,9 +1898,10 @@ __global__ __launch_bounds__(256) void k_gfirst_rl(double *__restrict__ T, int64
 #pragma unroll
     for (int u = 0; u < kRlPer; ++u) x[u] = double2{e[0][u], e[1][u]};
     if (kd > 0) {
-        rl_stage<KF>(sF, Fk, ld, i0);
+        const int kn = chain_len<KF, 2>(kd);
+        rl_stage<KF>(sF, Fk, ld, i0, kn);
         __syncthreads();
-        rl_chain<KF>(x, sF, Rk + sw, Lg, lane);
+        rl_chain<KF>(x, sF, Rk + sw, Lg, lane, kn);
     }
     if (i < ld) {
 #pragma unroll
@@ -1918,24 +1931,25 @@ constexpr int kMfRows = 64 * kMfWr;         // rows per tile
 constexpr int kMfSlots = 16 * (4 / kMfWr);  // slots per tile
 
 template <int KF>
-__device__ __forceinline__ void mf_stage(double (*sF)[kMfRows], const double *__restrict__ Fk, int64_t ld, int64_t i0) {
-    for (int t = threadIdx.x; t < KF * kMfRows; t += 256) {
+__device__ __forceinline__ void mf_stage(double (*sF)[kMfRows], const double *__restrict__ Fk, int64_t ld, int64_t i0,
+                                         int kn) {
+    for (int t = threadIdx.x; t < kn * kMfRows; t += 256) {
         const int k = t / kMfRows, l = t % kMfRows;
         const int64_t i = i0 + l;
         sF[k][l] = i < ld ? Fk[(int64_t)k * ld + i] : 0.0;
     }
 }
 
-// acc[rt] (row tile rt of the wave's 64 rows, from tile row r0) after the KF
-// pivots: the A operand (-R of the lane's slot row l % 16, pivot
-// 4s + l / 16) from memory, the B operand (F of row r0 + 16 rt + l % 16,
-// pivot 4s + l / 16) from LDS.
+// acc[rt] (row tile rt of the wave's 64 rows, from tile row r0) after
+// pivots 0 .. kn-1 (kn a multiple of 4): the A operand (-R of the lane's
+// slot row l % 16, pivot 4s + l / 16) from memory, the B operand (F of row
+// r0 + 16 rt + l % 16, pivot 4s + l / 16) from LDS.
 template <int KF>
 __device__ __forceinline__ void mf_chain(v4d_t (&acc)[4], const double (*sF)[kMfRows], const double *__restrict__ Rk,
-                                         int64_t Lg, int32_t sw, int r0, int lane) {
+                                         int64_t Lg, int32_t sw, int r0, int lane, int kn) {
     const int kq = lane >> 4, ll = lane & 15;
 #pragma unroll 4
-    for (int s = 0; s < KF / 4; ++s) {
+    for (int s = 0; s < kn / 4; ++s) {
         const double r = -Rk[(int64_t)(4 * s + kq) * Lg + sw + ll];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
@@ -1978,9 +1992,10 @@ __global__ __launch_bounds__(256) void k_gpure_mf(double *__restrict__ T, int64_
         for (int e = 0; e < 4; ++e)
             acc[rt][e] = jc[e] >= 0 && row < ld ? T[(int64_t)jc[e] * ld + row] : 0.0;
     }
-    mf_stage<KF>(sF, Fk, ld, i0);
+    const int kn = chain_len<KF, 4>(gs->kdone);
+    mf_stage<KF>(sF, Fk, ld, i0, kn);
     __syncthreads();
-    mf_chain<KF>(acc, sF, Rk, Lg, sw, r0, lane);
+    mf_chain<KF>(acc, sF, Rk, Lg, sw, r0, lane, kn);
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt) {
         const int64_t row = i0 + r0 + 16 * rt + ll;
