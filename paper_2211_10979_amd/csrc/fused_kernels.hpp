@@ -1212,6 +1212,17 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
         }
         const int32_t aslot = inl ? -1 : n + 1 + napp;  // appended slot of the leaving column
         if (aslot >= 0) ++napp;
+        // The loads of the Step 3 inputs first, so that their latency covers
+        // the bookkeeping below: F_k at the pivot row (lane k), F_j[0], and
+        // this slot's pivot-row entry at the group's start (R = 0 for a slot
+        // not filled yet: its column is a unit vector that no pivot of the
+        // group has changed; the slot just appended holds e_r, whose entry in
+        // row r is 1, taken as is since its store below may not be visible
+        // yet)
+        const int32_t c_new = t == aslot ? leave : c_t;
+        const double fr_l = Fk[(int64_t)(lane < K ? lane : K - 1) * ld + r];  // lane k: F_k[r]
+        const double F0 = Fk[(int64_t)j * ld];
+        const double y0 = c_new < 0 ? 0.0 : (t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_new, r));
         if (w == 0 && tid == 0) {
             gs->r[j] = r;
             gs->q[j] = q;
@@ -1244,7 +1255,7 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
             basis_i = q;
             inlist_i = true;
         }
-        if (t == aslot) c_t = leave;
+        c_t = c_new;
         // a column that leaves the basis for the first time in this group is
         // stored now as the unit vector it is (e_r: its basic row is the
         // pivot row), which makes it readable by the later pivots of the
@@ -1255,20 +1266,13 @@ __device__ __forceinline__ void decide_body(double *__restrict__ T, int64_t ld, 
 
         // Step 3 inputs of this thread's slot: the pivot-row entry after the
         // j earlier pivots, R_j[t] = that / p, and the row-0 entry after
-        // pivot j (R = 0 for a slot not filled yet: its column is a unit
-        // vector that no pivot of the group has changed)
-        const double fr_l = Fk[(int64_t)(lane < K ? lane : K - 1) * ld + r];  // lane k: F_k[r]
-        const double F0 = Fk[(int64_t)j * ld];
+        // pivot j
         double R = 0.0;
         {
-            // (the slot just appended holds e_r, whose entry in row r is 1:
-            // taken as is, since the store above may not be visible yet).
             // The chain runs with every lane active: it reads the shared
             // factors from lanes 0 .. j-1, which must hold them
-            const bool live = c_t >= 0;
-            const double y0 = !live ? 0.0 : (t == aslot ? 1.0 : start_entry<First>(T, ld, n, A, cv, c_t, r));
             const double y = chain_tiered<KM, false>(y0, j, r, rk_l, rslot, fr_l);
-            if (live) {
+            if (c_t >= 0) {
                 R = y / p;
                 D_t = fma(-F0, R, D_t);
             }
