@@ -240,7 +240,7 @@ def bench_batch(args, lpgpu, lpgen, torch):
     h = lpgpu.lp_batch_create([(lp.A, lp.b, lp.c) for lp in lps])
     try:
         tune_ms = lpgpu.lp_batch_autotune(h, os.environ.get("LP_AUTOTUNE_CACHE"), trials=2)
-        shape = lpgpu.lp_batch_get_shape(h)
+        shape = dict(lpgpu.lp_batch_get_shape(h), **lpgpu.lp_batch_get_split(h))
         for _ in range(2):
             lpgpu.lp_batch_reset(h)
             lpgpu.lp_batch_solve(h)

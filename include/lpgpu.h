@@ -131,7 +131,9 @@ typedef struct {
                                with LP_STALLED (0 = default, about 0.2 s); its check-in gate
                                waits at least the default. -1: the first decision launch finds
                                its gate closed, as when its workgroups cannot all be resident
-                               (a test of the barrier-free fallback) */
+                               (a test of the barrier-free fallback); in the batched form, every
+                               split LP's check-in gate closes at once and one workgroup runs
+                               that LP whole */
     int32_t decide_block;   /* threads per workgroup of the decision kernel (256 or 512; 0 = auto:
                                256); 512 holds groups of at most 16 pivots */
     int32_t eager_build;    /* 0 = auto: with the one-launch decision kernel, lp_reload_device
@@ -435,6 +437,24 @@ int lp_batch_reset(lp_batch *bt);
 /* The persistent kernel's shape in use: threads per workgroup, items in
  * flight per thread, workgroups per compute unit. Any pointer may be NULL. */
 int lp_batch_get_shape(const lp_batch *bt, int32_t *block, int32_t *unroll, int32_t *grid_per_cu);
+
+/*
+ * How the shape in use splits large LPs. A split LP (Steps 1-3 of Section
+ * III as for any LP, with the same pivots and bits) is run by several
+ * workgroups at once, each rewriting a share of its columns and meeting the
+ * others twice per pivot: the batch's largest LPs, which would otherwise
+ * finish last, then take a fraction of the time. *max_parts: the shape's
+ * limit (1: no LP is split); *split_lps: LPs the current plan splits;
+ * *queue_entries: the persistent kernel's queue (one entry per LP, one per
+ * part of a split LP). Any pointer may be NULL. The autotuner chooses among
+ * shapes with and without splitting; LPs whose work area does not fit in
+ * LDS are never split.
+ */
+int lp_batch_get_split(const lp_batch *bt, int32_t *max_parts, int32_t *split_lps, int32_t *queue_entries);
+
+/* Selects the kernel shape (block, unroll, grid_per_cu, split: one of the
+ * shapes the autotuner tries) for later solves. LP_E_INVAL if no such shape. */
+int lp_batch_set_shape(lp_batch *bt, int32_t block, int32_t unroll, int32_t grid_per_cu, int32_t split);
 
 /*
  * Autotuner: solves the batch once per candidate kernel shape (rebuilding the

@@ -22,9 +22,13 @@ using namespace lpgpu;
 
 namespace lpgpu {
 
+// (the shapes that split large LPs come last: the server, which never
+// splits, takes the first shape that matches its options)
 const BatchShape kBatchShapes[] = {
-    {256, 1, 2}, {256, 2, 2}, {256, 4, 2}, {256, 4, 4}, {256, 8, 2}, {512, 1, 1}, {512, 2, 1}, {512, 2, 2},
-    {512, 4, 1}, {512, 4, 2}, {1024, 1, 1}, {1024, 2, 1}, {1024, 4, 1}, {1024, 2, 2},
+    {256, 1, 2},     {256, 2, 2},     {256, 4, 2},     {256, 4, 4},     {256, 8, 2},     {512, 1, 1},
+    {512, 2, 1},     {512, 2, 2},     {512, 4, 1},     {512, 4, 2},     {1024, 1, 1},    {1024, 2, 1},
+    {1024, 4, 1},    {1024, 2, 2},    {256, 2, 2, 8},  {512, 2, 2, 4},  {512, 2, 2, 8},  {1024, 2, 1, 4},
+    {1024, 2, 1, 8}, {1024, 4, 1, 4}, {1024, 4, 1, 8},
 };
 const int kNumBatchShapes = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
 
@@ -46,12 +50,12 @@ uint64_t nvec_magic(int32_t nvec) { return (((uint64_t)1 << 36) + (uint64_t)nvec
 
 int launch_batch_kernel(const BatchShape &sh, int grid, size_t lds, hipStream_t stream, const BatchDesc *desc,
                         BatchState *state, const int32_t *order, const int32_t *norder, int32_t *head,
-                        int64_t budget) {
+                        int64_t budget, const int32_t *parts, uint32_t gate_spin) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, head);
 #define LP_BATCH(B, U)                                                                                          \
     if (sh.block == B && sh.unroll == U) {                                                                      \
         hipLaunchKernelGGL((k_batch<B, U>), dim3((unsigned)grid), dim3(B), lds, stream, desc, state, order,     \
-                           norder, head, budget);                                                               \
+                           norder, head, budget, parts, gate_spin);                                             \
         return LP_OK;                                                                                           \
     }
     LP_BATCH(256, 1)
@@ -66,6 +70,28 @@ int launch_batch_kernel(const BatchShape &sh, int grid, size_t lds, hipStream_t 
     LP_BATCH(1024, 4)
 #undef LP_BATCH
     return set_error(LP_E_INVAL, "unsupported batch kernel shape");
+}
+
+int batch_blocks_per_cu(const BatchShape &sh, size_t lds) {
+    int blocks = 0;
+#define LP_OCC(B, U)                                                                                          \
+    if (sh.block == B && sh.unroll == U &&                                                                    \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(&k_batch<B, U>), B, \
+                                                     lds) == hipSuccess)                                     \
+        return blocks;
+    LP_OCC(256, 1)
+    LP_OCC(256, 2)
+    LP_OCC(256, 4)
+    LP_OCC(256, 8)
+    LP_OCC(512, 1)
+    LP_OCC(512, 2)
+    LP_OCC(512, 4)
+    LP_OCC(1024, 1)
+    LP_OCC(1024, 2)
+    LP_OCC(1024, 4)
+#undef LP_OCC
+    (void)hipGetLastError();
+    return 0;
 }
 
 // Raises (never lowers) the dynamic-LDS limit of every batched-kernel
@@ -106,7 +132,8 @@ int device_cus(int device) {
 }
 
 // ---- autotune cache: one JSON object per line,
-// {"key": "<bucket>", "block": B, "unroll": U, "grid_per_cu": G, "ms": t}
+// {"key": "<bucket>", "block": B, "unroll": U, "grid_per_cu": G, "split": S, "ms": t}
+// (a line without "split" means 1)
 std::string batch_bucket_key(int32_t count, int32_t mmax, int32_t nmax) {
     auto up = [](int64_t x) {
         int64_t p = 1;
@@ -127,12 +154,14 @@ bool cache_lookup(const char *path, const std::string &key, BatchShape *out) {
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[256];
-        int b = 0, u = 0, g = 0;
-        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d", k, &b,
-                        &u, &g) == 4 &&
-            key == k) {
+        int b = 0, u = 0, g = 0, sp = 1;
+        const int got = std::sscanf(line, " {\"key\": \"%255[^\"]\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d, "
+                                          "\"split\": %d", k, &b, &u, &g, &sp);
+        if (got >= 4 && key == k) {
+            if (got < 5) sp = 1;
             for (int i = 0; i < kNumBatchShapes; ++i)
-                if (kBatchShapes[i].block == b && kBatchShapes[i].unroll == u && kBatchShapes[i].grid_per_cu == g) {
+                if (kBatchShapes[i].block == b && kBatchShapes[i].unroll == u && kBatchShapes[i].grid_per_cu == g &&
+                    kBatchShapes[i].split == sp) {
                     *out = kBatchShapes[i];
                     found = true;  // the last matching line wins
                 }
@@ -148,8 +177,8 @@ void cache_store(const char *path, const std::string &key, const BatchShape &sh,
     std::lock_guard<std::mutex> lock(mu);
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d, \"ms\": %.6f}\n",
-                 key.c_str(), sh.block, sh.unroll, sh.grid_per_cu, ms);
+    std::fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"unroll\": %d, \"grid_per_cu\": %d, \"split\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), sh.block, sh.unroll, sh.grid_per_cu, sh.split, ms);
     std::fclose(f);
 }
 
@@ -186,9 +215,14 @@ struct lp_batch {
     int64_t *out_off_dev = nullptr;
     BatchDesc *desc = nullptr;
     BatchState *state = nullptr;
-    int32_t *order = nullptr;    // LP indices, largest first
+    int32_t *order = nullptr;    // the queue: LP indices, largest first (a split LP once per part)
+    int32_t *parts = nullptr;    // per queue entry: (parts << 8) | part of a split LP, else 0
     int32_t *norder = nullptr;   // number of entries of `order`
     int32_t *head = nullptr;     // queue head
+    BatchSync *sync = nullptr;   // meeting areas, one per LP (used by split LPs)
+    int32_t entries = 0;         // queue entries of the current plan
+    uint32_t gate_spin = kPartGateSpin;  // polls of a split LP's check-in gate (0: closes at once)
+    int32_t split_lps = 0;       // LPs the current plan splits
     int32_t *tile_lp = nullptr;  // build tile -> LP
     int64_t *tile_first = nullptr, *in_off_dev = nullptr;
     int64_t ntiles = 0;
@@ -216,7 +250,8 @@ void free_batch(lp_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void *p : {(void *)b->tab, (void *)b->ints, (void *)b->inputs, (void *)b->out, (void *)b->scratch,
                     (void *)b->out_off_dev,
-                    (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->norder, (void *)b->head,
+                    (void *)b->desc, (void *)b->state, (void *)b->order, (void *)b->parts, (void *)b->norder,
+                    (void *)b->head, (void *)b->sync,
                     (void *)b->tile_lp, (void *)b->tile_first, (void *)b->in_off_dev})
         if (p) (void)hipFree(p);
     if (b->e0) (void)hipEventDestroy(b->e0);
@@ -225,7 +260,58 @@ void free_batch(lp_batch *b) {
     delete b;
 }
 
+// The queue for the current shape: LPs in decreasing order of estimated work
+// ((m+1)(n+2) entries times min(m, n), a stand-in for the pivot count); with
+// a shape that splits, an LP whose estimate exceeds twice the work per
+// workgroup of the grid gets ceil(estimate / that) parts, at most
+// shape.split, and only while the parts of the split LPs fill at most half
+// of the grid (they come first, so their parts start together) and every
+// workgroup of the grid is resident at once. LPs whose work area lives in
+// global memory are never split.
+int plan_queue(lp_batch *b) {
+    const int32_t count = b->count;
+    std::vector<double> work(count);
+    double total = 0.0;
+    for (int32_t k = 0; k < count; ++k) {
+        work[k] = (double)(b->m[k] + 1) * (b->n[k] + 2) * std::min(b->m[k], b->n[k]);
+        total += work[k];
+    }
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+    const int slots = std::max(1, b->shape.grid_per_cu * b->cus);
+    int wmax = std::min(b->shape.split, kMaxBatchParts);
+    if (wmax > 1 && batch_blocks_per_cu(b->shape, b->lds) < b->shape.grid_per_cu) wmax = 1;
+    const double share = total / slots;
+    std::vector<int32_t> q, qp;
+    int used = 0;
+    b->split_lps = 0;
+    for (int32_t k : order) {
+        int w = 1;
+        if (wmax > 1 && !b->desc_host[k].scratch && work[k] > 2.0 * share) {
+            w = std::min<int>(wmax, (int)std::ceil(work[k] / share));
+            if (used + w > slots / 2) w = 1;
+        }
+        b->desc_host[k].sync = w > 1 ? b->sync + k : nullptr;
+        if (w > 1) {
+            used += w;
+            ++b->split_lps;
+        }
+        for (int p = 0; p < w; ++p) {
+            q.push_back(k);
+            qp.push_back(w > 1 ? (w << 8) | p : 0);
+        }
+    }
+    b->entries = (int32_t)q.size();
+    LP_HIP_CHECK(hipMemcpy(b->desc, b->desc_host.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice));
+    LP_HIP_CHECK(hipMemcpy(b->order, q.data(), q.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    LP_HIP_CHECK(hipMemcpy(b->parts, qp.data(), qp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    LP_HIP_CHECK(hipMemcpy(b->norder, &b->entries, sizeof(int32_t), hipMemcpyHostToDevice));
+    return LP_OK;
+}
+
 int capture_batch_graph(lp_batch *b) {
+    if (int rc = plan_queue(b)) return rc;
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
@@ -234,11 +320,11 @@ int capture_batch_graph(lp_batch *b) {
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
-    const int grid = std::max(1, std::min<int>(b->count, b->shape.grid_per_cu * b->cus));
+    const int grid = std::max(1, std::min<int>(b->entries, b->shape.grid_per_cu * b->cus));
     LP_HIP_CHECK(hipStreamSynchronize(b->stream));
     LP_HIP_CHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = launch_batch_kernel(b->shape, grid, b->lds, b->stream, b->desc, b->state, b->order, b->norder, b->head,
-                                 INT64_MAX);
+                                 INT64_MAX, b->parts, b->gate_spin);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &graph);
     if (rc) {
@@ -257,6 +343,8 @@ int rebuild_all(lp_batch *b) {
     hipLaunchKernelGGL(k_batch_build, dim3((unsigned)b->ntiles), dim3(256), 0, b->stream, b->desc, b->inputs,
                        b->in_off_dev, b->tile_lp, b->tile_first);
     hipLaunchKernelGGL(k_batch_init_all, dim3((unsigned)b->count), dim3(256), 0, b->stream, b->desc);
+    hipLaunchKernelGGL(k_batch_sync_reset, dim3((unsigned)((b->count + 255) / 256)), dim3(256), 0, b->stream, b->sync,
+                       b->count);
     LP_HIP_CHECK(hipGetLastError());
     LP_HIP_CHECK(hipMemcpyAsync(b->state, b->st_init.data(), b->st_init.size() * sizeof(BatchState),
                                 hipMemcpyHostToDevice, b->stream));
@@ -325,6 +413,7 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         return rc;
     };
     b->count = count;
+    b->gate_spin = o.decide_spin == -1 ? 0u : kPartGateSpin;
     b->m.assign(m, m + count);
     b->n.assign(n, n + count);
     b->cus = device_cus(o.device);
@@ -384,7 +473,11 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
     if (int rc = dmalloc((void **)&b->out_off_dev, count * sizeof(int64_t))) return fail(rc);
     if (int rc = dmalloc((void **)&b->desc, count * sizeof(BatchDesc))) return fail(rc);
     if (int rc = dmalloc((void **)&b->state, count * sizeof(BatchState))) return fail(rc);
-    if (int rc = dmalloc((void **)&b->order, count * sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->order, (size_t)count * kMaxBatchParts * sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->parts, (size_t)count * kMaxBatchParts * sizeof(int32_t))) return fail(rc);
+    if (int rc = dmalloc((void **)&b->sync, (size_t)count * sizeof(BatchSync))) return fail(rc);
+    if (hipMemset(b->sync, 0, (size_t)count * sizeof(BatchSync)) != hipSuccess)
+        return fail(set_error(LP_E_DEVICE, "hipMemset failed"));
     if (int rc = dmalloc((void **)&b->norder, sizeof(int32_t))) return fail(rc);
     if (int rc = dmalloc((void **)&b->head, sizeof(int32_t))) return fail(rc);
 
@@ -406,6 +499,7 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         d.magic = nvec_magic(d.nvec);
         d.pad = 0;
         d.scratch = scr_off[k] >= 0 ? b->scratch + scr_off[k] : nullptr;
+        d.sync = nullptr;
     }
     // inputs, staged through one host buffer
     {
@@ -419,14 +513,9 @@ int lp_batch_create(lp_batch **out, int32_t count, const int32_t *m, const int32
         if (hipMemcpy(b->inputs, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
             return fail(set_error(LP_E_DEVICE, "input copy failed"));
     }
-    std::vector<int32_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
-        return (int64_t)m[a] * (n[a] + 2) > (int64_t)m[c] * (n[c] + 2);
-    });
+    // (the queue, and the descriptors again with their meeting areas, are
+    // uploaded with the plan of the kernel shape)
     if (hipMemcpy(b->desc, b->desc_host.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->norder, &count, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->out_off_dev, b->out_off.data(), count * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
         return fail(set_error(LP_E_DEVICE, "descriptor copy failed"));
 
@@ -541,6 +630,27 @@ int lp_batch_get_shape(const lp_batch *b, int32_t *block, int32_t *unroll, int32
     if (unroll) *unroll = b->shape.unroll;
     if (grid_per_cu) *grid_per_cu = b->shape.grid_per_cu;
     return LP_OK;
+}
+
+int lp_batch_get_split(const lp_batch *b, int32_t *max_parts, int32_t *split_lps, int32_t *queue_entries) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    if (max_parts) *max_parts = b->shape.split;
+    if (split_lps) *split_lps = b->split_lps;
+    if (queue_entries) *queue_entries = b->entries;
+    return LP_OK;
+}
+
+int lp_batch_set_shape(lp_batch *b, int32_t block, int32_t unroll, int32_t grid_per_cu, int32_t split) {
+    if (!b) return set_error(LP_E_INVAL, "NULL batch");
+    for (int i = 0; i < kNumBatchShapes; ++i) {
+        const BatchShape &sh = kBatchShapes[i];
+        if (sh.block == block && sh.unroll == unroll && sh.grid_per_cu == grid_per_cu && sh.split == split) {
+            DeviceGuard g(b->device);
+            b->shape = sh;
+            return capture_batch_graph(b);
+        }
+    }
+    return set_error(LP_E_INVAL, "no batch kernel shape with that block, unroll, grid_per_cu and split");
 }
 
 int lp_batch_autotune(lp_batch *b, const char *cache_path, int32_t trials, double *best_ms) {

@@ -8,11 +8,13 @@
 namespace lpgpu {
 
 // Shape of the persistent batched kernel: threads per workgroup, update
-// unroll (row-pair items in flight per thread) and workgroups per CU.
+// unroll (row-pair items in flight per thread), workgroups per CU, and the
+// most parts a large LP is split into (1: every LP on one workgroup).
 struct BatchShape {
     int block;
     int unroll;
     int grid_per_cu;
+    int split = 1;
 };
 
 extern const BatchShape kBatchShapes[];
@@ -31,7 +33,10 @@ int set_batch_lds_limit(size_t lds);
 // Enqueues {queue reset, persistent kernel} on `stream`.
 int launch_batch_kernel(const BatchShape &sh, int grid, size_t lds, hipStream_t stream, const BatchDesc *desc,
                         BatchState *state, const int32_t *order, const int32_t *norder, int32_t *head,
-                        int64_t budget);
+                        int64_t budget, const int32_t *parts = nullptr, uint32_t gate_spin = kPartGateSpin);
+// Workgroups of the shape's kernel instance resident per CU with `lds` bytes
+// of dynamic LDS (0 if unknown).
+int batch_blocks_per_cu(const BatchShape &sh, size_t lds);
 std::string batch_bucket_key(int32_t count, int32_t mmax, int32_t nmax);
 bool cache_lookup(const char *path, const std::string &key, BatchShape *out);
 void cache_store(const char *path, const std::string &key, const BatchShape &sh, double ms);

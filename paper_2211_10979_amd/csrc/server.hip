@@ -658,6 +658,7 @@ int lp_server_create(lp_server **out, size_t hbm_budget_bytes, int32_t max_slots
             }
         if (!found) return fail(set_error(LP_E_INVAL, "no batch kernel shape with that block / unroll"));
     }
+    s->shape.split = 1;  // the server's LPs come and go: none is split
     s->grid = std::max(1, s->shape.grid_per_cu * device_cus(o.device));
     // the captured graph: queue reset + persistent kernel over the order list
     if (hipStreamBeginCapture(s->sched, hipStreamCaptureModeThreadLocal) != hipSuccess)

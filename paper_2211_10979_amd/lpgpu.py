@@ -180,6 +180,8 @@ SIGNATURES = {
     "lp_batch_solve_ms": (ctypes.c_double, [_P]),
     "lp_batch_reset": (ctypes.c_int, [_P]),
     "lp_batch_get_shape": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "lp_batch_get_split": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "lp_batch_set_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "lp_batch_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _D]),
     "lp_batch_destroy": (None, [_P]),
     "lp_server_create": (ctypes.c_int, [_PP, ctypes.c_size_t, ctypes.c_int32, _OPT]),
@@ -496,6 +498,16 @@ def lp_batch_get_shape(h):
     b, u, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(library().lp_batch_get_shape(h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(g)), "lp_batch_get_shape")
     return dict(block=b.value, unroll=u.value, grid_per_cu=g.value)
+
+
+def lp_batch_get_split(h):
+    w, k, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(library().lp_batch_get_split(h, ctypes.byref(w), ctypes.byref(k), ctypes.byref(e)), "lp_batch_get_split")
+    return dict(max_parts=w.value, split_lps=k.value, queue_entries=e.value)
+
+
+def lp_batch_set_shape(h, block, unroll, grid_per_cu, split=1):
+    _check(library().lp_batch_set_shape(h, int(block), int(unroll), int(grid_per_cu), int(split)), "lp_batch_set_shape")
 
 
 def lp_batch_autotune(h, cache_path=None, trials=2) -> float:

@@ -175,3 +175,95 @@ def test_lp_beyond_the_lds_limit_uses_a_global_work_area():
         check_batch(h, lps)
     finally:
         lpgpu.lp_batch_destroy(h)
+
+
+# Shapes that split large LPs over several workgroups (block, unroll,
+# workgroups per CU, most parts per LP).
+SPLIT_SHAPES = [(256, 2, 2, 8), (512, 2, 2, 4), (512, 2, 2, 8), (1024, 2, 1, 4), (1024, 2, 1, 8), (1024, 4, 1, 4),
+                (1024, 4, 1, 8)]
+
+
+def heavy_mix(seed):
+    """A few large LPs among many small ones: the large ones get split."""
+    big = [lpgen.dense_lp(seed, m, n, k=k) for k, (m, n) in enumerate([(480, 500), (450, 470), (400, 512), (300, 350)])]
+    return [(lp.A, lp.b, lp.c) for lp in big] + mixed_lps(seed + 1, 60, 10, 120)
+
+
+@pytest.mark.parametrize("shape", SPLIT_SHAPES)
+def test_split_lps_follow_the_oracle(shape):
+    """Each part of a split LP rewrites a share of its columns and the parts
+    meet twice per pivot: pivots, x, y as the oracle's, again after a reset."""
+    lps = heavy_mix(29)
+    say(f"split shape {shape}")
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_set_shape(h, *shape)
+        sp = lpgpu.lp_batch_get_split(h)
+        assert sp["max_parts"] == shape[3] and sp["split_lps"] >= 4, sp
+        assert sp["queue_entries"] >= len(lps) + 4, sp
+        lpgpu.lp_batch_solve(h)
+        check_batch(h, lps)
+        lpgpu.lp_batch_reset(h)
+        lpgpu.lp_batch_solve(h)
+        check_batch(h, lps)
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_split_batch_equals_whole_batch_bitwise():
+    """The 512-LP workload with its largest LPs split gives the bits of the
+    batch without splitting, LP by LP."""
+    sizes = lpgen.batch_sizes(lpgen.BATCH_SEED, 512)
+    lps = [(lp.A, lp.b, lp.c) for lp in (lpgen.dense_lp(lpgen.BATCH_SEED, m, n, k=k)
+                                         for k, (m, n) in enumerate(sizes))]
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        lpgpu.lp_batch_set_shape(h, 1024, 2, 1, 1)
+        lpgpu.lp_batch_solve(h)
+        whole = [lpgpu.lp_batch_get_solution(h, k, *A.shape) for k, (A, _, _) in enumerate(lps)]
+        logs = [lpgpu.lp_batch_get_pivots(h, k) for k in range(len(lps))]
+        for shape in ((1024, 2, 1, 8), (512, 2, 2, 4)):
+            say(f"batch of 512, split shape {shape}")
+            lpgpu.lp_batch_set_shape(h, *shape)
+            assert lpgpu.lp_batch_get_split(h)["split_lps"] > 0
+            lpgpu.lp_batch_reset(h)
+            lpgpu.lp_batch_solve(h)
+            for k, (A, _, _) in enumerate(lps):
+                res, x, y = lpgpu.lp_batch_get_solution(h, k, *A.shape)
+                rows, cols = lpgpu.lp_batch_get_pivots(h, k)
+                assert res["status"] == whole[k][0]["status"] and res["pivots"] == whole[k][0]["pivots"], k
+                assert rows.tolist() == logs[k][0].tolist() and cols.tolist() == logs[k][1].tolist(), k
+                assert np.array_equal(x.view(np.uint64), whole[k][1].view(np.uint64)), k
+                assert np.array_equal(y.view(np.uint64), whole[k][2].view(np.uint64)), k
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_split_gate_closed_runs_the_lp_whole():
+    """decide_spin = -1 closes every split LP's check-in gate at once: the
+    workgroup that closed it runs the LP alone, the other parts leave."""
+    lps = heavy_mix(31)
+    h = lpgpu.lp_batch_create(lps, decide_spin=-1)
+    try:
+        lpgpu.lp_batch_set_shape(h, 1024, 2, 1, 8)
+        assert lpgpu.lp_batch_get_split(h)["split_lps"] >= 4
+        for _ in range(2):  # the gates reopen for the next solve
+            lpgpu.lp_batch_solve(h)
+            check_batch(h, lps)
+            lpgpu.lp_batch_reset(h)
+    finally:
+        lpgpu.lp_batch_destroy(h)
+
+
+def test_set_shape_rejects_unknown_shapes():
+    lps = mixed_lps(33, 4)
+    h = lpgpu.lp_batch_create(lps)
+    try:
+        with pytest.raises(lpgpu.LPError):
+            lpgpu.lp_batch_set_shape(h, 1024, 2, 1, 3)
+        with pytest.raises(lpgpu.LPError):
+            lpgpu.lp_batch_set_shape(h, 768, 2, 1, 1)
+        lpgpu.lp_batch_set_shape(h, 256, 1, 2, 1)
+        assert lpgpu.lp_batch_get_split(h) == dict(max_parts=1, split_lps=0, queue_entries=len(lps))
+    finally:
+        lpgpu.lp_batch_destroy(h)
