@@ -186,7 +186,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDesc &d, BatchState *
             L[t] = j;
             nz += Rt != 0.0;
         }
-        for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
+        nz = wave_sum_i32(nz);
         if ((tid & 63) == 0) sint[tid >> 6] = nz;
         __syncthreads();  // F, R, L ready; every read of cols/pos/basis done
         if (tid == 0) {
@@ -494,7 +494,7 @@ __device__ __forceinline__ void batch_solve_part(const BatchDesc &d, BatchState 
             L[c] = j;
             nz += Rt != 0.0;
         }
-        for (int off = 32; off >= 1; off >>= 1) nz += __shfl_xor(nz, off, 64);
+        nz = wave_sum_i32(nz);
         if ((tid & 63) == 0) sint[tid >> 6] = nz;
         __syncthreads();  // F, R, L ready; this part's reads of the shared columns and lists done
         if (tid == 0) {

@@ -81,16 +81,71 @@ __device__ __forceinline__ bool step2_bad(double a, double rhs) {
 // An empty slot: +inf with the largest index loses to every real candidate.
 constexpr int32_t kNoIndex = 0x7fffffff;
 
-__device__ __forceinline__ void wave_argmin(double &v, int32_t &i) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int32_t oi = __shfl_xor(i, off, 64);
-        if (lex_less(ov, oi, v, i)) {
-            v = ov;
-            i = oi;
-        }
+// Cross-lane exchanges of a wave (every lane active): DPP within rows of 16
+// lanes, and the gfx950 lane swaps across rows (v_permlane16_swap,
+// v_permlane32_swap: VALU exchanges, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    return __hiloint2double(dpp_i32<CTRL>(__double2hiint(x)), dpp_i32<CTRL>(__double2loint(x)));
+}
+
+// x of lane l ^ 16 (W = 16) or l ^ 32 (W = 32): the swap of a register with
+// itself leaves, in the first result, rows 0 and 2 (lanes 0-31 for W = 32)
+// in their place and their copies in rows 1 and 3 (lanes 32-63), and in the
+// second result rows 1 and 3 (lanes 32-63) with their copies in rows 0 and 2
+// (lanes 0-31).
+template <int W>
+__device__ __forceinline__ int32_t swap_i32(int32_t x) {
+    const bool hi = (threadIdx.x & W) != 0;
+    if constexpr (W == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return hi ? r[0] : r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return hi ? r[0] : r[1];
     }
+}
+
+template <int W>
+__device__ __forceinline__ double swap_f64(double x) {
+    return __hiloint2double(swap_i32<W>(__double2hiint(x)), swap_i32<W>(__double2loint(x)));
+}
+
+// Keeps the smaller of (v, i) and (ov, oi) under lex_less.
+__device__ __forceinline__ void argmin_take(double &v, int32_t &i, double ov, int32_t oi) {
+    const bool take = lex_less(ov, oi, v, i);
+    v = take ? ov : v;
+    i = take ? oi : i;
+}
+
+// Wave argmin of (v, i); every lane gets the winner. Within a row of 16
+// lanes: the quad permutations [1,0,3,2] and [2,3,0,1], the half-row mirror
+// and the row mirror; then rows 0 <-> 1, 2 <-> 3 and lanes 0-31 <-> 32-63.
+// The argmin is unique under lex_less, so the order of the steps does not
+// change the result. Call with every lane of the wave active.
+__device__ __forceinline__ void wave_argmin(double &v, int32_t &i) {
+    argmin_take(v, i, dpp_f64<0xB1>(v), dpp_i32<0xB1>(i));
+    argmin_take(v, i, dpp_f64<0x4E>(v), dpp_i32<0x4E>(i));
+    argmin_take(v, i, dpp_f64<0x141>(v), dpp_i32<0x141>(i));
+    argmin_take(v, i, dpp_f64<0x140>(v), dpp_i32<0x140>(i));
+    argmin_take(v, i, swap_f64<16>(v), swap_i32<16>(i));
+    argmin_take(v, i, swap_f64<32>(v), swap_i32<32>(i));
+}
+
+// Sum of x over a wave (every lane active); every lane gets it.
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t x) {
+    x += dpp_i32<0xB1>(x);
+    x += dpp_i32<0x4E>(x);
+    x += dpp_i32<0x141>(x);
+    x += dpp_i32<0x140>(x);
+    x += swap_i32<16>(x);
+    x += swap_i32<32>(x);
+    return x;
 }
 
 // Block-wide lexicographic argmin; every thread gets the result. `sv`/`si`

@@ -234,19 +234,21 @@ struct GRatio {
     double rb;  // k_gdecide: the RHS entry of row r after the earlier pivots of the group
 };
 
-// Lexicographic argmin that carries an int payload along with the winner.
+// Lexicographic argmin that carries an int payload along with the winner:
+// the steps of wave_argmin (every lane active).
 __device__ __forceinline__ void wave_argmin_t(double &v, int32_t &i, int32_t &t) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int32_t oi = __shfl_xor(i, off, 64);
-        const int32_t ot = __shfl_xor(t, off, 64);
-        if (lex_less(ov, oi, v, i)) {
-            v = ov;
-            i = oi;
-            t = ot;
-        }
-    }
+    auto take = [&](double ov, int32_t oi, int32_t ot) {
+        const bool tk = lex_less(ov, oi, v, i);
+        v = tk ? ov : v;
+        i = tk ? oi : i;
+        t = tk ? ot : t;
+    };
+    take(dpp_f64<0xB1>(v), dpp_i32<0xB1>(i), dpp_i32<0xB1>(t));
+    take(dpp_f64<0x4E>(v), dpp_i32<0x4E>(i), dpp_i32<0x4E>(t));
+    take(dpp_f64<0x141>(v), dpp_i32<0x141>(i), dpp_i32<0x141>(t));
+    take(dpp_f64<0x140>(v), dpp_i32<0x140>(i), dpp_i32<0x140>(t));
+    take(swap_f64<16>(v), swap_i32<16>(i), swap_i32<16>(t));
+    take(swap_f64<32>(v), swap_i32<32>(i), swap_i32<32>(t));
 }
 
 __device__ __forceinline__ void block_argmin_t(double &v, int32_t &i, int32_t &t, double *sv, int32_t *si,
@@ -600,16 +602,6 @@ __global__ __launch_bounds__(256) void k_gstage(const double *__restrict__ T, in
 // under the (value, index) order of lex_less, so the result does not depend
 // on the order of the reduction: every wave that reduces the same candidates
 // gets the same winner.
-template <int CTRL>
-__device__ __forceinline__ int32_t dpp_i32(int32_t x) {
-    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-    return __hiloint2double(dpp_i32<CTRL>(__double2hiint(x)), dpp_i32<CTRL>(__double2loint(x)));
-}
-
 __device__ __forceinline__ double readlane_f64(double x, int32_t lane) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
                             __builtin_amdgcn_readlane(__double2loint(x), lane));
@@ -628,27 +620,9 @@ __device__ __forceinline__ void dpp_step(double &v, int32_t &i, int32_t &t) {
     argmin_take(v, i, t, dpp_f64<CTRL>(v), dpp_i32<CTRL>(i), dpp_i32<CTRL>(t));
 }
 
-// x of lane l ^ 16 (W = 16) or l ^ 32 (W = 32), with every lane active: the
-// swap of a register with itself leaves, in the first result, rows 0 and 2
-// (lanes 0-31 for W = 32) in their place and their copies in rows 1 and 3
-// (lanes 32-63), and in the second result rows 1 and 3 (lanes 32-63) with
-// their copies in rows 0 and 2 (lanes 0-31).
-template <int W>
-__device__ __forceinline__ int32_t swap_i32(int32_t x) {
-    const bool hi = (threadIdx.x & W) != 0;
-    if constexpr (W == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-        return hi ? r[0] : r[1];
-    } else {
-        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-        return hi ? r[0] : r[1];
-    }
-}
-
 template <int W>
 __device__ __forceinline__ void swap_step(double &v, int32_t &i, int32_t &t) {
-    const double ov = __hiloint2double(swap_i32<W>(__double2hiint(v)), swap_i32<W>(__double2loint(v)));
-    argmin_take(v, i, t, ov, swap_i32<W>(i), swap_i32<W>(t));
+    argmin_take(v, i, t, swap_f64<W>(v), swap_i32<W>(i), swap_i32<W>(t));
 }
 
 // wave argmin of (v, i) carrying t; every lane gets the winner
