@@ -311,6 +311,7 @@ int plan_queue(lp_batch *b) {
 }
 
 int capture_batch_graph(lp_batch *b) {
+    LP_HIP_CHECK(hipStreamSynchronize(b->stream));  // (nothing in flight reads the queue being replaced)
     if (int rc = plan_queue(b)) return rc;
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);

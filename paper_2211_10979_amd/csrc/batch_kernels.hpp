@@ -46,7 +46,7 @@ struct BatchDesc {
 // p*S .. p*S+S-1 (S = ceil((n+2)/W)). Per pivot they meet twice: after the
 // Step 1 partials of their slots (exchanged with the meeting, each part then
 // reduces all W) and after every part has read what the pivot's other parts
-// rewrite (column q, the RHS, the list, the basis). Steps 2 and the Step 3
+// rewrite (column q, the RHS, the list, the basis). Step 2 and the Step 3
 // inputs run in every part (the same values, so the same pivot). A meeting
 // carries its data like the decision kernel's grid barrier: per part one
 // 128-byte record line of 64-bit words, 32 data bits and a flag (the LP's
