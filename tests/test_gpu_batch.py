@@ -267,3 +267,36 @@ def test_set_shape_rejects_unknown_shapes():
         assert lpgpu.lp_batch_get_split(h) == dict(max_parts=1, split_lps=0, queue_entries=len(lps))
     finally:
         lpgpu.lp_batch_destroy(h)
+
+
+def test_split_lps_stop_like_the_oracle():
+    """Split LPs that end unbounded, at the iteration cap, or at once (no
+    pivot), beside whole ones: status, pivots and log as the oracle's."""
+    rng = np.random.default_rng(37)
+    lps = []
+    for k, (m, n) in enumerate([(460, 500), (430, 480), (500, 420), (380, 450)]):
+        A = rng.integers(1, 10, size=(m, n)).astype(float)
+        if k % 2 == 0:
+            A *= rng.choice([-1.0, 1.0], size=(m, n), p=[0.4, 0.6])  # often unbounded
+        b = rng.integers(1, 10, size=m).astype(float)
+        c = rng.integers(1, 10, size=n).astype(float)
+        if k == 3:
+            c = -c  # optimal at the origin: no pivot
+        lps.append((A, b, c))
+    lps += mixed_lps(39, 40, 10, 100)
+    for cap in (None, 3):
+        kw = {} if cap is None else dict(max_pivots=cap)
+        say(f"split LPs, stops, cap {cap}")
+        h = lpgpu.lp_batch_create(lps, **kw)
+        try:
+            lpgpu.lp_batch_set_shape(h, 1024, 2, 1, 8)
+            assert lpgpu.lp_batch_get_split(h)["split_lps"] >= 3
+            lpgpu.lp_batch_solve(h)
+            for k, (A, b, c) in enumerate(lps):
+                res, x, y = lpgpu.lp_batch_get_solution(h, k, *A.shape)
+                rows, cols = lpgpu.lp_batch_get_pivots(h, k)
+                o = oracle.solve(A, b, c, **kw)
+                assert res["status"] == o["status"] and res["pivots"] == o["pivots"], (k, res, o["status"])
+                assert rows.tolist() == o["rows"].tolist() and cols.tolist() == o["cols"].tolist(), k
+        finally:
+            lpgpu.lp_batch_destroy(h)
