@@ -1343,20 +1343,40 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  int32_t *__restrict__ pos, int32_t *__restrict__ basis,
                                                  int32_t *__restrict__ log_r, int32_t *__restrict__ log_q,
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
-                                                 uint32_t spin_limit, uint32_t gate_spin, double *__restrict__ PV) {
+                                                 uint32_t spin_limit, uint32_t gate_spin, double *__restrict__ PV,
+                                                 unsigned char *pub, int32_t pub_words, uint32_t *pub_seq_at,
+                                                 uint32_t pub_seq) {
     decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r,
                                log_q, rparts, gsync, spin_limit, gate_spin, PV);
     // every workgroup leaves through here; the last one advances the epoch,
     // so the next launch's records carry a new flag, and reopens the gate
+    __shared__ int32_t s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(&gsync->exits, 1u) == (uint32_t)gridDim.x - 1) {
+        const bool last = atomicAdd(&gsync->exits, 1u) == (uint32_t)gridDim.x - 1;
+        if (last) {
             gsync->exits = 0;
             gsync->count = 0;  // the gate opens for the next launch
             gsync->epoch = gsync->epoch + 1u;
             __threadfence();
         }
+        s_last = last;
+    }
+    __syncthreads();
+    // The last workgroup also hands the solver state and the work counters
+    // to the host: every workgroup's writes to them came before its exit
+    // count (fences), the copy goes to mapped host memory, then the sequence
+    // word after a system-scope fence. The host reads them there while the
+    // update pass runs, with no copy and no event in the stream.
+    if (pub && s_last) {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(st);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(pub);
+        for (int k = threadIdx.x; k < pub_words; k += BD)
+            dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(pub_seq_at, pub_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1598,12 +1618,27 @@ __global__ __launch_bounds__(B) void k_gupdate_pure(double *__restrict__ T, int6
 // unit vectors when they left the basis).
 constexpr int kFirstRows = 32;  // tile rows (tableau rows)
 constexpr int kFirstTile = 64;  // tile columns
+constexpr int kFirstTailC = 1;  // slots per workgroup of the tail (few registers: the tile's F stays the largest)
 
+// Workgroups from `tiles` on take the tail instead: the pure pass over the
+// slots from n on (the RHS and the columns appended during the group),
+// kFirstTailC slots by 512 rows each, in the same launch.
 template <int KF>
 __global__ __launch_bounds__(256) void k_gfirst(double *__restrict__ T, int64_t ld, int32_t m, int32_t n, int64_t Lg,
                                                 int32_t ntx, const double *__restrict__ A, const double *__restrict__ cv,
                                                 const double *__restrict__ Rk, const double *__restrict__ Fk,
-                                                const GroupState *__restrict__ gs) {
+                                                const GroupState *__restrict__ gs, int32_t tiles, int32_t rowchunks,
+                                                const int32_t *__restrict__ cols, double *__restrict__ dump) {
+    if ((int32_t)blockIdx.x >= tiles) {
+        if (gs->kdone == 0 || gs->stalled) return;
+        const int32_t Lv = n + 1 + gs->napp;
+        const int32_t b = (int32_t)blockIdx.x - tiles;
+        const int32_t rc = b % rowchunks, g = b / rowchunks;
+        const int32_t c0 = n + g * kFirstTailC;
+        if (c0 >= Lv) return;
+        pure_tile<256, kFirstTailC, KF>(T, ld, m, Lg, Lv, rc, c0, cols, Rk, Fk, gs, dump);
+        return;
+    }
     constexpr int TR = kFirstRows, TC = kFirstTile;
     constexpr int NP = TR / 2;          // row pairs of a tile
     constexpr int CG = 256 / NP;        // column groups of the write phase

@@ -161,7 +161,8 @@ template <int BD, bool First, int KM>
 void decide_bd(const FusedArgs &a, const double *A, const double *c, hipStream_t s) {
     hipLaunchKernelGGL((k_gdecide<BD, First, KM>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n,
                        A, c, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis,
-                       a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin, a.gate_spin, a.PV);
+                       a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin, a.gate_spin, a.PV, a.pub, a.pub_words,
+                       a.pub_seq_at, a.pub_seq);
 }
 
 // the instance for the group size (its KF pivot slots kept in registers)
@@ -277,24 +278,19 @@ void first_kf(const FusedArgs &a, const double *A, const double *c, hipStream_t 
     const int64_t Lg = (int64_t)a.n + 1 + a.K;
     const int32_t ntx = (a.n + kFirstTile - 1) / kFirstTile;
     const int32_t nty = (int32_t)((a.ld + kFirstRows - 1) / kFirstRows);
-    const unsigned tiles = (unsigned)((int64_t)ntx * nty);
-    // the tiles of the structural columns, then the pure pass over slots n ..
-    // n+K (the RHS and the appended columns): 256 threads by 8 slots
+    const int32_t tiles = (int32_t)((int64_t)ntx * nty);
+    // the tiles of the structural columns, then in the same launch the pure
+    // pass over slots n .. n+K (the RHS and the appended columns)
     const int32_t rowchunks = (int32_t)((((int64_t)a.m + 2) / 2 + 255) / 256);  // row pairs
-    const unsigned pure = (unsigned)((int64_t)rowchunks * ((1 + a.K + 7) / 8));
-    if (e0) {
-        hipExtLaunchKernelGGL((k_gfirst<KF>), dim3(tiles), dim3(256), 0, s, e0, nullptr, 0, a.T, a.ld, a.m, a.n, Lg,
-                              ntx, A, c, (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
-        hipExtLaunchKernelGGL((k_gupdate_pure<256, 8, KF>), dim3(pure), dim3(256), 0, s, nullptr, e1, 0, a.T, a.ld,
-                              a.m, a.n, Lg, rowchunks, (const int32_t *)a.cols, (const double *)a.Rk,
-                              (const double *)a.Fk, (const GroupState *)a.gs, a.dump, a.n);
-    } else {
-        hipLaunchKernelGGL((k_gfirst<KF>), dim3(tiles), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, ntx, A, c,
-                           (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs);
-        hipLaunchKernelGGL((k_gupdate_pure<256, 8, KF>), dim3(pure), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg,
-                           rowchunks, (const int32_t *)a.cols, (const double *)a.Rk, (const double *)a.Fk,
-                           (const GroupState *)a.gs, a.dump, a.n);
-    }
+    const unsigned grid = (unsigned)(tiles + (int64_t)rowchunks * ((1 + a.K + kFirstTailC - 1) / kFirstTailC));
+    if (e0 || e1)
+        hipExtLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, e0, e1, 0, a.T, a.ld, a.m, a.n, Lg, ntx, A,
+                              c, (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs, tiles,
+                              rowchunks, (const int32_t *)a.cols, a.dump);
+    else
+        hipLaunchKernelGGL((k_gfirst<KF>), dim3(grid), dim3(256), 0, s, a.T, a.ld, a.m, a.n, Lg, ntx, A, c,
+                           (const double *)a.Rk, (const double *)a.Fk, (const GroupState *)a.gs, tiles, rowchunks,
+                           (const int32_t *)a.cols, a.dump);
 }
 
 }  // namespace

@@ -38,6 +38,14 @@ struct FusedArgs {
     uint32_t gate_spin;  // polls before its check-in gate closes
     double *dump;       // a zero column the pure update pass writes for slots past the list
     double *PV;         // the group's pivot rows after the group, K rows of n + 1 + K doubles
+    // The one-launch decision kernel's last workgroup copies the solver state
+    // and the work counters (pub_words 8-byte words from st) to `pub`, host
+    // memory mapped into the device, then stores pub_seq at pub_seq_at
+    // (NULL pub: no copy).
+    unsigned char *pub;
+    uint32_t pub_seq;
+    int32_t pub_words;
+    uint32_t *pub_seq_at;
 };
 
 // Update instances exist for groups of up to 2, 4, 8, 12, 16, 24, 32 and

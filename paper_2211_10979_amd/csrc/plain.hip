@@ -104,7 +104,6 @@ struct lp_ctx {
     double *Rl = nullptr;     // normalised pivot row by list position (n+2)
     DevState *host_st = nullptr;  // pinned: two slots for the pipelined status read-back, one for the end
     unsigned long long *host_cols = nullptr;  // pinned: the work counters at the end of the last solve
-    unsigned char *host_blk = nullptr;        // pinned: two copies of the state block (status read-back 2)
     double *host_out = nullptr;               // pinned: extraction output
     bool counters_cached = false;             // host_st[2] and host_cols hold the device's current values
     bool solution_cached = false;             // host_out holds the extraction of the current tableau
@@ -157,6 +156,12 @@ struct lp_ctx {
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ev_upd[2];  // timing mode: before/after each update kernel of a chunk
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_slot[2] = {nullptr, nullptr};
+    // status read-back 2: host memory mapped into the device, two slots of
+    // kPubStride bytes, each the solver state and the work counters as the
+    // decision kernel leaves them, then a sequence word (pub_seq: the last
+    // one asked for)
+    unsigned char *pub = nullptr;
+    uint32_t pub_seq = 0;
     double update_ms = 0.0;
     int64_t update_launches = 0;
     double update_ms_applied = 0.0;  // part of update_ms in launches that applied pivots
@@ -195,7 +200,7 @@ void free_ctx(lp_ctx *h) {
     if (h->aux) (void)hipFree(h->aux);
     if (h->host_st) (void)hipHostFree(h->host_st);
     if (h->host_cols) (void)hipHostFree(h->host_cols);
-    if (h->host_blk) (void)hipHostFree(h->host_blk);
+    if (h->pub) (void)hipHostFree(h->pub);
     if (h->host_out) (void)hipHostFree(h->host_out);
     if (h->ev_start) (void)hipEventDestroy(h->ev_start);
     if (h->ev_stop) (void)hipEventDestroy(h->ev_stop);
@@ -238,6 +243,9 @@ int validate_opts(const Options &o) {
 // The state block: DevState, then the work counters at a 64-byte offset.
 constexpr size_t kCountersAt = (sizeof(DevState) + 63) / 64 * 64;
 constexpr size_t kStateBlock = kCountersAt + 4 * sizeof(unsigned long long);
+// a slot of the mapped block the decision kernel publishes to: the state
+// block, then the sequence word
+constexpr size_t kPubStride = (kStateBlock + sizeof(uint64_t) + 127) / 128 * 128;
 
 // status_readback 0 reads the state right after the decisions (2) from a
 // tableau of this size on: its update pass then outlasts the host's reaction
@@ -469,7 +477,6 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_blk, 2 * kStateBlock, hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&h->host_out, ((size_t)n + m + 1) * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
@@ -621,7 +628,7 @@ void launch_update(lp_ctx *h, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) 
 }
 
 FusedArgs fused_args(lp_ctx *h) {
-    FusedArgs a;
+    FusedArgs a{};  // (pub NULL: the decision kernel copies nothing to the host)
     a.T = h->T;
     a.ld = h->ld;
     a.m = h->m;
@@ -795,7 +802,32 @@ void set_stop(lp_ctx *h, int64_t stop_at) {
 // Solver-state read-back right after each group's decisions: the next
 // group is launched while the current group's update pass runs, so no group
 // is queued after the solve ends.
+// Waits until the decision kernel has published the state in `slot` with
+// sequence `seq`: polls the mapped word for up to 20 ms, then waits for the
+// stream (the kernel has then ended) and checks once more.
+int wait_pub(lp_ctx *h, int slot, uint32_t seq) {
+    const volatile uint32_t *w = reinterpret_cast<const volatile uint32_t *>(h->pub + slot * kPubStride + kStateBlock);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t k = 0; *w != seq; ++k) {
+        if ((k & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+            LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+            if (*w != seq) return set_error(LP_E_DEVICE, "the decision kernel's state did not arrive");
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return LP_OK;
+}
+
 int run_until_early(lp_ctx *h, int64_t stop_at) {
+    if (!h->pub) {  // (allocated on first use)
+        if (hipHostMalloc((void **)&h->pub, 2 * kPubStride, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(LP_E_NOMEM, "hipHostMalloc failed");
+        }
+        std::memset(h->pub, 0, 2 * kPubStride);
+    }
     int64_t last = h->pivots_host;  // pivots before the group being harvested
     set_stop(h, stop_at);
     LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
@@ -803,9 +835,17 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
     int64_t advanced = 0;  // pivots of the group in the other slot, harvested once its pass is done
     bool have_prev = false;
     for (;;) {
-        // the group's decisions, the state they leave read back, then its
-        // update pass (queued at once: the device never waits for the host)
-        const FusedArgs a = fused_args(h);
+        // the group's decisions, which hand the state they leave to the host
+        // (published to mapped memory by the kernel's last workgroup), then
+        // its update pass (queued at once: the device never waits for the
+        // host)
+        FusedArgs a = fused_args(h);
+        const uint32_t seq = ++h->pub_seq;
+        unsigned char *blk = h->pub + slot * kPubStride;  // the state and the work counters
+        a.pub = blk;
+        a.pub_words = (int32_t)(kStateBlock / sizeof(uint64_t));
+        a.pub_seq_at = reinterpret_cast<uint32_t *>(blk + kStateBlock);
+        a.pub_seq = seq;
         const bool first = h->pending;
         h->first_slot[slot] = first;
         if (first) {
@@ -815,9 +855,6 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         } else {
             launch_fused_decide(a, h->stream);
         }
-        unsigned char *blk = h->host_blk + slot * kStateBlock;  // the state and the work counters
-        LP_HIP_CHECK(hipMemcpyAsync(blk, h->st, kStateBlock, hipMemcpyDeviceToHost, h->stream));
-        LP_HIP_CHECK(hipEventRecord(h->ev_slot[slot], h->stream));
         if (first) {
             launch_first_update(a, h->pend_A, h->pend_c, h->stream, h->timing ? h->ev_first[0] : nullptr,
                                 h->timing ? h->ev_first[1] : nullptr);
@@ -827,7 +864,7 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
                                 h->timing ? h->ev_upd[slot][1] : nullptr);
         }
         LP_HIP_CHECK(hipGetLastError());
-        LP_HIP_CHECK(hipEventSynchronize(h->ev_slot[slot]));
+        if (int rc = wait_pub(h, slot, seq)) return rc;
         std::memcpy(&h->host_st[slot], blk, sizeof(DevState));
         const DevState s = h->host_st[slot];
         // the previous group's update pass ran before these decisions
@@ -846,7 +883,7 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
     // final: only the decision kernels write them (not the update pass, the
     // pivot-row stores or the extraction)
     h->host_st[2] = h->host_st[slot];
-    std::memcpy(h->host_cols, h->host_blk + slot * kStateBlock + kCountersAt, 4 * sizeof(unsigned long long));
+    std::memcpy(h->host_cols, h->pub + slot * kPubStride + kCountersAt, 4 * sizeof(unsigned long long));
     const DevState s = h->host_st[2];
     h->counters_cached = true;
     h->solution_cached = true;
@@ -1605,7 +1642,6 @@ int lane_create(Lane **out, int device, hipStream_t stream, const Options &opt, 
     DeviceGuard g(device);
     hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_blk, 2 * kStateBlock, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&h->host_out, ((size_t)max_n + max_m + 1) * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreate(&h->ev_start);
