@@ -219,6 +219,34 @@ def bench_plain(args, lpgpu, lpgen, torch):
                                achieved_applied=round(alg / max(upd_ms_applied, 1e-9) / 1e6, 1),
                                pivots=upd_piv, alg_bytes_per_pivot=alg / max(upd_piv, 1),
                                columns_per_pivot=upd_cols / max(upd_piv, 1))
+    # the library's default path (no per-launch timing events, which each
+    # delay the next dispatch by a few microseconds): the same steps, timed
+    # on their own
+    if args.time_kernels:
+        h2 = lpgpu.lp_create_device(m, n, dA, db, dc, time_kernels=0, chunk_pivots=args.chunk,
+                                    cols_per_block=args.cols_per_block, rows_per_thread=args.rows_per_thread,
+                                    fuse_pivots=args.fuse)
+        try:
+            def step2():
+                lpgpu.lp_reload_device(h2, dA, db, dc)
+                lpgpu.lp_solve(h2)
+                return lpgpu.lp_get_solution(h2)
+
+            for _ in range(args.warmup):
+                step2()
+            torch.cuda.synchronize()
+            piv2 = 0
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                r2, _, _ = step2()
+                piv2 += r2["pivots"]
+            torch.cuda.synchronize()
+            el2 = time.perf_counter() - t0
+            assert r2["pivots"] == res["pivots"] and r2["objective"] == res["objective"]
+            out["default_path"] = dict(pivots_per_s=round(piv2 / el2, 1), ms_per_step=round(1000.0 * el2 / args.steps, 4),
+                                       note="time_kernels 0: no timing events between the kernels")
+        finally:
+            lpgpu.lp_destroy(h2)
     if first_launches:
         out["first_pass"] = dict(kernel=f"k_gfirst_rl<{kf}>" if kf >= 32 else f"k_gfirst<{kf}>", launches=first_launches,
                                  avg_launch_us=round(first_ms / first_launches * 1e3, 2),
