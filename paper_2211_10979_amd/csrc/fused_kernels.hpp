@@ -1345,7 +1345,11 @@ __global__ __launch_bounds__(BD) void k_gdecide(double *__restrict__ T, int64_t 
                                                  GRatio *__restrict__ rparts, GridSync *__restrict__ gsync,
                                                  uint32_t spin_limit, uint32_t gate_spin, double *__restrict__ PV,
                                                  unsigned char *pub, int32_t pub_words, uint32_t *pub_seq_at,
-                                                 uint32_t pub_seq) {
+                                                 uint32_t pub_seq, unsigned long long *t_mark) {
+    // the start of a solve, by the device's constant-rate clock (instead of
+    // an event in the stream, which would delay this dispatch)
+    if (t_mark && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(t_mark, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     decide_body<BD, First, KM>(T, ld, m, n, A, cv, K, KF, sparts, cols_done, st, gs, Fk, Rk, cols, pos, basis, log_r,
                                log_q, rparts, gsync, spin_limit, gate_spin, PV);
     // every workgroup leaves through here; the last one advances the epoch,

@@ -162,7 +162,7 @@ void decide_bd(const FusedArgs &a, const double *A, const double *c, hipStream_t
     hipLaunchKernelGGL((k_gdecide<BD, First, KM>), dim3((unsigned)a.decide_wgs), dim3(BD), 0, s, a.T, a.ld, a.m, a.n,
                        A, c, a.K, a.KF, a.sparts, a.cols_done, a.st, a.gs, a.Fk, a.Rk, a.cols, a.pos, a.basis,
                        a.log_r, a.log_q, a.rparts, a.gsync, a.decide_spin, a.gate_spin, a.PV, a.pub, a.pub_words,
-                       a.pub_seq_at, a.pub_seq);
+                       a.pub_seq_at, a.pub_seq, a.t_mark);
 }
 
 // the instance for the group size (its KF pivot slots kept in registers)

@@ -46,6 +46,10 @@ struct FusedArgs {
     uint32_t pub_seq;
     int32_t pub_words;
     uint32_t *pub_seq_at;
+    // non-NULL: the decision kernel stores the device's constant-rate clock
+    // there when it starts (the start of a solve, in host memory mapped into
+    // the device)
+    unsigned long long *t_mark;
 };
 
 // Update instances exist for groups of up to 2, 4, 8, 12, 16, 24, 32 and

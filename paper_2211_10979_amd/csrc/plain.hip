@@ -162,6 +162,8 @@ struct lp_ctx {
     // one asked for)
     unsigned char *pub = nullptr;
     uint32_t pub_seq = 0;
+    uint32_t *xticket = nullptr;  // the mapped extraction's count of finished workgroups (zero between launches)
+    double clock_khz = 0.0;       // rate of the device clock the kernels read (wall_clock64)
     double update_ms = 0.0;
     int64_t update_launches = 0;
     double update_ms_applied = 0.0;  // part of update_ms in launches that applied pivots
@@ -246,6 +248,10 @@ constexpr size_t kStateBlock = kCountersAt + 4 * sizeof(unsigned long long);
 // a slot of the mapped block the decision kernel publishes to: the state
 // block, then the sequence word
 constexpr size_t kPubStride = (kStateBlock + sizeof(uint64_t) + 127) / 128 * 128;
+// after the two slots: the device clock at the start of the solve and at the
+// end of its pivoting, then the sequence word of the extraction
+constexpr size_t kPubMarks = 2 * kPubStride;
+constexpr size_t kPubBytes = kPubMarks + 128;
 
 // status_readback 0 reads the state right after the decisions (2) from a
 // tableau of this size on: its update pass then outlasts the host's reaction
@@ -396,6 +402,7 @@ size_t carve_aux(lp_ctx *h, unsigned char *base) {
     take(&h->out, ((size_t)n + m + 1) * sizeof(double));
     take(&h->rparts, 64 * sizeof(RatioPart));
     take(&h->ticket, sizeof(uint32_t));
+    take(&h->xticket, sizeof(uint32_t));
     // the fused update reads the list and R of a whole slot group at once, so
     // both are padded past the last slot
     take(&h->cols, ((size_t)h->Lg + kMaxFuse) * sizeof(int32_t));
@@ -477,9 +484,14 @@ int alloc_ctx(lp_ctx **out, int32_t m, int32_t n, const lp_options *opt_in) {
     {
         hipError_t e = hipHostMalloc((void **)&h->host_st, 3 * sizeof(DevState), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_cols, 4 * sizeof(unsigned long long), hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc((void **)&h->host_out, ((size_t)n + m + 1) * sizeof(double), hipHostMallocDefault);
+        if (e == hipSuccess)  // (mapped: the extraction after a read-back-2 solve writes it directly)
+            e = hipHostMalloc((void **)&h->host_out, ((size_t)n + m + 1) * sizeof(double),
+                              hipHostMallocMapped | hipHostMallocCoherent);
         if (e != hipSuccess) return fail(set_error(LP_E_NOMEM, "hipHostMalloc failed"));
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || khz <= 0)
+            return fail(set_error(LP_E_DEVICE, "no device clock rate"));
+        h->clock_khz = (double)khz;
     }
     if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_stop) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_slot[0], hipEventDisableTiming) != hipSuccess ||
@@ -784,9 +796,9 @@ int harvest_timing(lp_ctx *h, int slot, int64_t advanced) {
 int enqueue_extract(lp_ctx *h) {
     const int64_t ny = (int64_t)h->n + h->m + 1;
     hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
-                       h->n, h->out);
+                       h->n, h->out, nullptr);
     hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
-                       h->n, (const int32_t *)h->basis, h->out);
+                       h->n, (const int32_t *)h->basis, h->out, nullptr, nullptr, 0u);
     LP_HIP_CHECK(hipGetLastError());
     LP_HIP_CHECK(hipMemcpyAsync(h->host_out, h->out, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     return LP_OK;
@@ -805,13 +817,12 @@ void set_stop(lp_ctx *h, int64_t stop_at) {
 // Waits until the decision kernel has published the state in `slot` with
 // sequence `seq`: polls the mapped word for up to 20 ms, then waits for the
 // stream (the kernel has then ended) and checks once more.
-int wait_pub(lp_ctx *h, int slot, uint32_t seq) {
-    const volatile uint32_t *w = reinterpret_cast<const volatile uint32_t *>(h->pub + slot * kPubStride + kStateBlock);
+int wait_word(lp_ctx *h, const volatile uint32_t *w, uint32_t seq) {
     const auto t0 = std::chrono::steady_clock::now();
     for (uint32_t k = 0; *w != seq; ++k) {
         if ((k & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
             LP_HIP_CHECK(hipStreamSynchronize(h->stream));
-            if (*w != seq) return set_error(LP_E_DEVICE, "the decision kernel's state did not arrive");
+            if (*w != seq) return set_error(LP_E_DEVICE, "a kernel's published result did not arrive");
             break;
         }
     }
@@ -819,18 +830,25 @@ int wait_pub(lp_ctx *h, int slot, uint32_t seq) {
     return LP_OK;
 }
 
+int wait_pub(lp_ctx *h, int slot, uint32_t seq) {
+    return wait_word(h, reinterpret_cast<const volatile uint32_t *>(h->pub + slot * kPubStride + kStateBlock), seq);
+}
+
 int run_until_early(lp_ctx *h, int64_t stop_at) {
     if (!h->pub) {  // (allocated on first use)
-        if (hipHostMalloc((void **)&h->pub, 2 * kPubStride, hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess) {
+        if (hipHostMalloc((void **)&h->pub, kPubBytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             (void)hipGetLastError();
             return set_error(LP_E_NOMEM, "hipHostMalloc failed");
         }
-        std::memset(h->pub, 0, 2 * kPubStride);
+        std::memset(h->pub, 0, kPubBytes);
     }
+    // the device time of the solve is taken from the device clock, read by
+    // the first decision kernel and by the extraction: events between the
+    // kernels would each delay the next dispatch
+    unsigned long long *marks = reinterpret_cast<unsigned long long *>(h->pub + kPubMarks);
+    uint32_t *xseq_at = reinterpret_cast<uint32_t *>(h->pub + kPubMarks + 2 * sizeof(unsigned long long));
     int64_t last = h->pivots_host;  // pivots before the group being harvested
     set_stop(h, stop_at);
-    LP_HIP_CHECK(hipEventRecord(h->ev_start, h->stream));
     int slot = 0;
     int64_t advanced = 0;  // pivots of the group in the other slot, harvested once its pass is done
     bool have_prev = false;
@@ -846,6 +864,7 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         a.pub_words = (int32_t)(kStateBlock / sizeof(uint64_t));
         a.pub_seq_at = reinterpret_cast<uint32_t *>(blk + kStateBlock);
         a.pub_seq = seq;
+        a.t_mark = have_prev ? nullptr : marks;
         const bool first = h->pending;
         h->first_slot[slot] = first;
         if (first) {
@@ -876,9 +895,18 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         if (s.status != LP_RUNNING || s.pivots >= stop_at) break;
         slot ^= 1;
     }
-    LP_HIP_CHECK(hipEventRecord(h->ev_stop, h->stream));
-    if (int rc = enqueue_extract(h)) return rc;
-    LP_HIP_CHECK(hipStreamSynchronize(h->stream));
+    // Finalization straight into the mapped host buffer, which the host
+    // reads once the extraction's last workgroup has stored the sequence word
+    {
+        const int64_t ny = (int64_t)h->n + h->m + 1;
+        const uint32_t xseq = ++h->pub_seq;
+        hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
+                           h->m, h->n, h->host_out, marks + 1);
+        hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
+                           h->m, h->n, (const int32_t *)h->basis, h->host_out, h->xticket, xseq_at, xseq);
+        LP_HIP_CHECK(hipGetLastError());
+        if (int rc = wait_word(h, xseq_at, xseq)) return rc;
+    }
     // the state and the work counters read after the last decisions are
     // final: only the decision kernels write them (not the update pass, the
     // pivot-row stores or the extraction)
@@ -890,9 +918,8 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
     if (int rc = harvest_timing(h, slot, advanced)) return rc;  // the last group
     h->pivots_host = s.pivots;
     h->status_host = s.status;
-    float ms = 0.f;
-    LP_HIP_CHECK(hipEventElapsedTime(&ms, h->ev_start, h->ev_stop));
-    h->last_ms = ms;
+    const volatile unsigned long long *vm = marks;
+    h->last_ms = (double)(vm[1] - vm[0]) / h->clock_khz;
     h->ran = true;
     return LP_OK;
 }
@@ -1550,9 +1577,9 @@ int lp_solve_noalloc(int32_t m, int32_t n, const double *dA, const double *db, c
     // Finalization: x, y and the objective straight into the caller's arrays
     const int64_t ny = (int64_t)n + m + 1;
     hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
-                       h.out);
+                       h.out, nullptr);
     hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
-                       (const int32_t *)h.basis, h.out);
+                       (const int32_t *)h.basis, h.out, nullptr, nullptr, 0u);
     LP_HIP_CHECK(hipGetLastError());
     double objective = 0.0;
     if (x) LP_HIP_CHECK(hipMemcpyAsync(x, h.out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, h.stream));

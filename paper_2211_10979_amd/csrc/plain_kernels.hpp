@@ -618,22 +618,43 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
 // slack column n+i-1 (0 when that column is basic: row 0 of every slack
 // column is stored, also by a deferred build) and the objective; then x_j =
 // the RHS entry of the row in which structural column j is basic.
+// With `out` in host memory mapped into the device the host learns the end
+// from the second launch instead of waiting for the stream: the first one
+// stores the device's constant-rate clock at t_mark (non-NULL: the end of
+// the solve's pivoting, which precedes it in the stream), and in the second
+// the last workgroup to finish (counted on `ticket`, zero between launches)
+// stores `seq` at seq_at after a system-scope fence (ticket NULL: no
+// signal).
 static __global__ __launch_bounds__(256) void k_extract_y(const double *__restrict__ T, int64_t ld, int32_t m,
-                                                          int32_t n, double *__restrict__ out) {
+                                                          int32_t n, double *__restrict__ out,
+                                                          unsigned long long *t_mark) {
+    if (t_mark && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(t_mark, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n)
         out[idx] = 0.0;
     else if (idx <= (int64_t)n + m)
         out[idx] = T[idx * ld];  // column idx: slack idx - n, or the RHS (the objective)
+    if (t_mark) __threadfence_system();
 }
 
 static __global__ __launch_bounds__(256) void k_extract_x(const double *__restrict__ T, int64_t ld, int32_t m,
                                                           int32_t n, const int32_t *__restrict__ basis,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out, uint32_t *ticket,
+                                                          uint32_t *seq_at, uint32_t seq) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
-    if (i > m) return;
-    const int32_t bv = basis[i - 1];
-    if (bv < n) out[bv] = T[((int64_t)n + m) * ld + i];
+    if (i <= m) {
+        const int32_t bv = basis[i - 1];
+        if (bv < n) out[bv] = T[((int64_t)n + m) * ld + i];
+    }
+    if (!ticket) return;
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(ticket, 1u) == gridDim.x - 1) {
+        *ticket = 0u;  // (the stream orders the next launch after this one)
+        __threadfence_system();
+        __hip_atomic_store(seq_at, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // Stores every basic column as the unit vector it is: the basic column of

@@ -11,6 +11,7 @@ import ctypes
 import os
 import subprocess
 import sys
+import time
 import tempfile
 
 import numpy as np
@@ -158,10 +159,15 @@ def test_dense_8000_full_solve():
     say("dense_8000x8000: gpu", o.pivots, "pivots")
     h = lpgpu.lp_create(lp.A, lp.b, lp.c)
     try:
+        assert lpgpu.lp_get_info(h).status_readback == 2  # the solution handed over in mapped memory
+        t0 = time.perf_counter()
         lpgpu.lp_solve(h)
+        wall_ms = 1e3 * (time.perf_counter() - t0)
         res, x, y = lpgpu.lp_get_solution(h)
         rows, cols = lpgpu.lp_get_pivots(h)
         assert res["status"] == lpgpu.LP_OPTIMAL
+        # the device time from the device clock: positive, within the call
+        assert 0.0 < res["solve_ms"] < wall_ms, (res["solve_ms"], wall_ms)
         assert rows.tolist() == orow.tolist() and cols.tolist() == ocol.tolist()
         assert abs(res["objective"] - oobj) <= 1e-9 * max(1.0, abs(oobj))
         assert np.array_equal(x, ox) and np.array_equal(y, oy)
