@@ -796,7 +796,7 @@ int harvest_timing(lp_ctx *h, int slot, int64_t advanced) {
 int enqueue_extract(lp_ctx *h) {
     const int64_t ny = (int64_t)h->n + h->m + 1;
     hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
-                       h->n, h->out, nullptr);
+                       h->n, h->out, (int64_t)0, nullptr);
     hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld, h->m,
                        h->n, (const int32_t *)h->basis, h->out, nullptr, nullptr, 0u);
     LP_HIP_CHECK(hipGetLastError());
@@ -896,12 +896,16 @@ int run_until_early(lp_ctx *h, int64_t stop_at) {
         slot ^= 1;
     }
     // Finalization straight into the mapped host buffer, which the host
-    // reads once the extraction's last workgroup has stored the sequence word
+    // reads once the extraction's last workgroup has stored the sequence
+    // word. x is zeroed here, by the host, while the last update pass runs
+    // (before the launches, so before any device write to it), and the
+    // device writes y, the objective and the basic entries of x.
     {
-        const int64_t ny = (int64_t)h->n + h->m + 1;
+        std::memset(h->host_out, 0, (size_t)h->n * sizeof(double));
+        const int64_t ny = (int64_t)h->m + 1;
         const uint32_t xseq = ++h->pub_seq;
         hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
-                           h->m, h->n, h->host_out, marks + 1);
+                           h->m, h->n, h->host_out, (int64_t)h->n, marks + 1);
         hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((h->m + 255) / 256)), dim3(256), 0, h->stream, h->T, h->ld,
                            h->m, h->n, (const int32_t *)h->basis, h->host_out, h->xticket, xseq_at, xseq);
         LP_HIP_CHECK(hipGetLastError());
@@ -1577,7 +1581,7 @@ int lp_solve_noalloc(int32_t m, int32_t n, const double *dA, const double *db, c
     // Finalization: x, y and the objective straight into the caller's arrays
     const int64_t ny = (int64_t)n + m + 1;
     hipLaunchKernelGGL(k_extract_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
-                       h.out, nullptr);
+                       h.out, (int64_t)0, nullptr);
     hipLaunchKernelGGL(k_extract_x, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, h.stream, h.T, h.ld, m, n,
                        (const int32_t *)h.basis, h.out, nullptr, nullptr, 0u);
     LP_HIP_CHECK(hipGetLastError());

@@ -616,8 +616,9 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
 // Finalization: x (n), y (m) and the objective into out[0 .. n+m], in two
 // launches of one thread per entry. First x = 0, y_i = the row-0 entry of
 // slack column n+i-1 (0 when that column is basic: row 0 of every slack
-// column is stored, also by a deferred build) and the objective; then x_j =
-// the RHS entry of the row in which structural column j is basic.
+// column is stored, also by a deferred build) and the objective, for the
+// entries from `from` on (n when the caller has zeroed x); then x_j = the
+// RHS entry of the row in which structural column j is basic.
 // With `out` in host memory mapped into the device the host learns the end
 // from the second launch instead of waiting for the stream: the first one
 // stores the device's constant-rate clock at t_mark (non-NULL: the end of
@@ -626,11 +627,11 @@ __global__ __launch_bounds__(B) void k_update_gs(double *__restrict__ T, int64_t
 // stores `seq` at seq_at after a system-scope fence (ticket NULL: no
 // signal).
 static __global__ __launch_bounds__(256) void k_extract_y(const double *__restrict__ T, int64_t ld, int32_t m,
-                                                          int32_t n, double *__restrict__ out,
+                                                          int32_t n, double *__restrict__ out, int64_t from,
                                                           unsigned long long *t_mark) {
     if (t_mark && blockIdx.x == 0 && threadIdx.x == 0)
         __hip_atomic_store(t_mark, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n)
         out[idx] = 0.0;
     else if (idx <= (int64_t)n + m)
