@@ -148,9 +148,9 @@ typedef struct {
                                2 = right after each group's decisions, while its update pass
                                runs (no group after the end; the host's reaction time must
                                stay below one update pass). 0 = auto: 2 with the one-launch
-                               decision kernel, one group per chunk and a tableau of at least
-                               256 MiB, else 1. 2 needs the one-launch decision kernel and
-                               chunk_pivots 0 or at most fuse_pivots. */
+                               decision kernel and one group per chunk, else 1. 2 needs the
+                               one-launch decision kernel and chunk_pivots 0 or at most
+                               fuse_pivots. */
 } lp_tuning;
 
 /* Options of a solve (the fields listed first are the method's own). */

@@ -98,7 +98,7 @@ def test_degenerate_battery_deferred(K):
     assert events[1] > 0 and (K == 2 or events[0] > 0), events
 
 
-@pytest.mark.parametrize("K,readback", [(7, 0), (16, 0), (29, 0), (7, 2), (29, 2)])
+@pytest.mark.parametrize("K,readback", [(7, 1), (16, 1), (29, 1), (7, 0), (29, 2)])
 def test_stepping_after_reload(K, readback):
     """A first lp_step of 0 pivots (the first pass only builds), then
     budgets that cut groups short; the tableau after every step. Read-back 2
@@ -106,7 +106,7 @@ def test_stepping_after_reload(K, readback):
     lp = lpgen.workload("dense_200x200")
     say(f"deferred build K={K} status_readback={readback}: dense_200x200 stepping")
     d = Deferred(lp.m, lp.n, fuse_pivots=K, status_readback=readback)
-    assert lpgpu.lp_get_info(d.h).status_readback == (2 if readback == 2 else 1)
+    assert lpgpu.lp_get_info(d.h).status_readback == (1 if readback == 1 else 2)  # 0: auto
     o = oracle.OracleLP(lp.A, lp.b, lp.c)
     try:
         d.reload(lp.A, lp.b, lp.c)
@@ -307,7 +307,12 @@ def test_status_readback_counters_and_choice():
     small = lpgen.workload("dense_200x200")
     h = lpgpu.lp_create(small.A, small.b, small.c)
     try:
-        assert lpgpu.lp_get_info(h).status_readback == 1  # auto: a small tableau
+        assert lpgpu.lp_get_info(h).status_readback == 2  # auto, with the one-launch decision kernel
+    finally:
+        lpgpu.lp_destroy(h)
+    h = lpgpu.lp_create(small.A, small.b, small.c, decide_kernel=1)
+    try:
+        assert lpgpu.lp_get_info(h).status_readback == 1  # auto, with two launches per pivot
     finally:
         lpgpu.lp_destroy(h)
     for bad in (dict(status_readback=3), dict(status_readback=2, fuse_pivots=1),
